@@ -1,0 +1,325 @@
+/*
+ * oracle.c -- CPU FP64 oracle for the delayed-update Cholesky / LU library.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain C, IEEE binary64, built with
+ * -O2 -ffp-contract=off and without fast-math, so every sum is evaluated in the
+ * order written.  Where OpenMP is used, only independent rows are spread over
+ * threads; each row's arithmetic is unchanged, so the results are bitwise the
+ * same for any thread count.
+ *
+ * Paper: C. Camarero, arXiv 1812.02056 (Sec. 2: Algorithms 1 and 2 and the
+ * discussion of their special cases s = 1 and s = n).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define IDX(i, j, ld) ((size_t)(i) + (size_t)(j) * (size_t)(ld))
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/*
+ * Cholesky, plain definition: the lower-triangular L with positive diagonal and
+ * A = L L^T (Introduction).  Computed as the Cholesky-Crout algorithm, which is
+ * Algorithm 1 with s = n (Sec. 2): column j is formed from the original A and
+ * all previously computed columns,
+ *     L[j,j] = sqrt(A[j,j] - sum_{k<j} L[j,k]^2),
+ *     L[i,j] = (A[i,j] - sum_{k<j} L[i,k] L[j,k]) / L[j,j]      (i > j).
+ * The factor is kept in a row-major working array so each sum runs over
+ * contiguous memory; that is a storage choice only, the operations and their
+ * order are exactly the ones above.
+ */
+int oracle_chol(int64_t n, const double *A, int64_t lda, double *L, int64_t ldl)
+{
+    if (n <= 0) return 0;
+    double *W = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
+    if (!W) return -1;
+    int info = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double *wj = W + (size_t)j * (size_t)n;
+        double d = A[IDX(j, j, lda)];
+        for (int64_t k = 0; k < j; ++k) d -= wj[k] * wj[k];
+        if (!(d > 0.0)) {           /* non-positive or NaN pivot */
+            info = (int)(j + 1);
+            break;
+        }
+        const double ljj = sqrt(d);
+        W[(size_t)j * (size_t)n + (size_t)j] = ljj;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = j + 1; i < n; ++i) {
+            const double *wi = W + (size_t)i * (size_t)n;
+            double t = A[IDX(i, j, lda)];
+            for (int64_t k = 0; k < j; ++k) t -= wi[k] * wj[k];
+            W[(size_t)i * (size_t)n + (size_t)j] = t / ljj;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i)
+            L[IDX(i, j, ldl)] = (i >= j) ? W[(size_t)i * (size_t)n + (size_t)j] : 0.0;
+    free(W);
+    return info;
+}
+
+/*
+ * LU without pivoting, Doolittle form (unit lower L, upper U), the unique
+ * factorisation when all leading principal minors are nonzero (Sec. 2,
+ * Algorithm 2's data requirement).  For k = 0..n-1:
+ *     U[k,j] = A[k,j] - sum_{p<k} L[k,p] U[p,j]            (j >= k)
+ *     L[i,k] = (A[i,k] - sum_{p<k} L[i,p] U[p,k]) / U[k,k]  (i > k)
+ * L is held row-major and U column-major so each sum is contiguous.
+ */
+int oracle_lu(int64_t n, const double *A, int64_t lda, double *LU, int64_t ldlu)
+{
+    if (n <= 0) return 0;
+    double *Lr = (double *)calloc((size_t)n * (size_t)n, sizeof(double)); /* Lr[i*n+p] = L[i,p] */
+    double *Uc = (double *)calloc((size_t)n * (size_t)n, sizeof(double)); /* Uc[j*n+p] = U[p,j] */
+    if (!Lr || !Uc) { free(Lr); free(Uc); return -1; }
+    int info = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const double *lk = Lr + (size_t)k * (size_t)n;
+#pragma omp parallel for schedule(static)
+        for (int64_t j = k; j < n; ++j) {
+            const double *uj = Uc + (size_t)j * (size_t)n;
+            double t = A[IDX(k, j, lda)];
+            for (int64_t p = 0; p < k; ++p) t -= lk[p] * uj[p];
+            Uc[(size_t)j * (size_t)n + (size_t)k] = t;
+        }
+        const double ukk = Uc[(size_t)k * (size_t)n + (size_t)k];
+        if (ukk == 0.0 || !isfinite(ukk)) {
+            info = (int)(k + 1);
+            break;
+        }
+        const double *uk = Uc + (size_t)k * (size_t)n;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = k + 1; i < n; ++i) {
+            const double *li = Lr + (size_t)i * (size_t)n;
+            double t = A[IDX(i, k, lda)];
+            for (int64_t p = 0; p < k; ++p) t -= li[p] * uk[p];
+            Lr[(size_t)i * (size_t)n + (size_t)k] = t / ukk;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i)
+            LU[IDX(i, j, ldlu)] = (i > j) ? Lr[(size_t)i * (size_t)n + (size_t)j]
+                                          : Uc[(size_t)j * (size_t)n + (size_t)i];
+    free(Lr);
+    free(Uc);
+    return info;
+}
+
+/* Forward substitution L y = b, then backward L^T x = y, per right-hand side. */
+void oracle_chol_solve(int64_t n, int64_t nrhs, const double *L, int64_t ldl,
+                       const double *B, int64_t ldb, double *X, int64_t ldx)
+{
+    double *y = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t r = 0; r < nrhs; ++r) {
+        const double *b = B + (size_t)r * (size_t)ldb;
+        double *x = X + (size_t)r * (size_t)ldx;
+        for (int64_t i = 0; i < n; ++i) {
+            double t = b[i];
+            for (int64_t k = 0; k < i; ++k) t -= L[IDX(i, k, ldl)] * y[k];
+            y[i] = t / L[IDX(i, i, ldl)];
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int64_t k = i + 1; k < n; ++k) t -= L[IDX(k, i, ldl)] * x[k];
+            x[i] = t / L[IDX(i, i, ldl)];
+        }
+    }
+    free(y);
+}
+
+/* Forward substitution with the unit lower L, then backward with U. */
+void oracle_lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu,
+                     const double *B, int64_t ldb, double *X, int64_t ldx)
+{
+    double *y = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t r = 0; r < nrhs; ++r) {
+        const double *b = B + (size_t)r * (size_t)ldb;
+        double *x = X + (size_t)r * (size_t)ldx;
+        for (int64_t i = 0; i < n; ++i) {
+            double t = b[i];
+            for (int64_t k = 0; k < i; ++k) t -= LU[IDX(i, k, ldlu)] * y[k];
+            y[i] = t;
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int64_t k = i + 1; k < n; ++k) t -= LU[IDX(i, k, ldlu)] * x[k];
+            x[i] = t / LU[IDX(i, i, ldlu)];
+        }
+    }
+    free(y);
+}
+
+/*
+ * Algorithm 1 of Sec. 2 with step size s, 0-based.  z is the first column not
+ * yet folded into the trailing matrix.  When s columns are pending (c == z+s)
+ * the block R = L[c.., z..c-1] gives S = R R^T, which is subtracted from the
+ * whole trailing square A[c.., c..] of the working matrix; then column c is
+ * formed from the working matrix and the pending columns z..c-1 only.
+ */
+int64_t oracle_chol_alg1(int64_t n, int64_t s, const double *A, int64_t lda,
+                         double *L, int64_t ldl)
+{
+    if (n <= 0) return 0;
+    const size_t nn = (size_t)n * (size_t)n;
+    double *Aw = (double *)malloc(nn * sizeof(double));
+    double *Lw = (double *)calloc(nn, sizeof(double)); /* column-major n x n */
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) Aw[IDX(i, j, n)] = A[IDX(i, j, lda)];
+    int64_t z = 0, updates = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        if (c == z + s) {
+            const int64_t m = n - c;
+            double *S = (double *)malloc((size_t)m * (size_t)m * sizeof(double));
+            for (int64_t j = 0; j < m; ++j)
+                for (int64_t i = 0; i < m; ++i) {
+                    double t = 0.0;
+                    for (int64_t k = z; k < c; ++k) t += Lw[IDX(c + i, k, n)] * Lw[IDX(c + j, k, n)];
+                    S[IDX(i, j, m)] = t;
+                }
+            for (int64_t j = 0; j < m; ++j)
+                for (int64_t i = 0; i < m; ++i) Aw[IDX(c + i, c + j, n)] -= S[IDX(i, j, m)];
+            free(S);
+            z = c;
+            ++updates;
+        }
+        double d = Aw[IDX(c, c, n)];
+        for (int64_t k = z; k < c; ++k) d -= Lw[IDX(c, k, n)] * Lw[IDX(c, k, n)];
+        const double lcc = sqrt(d);
+        Lw[IDX(c, c, n)] = lcc;
+        for (int64_t i = c + 1; i < n; ++i) {
+            double t = Aw[IDX(i, c, n)];
+            for (int64_t k = z; k < c; ++k) t -= Lw[IDX(i, k, n)] * Lw[IDX(c, k, n)];
+            Lw[IDX(i, c, n)] = t / lcc;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) L[IDX(i, j, ldl)] = Lw[IDX(i, j, n)];
+    free(Aw);
+    free(Lw);
+    return updates;
+}
+
+/*
+ * Algorithm 2 of Sec. 2 with step size s, 0-based: Crout factors (L lower with
+ * its diagonal, U unit upper).  The deferred product is S = R_L R_U with
+ * R_L = L[c.., z..c-1] and R_U = U[z..c-1, c..].
+ */
+int64_t oracle_lu_alg2(int64_t n, int64_t s, const double *A, int64_t lda,
+                       double *L, int64_t ldl, double *U, int64_t ldu)
+{
+    if (n <= 0) return 0;
+    const size_t nn = (size_t)n * (size_t)n;
+    double *Aw = (double *)malloc(nn * sizeof(double));
+    double *Lw = (double *)calloc(nn, sizeof(double));
+    double *Uw = (double *)calloc(nn, sizeof(double));
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) Aw[IDX(i, j, n)] = A[IDX(i, j, lda)];
+    int64_t z = 0, updates = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        if (c == z + s) {
+            const int64_t m = n - c;
+            double *S = (double *)malloc((size_t)m * (size_t)m * sizeof(double));
+            for (int64_t j = 0; j < m; ++j)
+                for (int64_t i = 0; i < m; ++i) {
+                    double t = 0.0;
+                    for (int64_t k = z; k < c; ++k) t += Lw[IDX(c + i, k, n)] * Uw[IDX(k, c + j, n)];
+                    S[IDX(i, j, m)] = t;
+                }
+            for (int64_t j = 0; j < m; ++j)
+                for (int64_t i = 0; i < m; ++i) Aw[IDX(c + i, c + j, n)] -= S[IDX(i, j, m)];
+            free(S);
+            z = c;
+            ++updates;
+        }
+        for (int64_t i = c; i < n; ++i) {
+            double t = Aw[IDX(i, c, n)];
+            for (int64_t k = z; k < c; ++k) t -= Lw[IDX(i, k, n)] * Uw[IDX(k, c, n)];
+            Lw[IDX(i, c, n)] = t;
+        }
+        const double lcc = Lw[IDX(c, c, n)];
+        for (int64_t i = c; i < n; ++i) {
+            double t = Aw[IDX(c, i, n)];
+            for (int64_t k = z; k < c; ++k) t -= Lw[IDX(c, k, n)] * Uw[IDX(k, i, n)];
+            Uw[IDX(c, i, n)] = t / lcc;
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+            L[IDX(i, j, ldl)] = Lw[IDX(i, j, n)];
+            U[IDX(i, j, ldu)] = Uw[IDX(i, j, n)];
+        }
+    free(Aw);
+    free(Lw);
+    free(Uw);
+    return updates;
+}
+
+/* The deferred update of Algorithm 1 (Sec. 2), lower triangle only: the entries
+ * i < j of the trailing square are never read again by the algorithm. */
+void oracle_syrk_update(int64_t m, int64_t w, double *C, int64_t ldc,
+                        const double *P, int64_t ldp)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < m; ++j)
+        for (int64_t i = j; i < m; ++i) {
+            double t = 0.0;
+            for (int64_t k = 0; k < w; ++k) t += P[IDX(i, k, ldp)] * P[IDX(j, k, ldp)];
+            C[IDX(i, j, ldc)] -= t;
+        }
+}
+
+/* The deferred update of Algorithm 2 (Sec. 2) over the full trailing square. */
+void oracle_gemm_update(int64_t m, int64_t w, double *C, int64_t ldc,
+                        const double *X, int64_t ldx, const double *Y, int64_t ldy)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < m; ++j)
+        for (int64_t i = 0; i < m; ++i) {
+            double t = 0.0;
+            for (int64_t k = 0; k < w; ++k) t += X[IDX(i, k, ldx)] * Y[IDX(k, j, ldy)];
+            C[IDX(i, j, ldc)] -= t;
+        }
+}
+
+double oracle_round_f32(double x) { return (double)(float)x; }
+
+/*
+ * bfloat16 keeps binary32's 8-bit exponent and 8 significant bits.  Round the
+ * binary32 value f to the nearer of its two bfloat16 neighbours, taking the one
+ * with an even last significand bit on a tie; magnitudes at or beyond the
+ * midpoint above the largest finite bfloat16 become infinity.
+ */
+double oracle_round_bf16(double x)
+{
+    const double f = (double)(float)x;
+    if (isnan(f) || isinf(f) || f == 0.0) return f;
+    int e;
+    (void)frexp(fabs(f), &e);                 /* 2^(e-1) <= |f| < 2^e */
+    int ulp_exp = e - 8;                      /* spacing of 8-bit significands */
+    if (ulp_exp < -133) ulp_exp = -133;       /* bfloat16 subnormal spacing */
+    const double q = ldexp(fabs(f), -ulp_exp);/* exact: scaling by a power of two */
+    const double lo = floor(q);
+    const double frac = q - lo;
+    double r;
+    if (frac > 0.5) r = lo + 1.0;
+    else if (frac < 0.5) r = lo;
+    else r = (fmod(lo, 2.0) == 0.0) ? lo : lo + 1.0;
+    double mag = ldexp(r, ulp_exp);
+    const double bf16_max = ldexp(255.0, 120);  /* (2 - 2^-7) * 2^127 */
+    if (mag > bf16_max) mag = INFINITY;
+    return copysign(mag, f);
+}

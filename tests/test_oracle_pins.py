@@ -1,0 +1,416 @@
+"""Pins for the CPU oracle: each test ties it to something other than itself.
+
+The oracle is the plain definition of the factorisations (Cholesky A = L L^T,
+LU with unit-lower L, Introduction and Sec. 2 of arXiv 1812.02056).  These
+tests hold it to: hand-worked examples, closed forms, exact integer families
+(any evaluation order must return the generating factor bit for bit), brute
+force over every small integer factor, LAPACK through numpy / scipy,
+uniqueness against a known factor, the paper's own special cases s = 1 and
+s = n of Algorithm 1, and invariants (backward error, failure index).
+"""
+import ctypes
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_1812_02056_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------- golden
+
+def test_golden_cholesky_hand_examples(golden):
+    for key in ("chol_2x2", "chol_3x3", "chol_4x4_halves"):
+        A = np.array(golden[key]["A"], dtype=np.float64)
+        L, info = oracle.chol(A)
+        assert info == 0, key
+        assert np.array_equal(L, np.array(golden[key]["L"], dtype=np.float64)), key
+
+
+def test_golden_cholesky_not_spd(golden):
+    A = np.array(golden["chol_not_spd"]["A"], dtype=np.float64)
+    _, info = oracle.chol(A)
+    assert info == golden["chol_not_spd"]["info"]
+
+
+def test_golden_lu_hand_example(golden):
+    d = golden["lu_3x3"]
+    A = np.array(d["A"], dtype=np.float64)
+    LU, info = oracle.lu(A)
+    assert info == 0
+    L = np.tril(LU, -1) + np.eye(3)
+    U = np.triu(LU)
+    assert np.array_equal(L, np.array(d["doolittle_L"], dtype=np.float64))
+    assert np.array_equal(U, np.array(d["doolittle_U"], dtype=np.float64))
+    # the paper's own convention (Algorithm 2): L with diagonal, U unit upper
+    Lc, Uc, _ = oracle.lu_alg2(A, 1)
+    assert np.array_equal(Lc, np.array(d["crout_L"], dtype=np.float64))
+    assert np.allclose(Uc, np.array(d["crout_U"], dtype=np.float64), rtol=0, atol=2e-16)
+
+
+def test_golden_lu_zero_minor(golden):
+    d = golden["lu_zero_minor"]
+    _, info = oracle.lu(np.array(d["A"], dtype=np.float64))
+    assert info == d["info"]
+
+
+# --------------------------------------------------------------------------- closed forms
+
+def test_chol_2x2_closed_form():
+    """L = [[sqrt(a), 0], [b/sqrt(a), sqrt(c - b^2/a)]] for random SPD 2x2."""
+    rng = np.random.default_rng(7)
+    for _ in range(500):
+        a = rng.uniform(0.5, 4.0)
+        c = rng.uniform(0.5, 4.0)
+        b = rng.uniform(-1.0, 1.0) * np.sqrt(a * c) * 0.9
+        L, info = oracle.chol(np.array([[a, b], [b, c]]))
+        assert info == 0
+        ref = np.array([[np.sqrt(a), 0.0], [b / np.sqrt(a), np.sqrt(c - b * b / a)]])
+        assert np.allclose(L, ref, rtol=4e-15, atol=0)
+
+
+def test_lu_2x2_closed_form():
+    """Doolittle 2x2: U = [[a, b], [0, d - c b / a]], L21 = c / a."""
+    rng = np.random.default_rng(8)
+    for _ in range(500):
+        a, b, c, d = rng.uniform(0.5, 2.0), rng.normal(), rng.normal(), rng.uniform(3.0, 5.0)
+        LU, info = oracle.lu(np.array([[a, b], [c, d]]))
+        assert info == 0
+        ref = np.array([[a, b], [c / a, d - (c / a) * b]])
+        assert np.allclose(LU, ref, rtol=4e-15, atol=1e-15)
+
+
+# --------------------------------------------------------------------------- exact families
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 33, 128, 300])
+def test_chol_integer_family_exact(n):
+    L0, A = wl.chol_int_family(n, seed=n)
+    L, info = oracle.chol(A)
+    assert info == 0
+    assert np.array_equal(L, L0)
+
+
+def _all_int_factors(order):
+    offs = [-1.0, 0.0, 1.0]
+    diags = [1.0, 2.0]
+    npos = order * (order - 1) // 2
+    idx = np.tril_indices(order, -1)
+    for d in itertools.product(diags, repeat=order):
+        for o in itertools.product(offs, repeat=npos):
+            L0 = np.zeros((order, order))
+            L0[idx] = o
+            L0[np.diag_indices(order)] = d
+            yield L0
+
+
+@pytest.mark.parametrize("order,count", [(2, 12), (3, 216), (4, 11664)])
+def test_chol_brute_force_small_integer_factors(order, count):
+    seen = 0
+    for L0 in _all_int_factors(order):
+        L, info = oracle.chol(L0 @ L0.T)
+        assert info == 0 and np.array_equal(L, L0), L0
+        seen += 1
+    assert seen == count
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 257])
+def test_lu_integer_family_exact(n):
+    L0, U0, A = wl.lu_int_family(n, seed=100 + n)
+    LU, info = oracle.lu(A)
+    assert info == 0
+    assert np.array_equal(np.tril(LU, -1) + np.eye(n), L0)
+    assert np.array_equal(np.triu(LU), U0)
+
+
+def test_lu_brute_force_order3():
+    vals = [-1.0, 0.0, 1.0]
+    for l in itertools.product(vals, repeat=3):
+        for u in itertools.product(vals, repeat=3):
+            for d in itertools.product([1.0, 2.0], repeat=3):
+                L0 = np.eye(3)
+                L0[1, 0], L0[2, 0], L0[2, 1] = l
+                U0 = np.diag(d)
+                U0[0, 1], U0[0, 2], U0[1, 2] = u
+                LU, info = oracle.lu(L0 @ U0)
+                assert info == 0
+                assert np.array_equal(np.tril(LU, -1) + np.eye(3), L0)
+                assert np.array_equal(np.triu(LU), U0)
+
+
+# --------------------------------------------------------------------------- library routines
+
+def test_chol_matches_lapack():
+    A = wl.spd_scaled(300, seed=3)
+    L, info = oracle.chol(A)
+    assert info == 0
+    Lref = np.linalg.cholesky(A)
+    assert oracle.rel_lower(L, Lref) < 1e-13
+
+
+def test_chol_config0_backward_error_and_lapack():
+    """A = G G^T + 512 I, n = 512: the small Cholesky configuration."""
+    A = wl.spd_shifted(512, seed=0)
+    L, info = oracle.chol(A)
+    assert info == 0
+    assert oracle.bwd_chol(A, L) <= 1e-13
+    assert oracle.rel_lower(L, np.linalg.cholesky(A)) <= 1e-13
+
+
+def test_chol_uniqueness_known_factor():
+    """A = L0 L0^T with a well-conditioned L0: the unique factor is L0 (to kappa*u)."""
+    L0, A = wl.chol_float_family(512, seed=1, scaled=True)
+    L, info = oracle.chol(A)
+    assert info == 0
+    assert oracle.rel_lower(L, L0) <= 1e-13
+
+
+def test_chol_literal_l0_family_is_not_numerically_spd():
+    """The N(0,1) off-diagonal L0 family is so ill-conditioned (kappa(L0) ~ 1e18 at
+    n = 512) that fl(L0 L0^T) is not positive definite in binary64: LAPACK and the
+    oracle both stop.  It is a documented negative case, not a parity case."""
+    _, A = wl.chol_float_family(512, seed=0, scaled=False)
+    _, info = oracle.chol(A)
+    assert info > 0
+    with pytest.raises(np.linalg.LinAlgError):
+        np.linalg.cholesky(A)
+
+
+def test_lu_matches_transposed_gepp():
+    """A strictly row-diagonally-dominant A has a column-dominant A^T, on which partial
+    pivoting never swaps; A^T = L' U' then gives the Crout factors of A
+    (L_c = U'^T, U_c = L'^T) and Doolittle is L_c D^-1, D U_c with D = diag(L_c)."""
+    A = wl.diag_dominant(256, seed=4)
+    P, Lp, Up = scipy.linalg.lu(A.T)
+    assert np.array_equal(P, np.eye(256))
+    Lc, Uc = Up.T, Lp.T
+    D = np.diag(Lc)
+    L_d = Lc / D[None, :]
+    U_d = Uc * D[:, None]
+    LU, info = oracle.lu(A)
+    assert info == 0
+    assert np.max(np.abs(np.tril(LU, -1) - np.tril(L_d, -1))) <= 1e-13
+    assert np.max(np.abs(np.triu(LU) - U_d)) / np.max(np.abs(U_d)) <= 1e-13
+    assert oracle.bwd_lu(A, LU) <= 1e-13
+
+
+# --------------------------------------------------------------------------- failure index
+
+@pytest.mark.parametrize("k", [0, 1, 17, 63])
+def test_chol_non_spd_info(k):
+    """A[k,k] -= L0[k,k]^2 + 1 makes the k-th pivot exactly -1: info = k+1."""
+    L0, A = wl.chol_int_family(64, seed=5)
+    A[k, k] -= L0[k, k] ** 2 + 1.0
+    L, info = oracle.chol(A)
+    assert info == k + 1
+    assert np.array_equal(L[:, :k], L0[:, :k])
+
+
+def test_chol_nan_info():
+    _, A = wl.chol_int_family(16, seed=6)
+    A[9, 9] = np.nan
+    _, info = oracle.chol(A)
+    assert info == 10
+
+
+def test_lu_zero_pivot_info():
+    L0, U0, _ = wl.lu_int_family(32, seed=7)
+    U0[11, 11] = 0.0
+    _, info = oracle.lu(L0 @ U0)
+    assert info == 12
+
+
+# --------------------------------------------------------------------------- Algorithm 1 / 2
+
+@pytest.mark.parametrize("s", [1, 2, 3, 5, 12, 13, 14, 100])
+def test_alg1_integer_family_every_step_size(s):
+    L0, A = wl.chol_int_family(13, seed=9)
+    L, nup = oracle.chol_alg1(A, s)
+    assert np.array_equal(L, L0)
+    assert nup == (13 - 1) // s
+
+
+@pytest.mark.parametrize("n,s", [(512, 27), (512, 28), (40, 1), (40, 7), (40, 40)])
+def test_alg1_matches_plain_definition(n, s):
+    A = wl.spd_shifted(n, seed=2)
+    L, nup = oracle.chol_alg1(A, s)
+    Lref, info = oracle.chol(A)
+    assert info == 0
+    assert nup == (n - 1) // s
+    assert oracle.rel_lower(L, Lref) <= 2e-15
+
+
+def test_alg1_s_equals_n_is_cholesky_crout_bitwise():
+    """With s = n no update happens and Algorithm 1 is Cholesky-Crout, the oracle's own loop."""
+    A = wl.spd_scaled(64, seed=11)
+    L, nup = oracle.chol_alg1(A, 64)
+    Lref, _ = oracle.chol(A)
+    assert nup == 0
+    assert np.array_equal(L, Lref)
+
+
+def test_alg1_s_equals_one_is_recursive_rank1_bitwise():
+    """With s = 1 Algorithm 1 is the recursive (right-looking rank-1) algorithm."""
+    A = wl.spd_scaled(48, seed=12)
+    n = A.shape[0]
+    W = np.array(A, copy=True)
+    Lr = np.zeros_like(W)
+    for j in range(n):
+        Lr[j, j] = np.sqrt(W[j, j])
+        Lr[j + 1:, j] = W[j + 1:, j] / Lr[j, j]
+        v = Lr[j + 1:, j]
+        W[j + 1:, j + 1:] -= np.multiply.outer(v, v)
+    L, nup = oracle.chol_alg1(A, 1)
+    assert nup == n - 1
+    assert np.array_equal(L, Lr)
+
+
+@pytest.mark.parametrize("s", [1, 3, 4, 13, 20])
+def test_alg2_crout_matches_doolittle_exactly_on_integers(s):
+    L0, U0, A = wl.lu_int_family(13, seed=13)
+    Lc, Uc, nup = oracle.lu_alg2(A, s)
+    D = np.diag(U0)
+    assert nup == (13 - 1) // s
+    assert np.array_equal(Lc, L0 * D[None, :])
+    assert np.array_equal(Uc, U0 / D[:, None])
+
+
+@pytest.mark.parametrize("s", [1, 5, 17, 64])
+def test_alg2_matches_doolittle_on_dominant_matrix(s):
+    A = wl.diag_dominant(64, seed=14)
+    Lc, Uc, _ = oracle.lu_alg2(A, s)
+    LU, info = oracle.lu(A)
+    assert info == 0
+    D = np.diag(Lc)
+    assert np.max(np.abs(np.tril(LU, -1) - np.tril(Lc / D[None, :], -1))) <= 1e-14
+    assert np.max(np.abs(np.triu(LU) - Uc * D[:, None])) / np.max(np.abs(np.triu(LU))) <= 1e-14
+
+
+# --------------------------------------------------------------------------- solves
+
+def test_chol_solve_integer_exact():
+    L0, A = wl.chol_int_family(200, seed=15)
+    x0 = np.random.default_rng(15).integers(-1, 2, size=(200, 3)).astype(np.float64)
+    B = A @ x0
+    X = oracle.chol_solve(L0, B)
+    assert np.array_equal(X, x0)
+
+
+def test_lu_solve_integer_exact():
+    L0, U0, A = wl.lu_int_family(150, seed=16)
+    x0 = np.random.default_rng(16).integers(-1, 2, size=(150, 2)).astype(np.float64)
+    LU = np.tril(L0, -1) + U0
+    X = oracle.lu_solve(LU, A @ x0)
+    assert np.array_equal(X, x0)
+
+
+def test_chol_solve_matches_lapack_and_backward_stable():
+    A = wl.spd_scaled(256, seed=17, lam=1e-3)
+    B = wl.rhs(256, 4, seed=18)
+    L, info = oracle.chol(A)
+    assert info == 0
+    X = oracle.chol_solve(L, B)
+    assert oracle.bwd_x(A, X, B) <= 1e-15
+    Xref = np.linalg.solve(A, B)
+    assert oracle.fwd_x(X, Xref) <= 1e-10     # kappa ~ 4e3
+
+
+# --------------------------------------------------------------------------- update definitions
+
+def test_syrk_update_integer_exact_and_upper_untouched():
+    rng = np.random.default_rng(19)
+    m, w = 70, 23
+    C = rng.integers(-50, 50, size=(m, m)).astype(np.float64)
+    P = rng.integers(-3, 4, size=(m, w)).astype(np.float64)
+    out = oracle.syrk_update(C, P)
+    ref = C - P @ P.T
+    assert np.array_equal(np.tril(out), np.tril(ref))
+    assert np.array_equal(np.triu(out, 1), np.triu(C, 1))
+
+
+def test_gemm_update_integer_exact():
+    rng = np.random.default_rng(20)
+    m, w = 61, 17
+    C = rng.integers(-50, 50, size=(m, m)).astype(np.float64)
+    X = rng.integers(-3, 4, size=(m, w)).astype(np.float64)
+    Y = rng.integers(-3, 4, size=(w, m)).astype(np.float64)
+    assert np.array_equal(oracle.gemm_update(C, X, Y), C - X @ Y)
+
+
+# --------------------------------------------------------------------------- rounding
+
+def test_round_f32_matches_numpy():
+    x = np.random.default_rng(21).standard_normal(2000) * 10.0 ** np.random.default_rng(22).integers(-30, 30, 2000)
+    assert np.array_equal(oracle.round_f32(x), x.astype(np.float32).astype(np.float64))
+
+
+def test_round_bf16_hand_cases():
+    one = 1.0
+    cases = {
+        one: one,
+        one + 2.0 ** -8: one,                       # tie, even neighbour is 1
+        one + 3 * 2.0 ** -8: one + 2.0 ** -6,       # tie, even neighbour is 1 + 2^-6
+        one + 2.0 ** -8 + 2.0 ** -20: one + 2.0 ** -7,
+        -3.0: -3.0,
+        2.0 ** -133: 2.0 ** -133,                   # smallest bfloat16 subnormal
+        255.0 * 2.0 ** 120: 255.0 * 2.0 ** 120,     # largest finite bfloat16
+        float(np.float32(3.4e38)): np.inf,          # past the midpoint above the largest finite bfloat16
+        float(np.float32(3.0e38)): 226.0 * 2.0 ** 120,    # nearest bfloat16, below the largest
+    }
+    for x, want in cases.items():
+        assert oracle.round_bf16(x) == want, x
+
+
+def test_round_bf16_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(23)
+    x = np.concatenate([rng.standard_normal(5000) * 10.0 ** rng.integers(-20, 20, 5000),
+                        (np.arange(-300, 300) + 0.5) * 2.0 ** -7])   # exact ties
+    x32 = x.astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(oracle.round_bf16(x32.astype(np.float64)), ref)
+
+
+# --------------------------------------------------------------------------- determinism
+
+def test_oracle_bitwise_independent_of_thread_count():
+    A = wl.spd_scaled(300, seed=24)
+    L8, _ = oracle.chol(A)
+    LU8, _ = oracle.lu(wl.diag_dominant(200, seed=25))
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        pytest.skip("libgomp not loadable")
+    nthr = oracle.num_threads()
+    gomp.omp_set_num_threads(1)
+    try:
+        L1, _ = oracle.chol(A)
+        LU1, _ = oracle.lu(wl.diag_dominant(200, seed=25))
+    finally:
+        gomp.omp_set_num_threads(nthr)
+    assert np.array_equal(L1, L8)
+    assert np.array_equal(LU1, LU8)
+
+
+# --------------------------------------------------------------------------- generators
+
+def test_generators_deterministic_and_structured():
+    A1, A2 = wl.spd_scaled(64, seed=3), wl.spd_scaled(64, seed=3)
+    assert np.array_equal(A1, A2) and np.array_equal(A1, A1.T)
+    D = wl.diag_dominant(64, seed=3)
+    off = np.sum(np.abs(D), axis=1) - np.abs(np.diag(D))
+    assert np.all(np.diag(D) > off)
+    L0, A = wl.chol_int_family(50, seed=3)
+    assert np.array_equal(A, L0 @ L0.T)
+    assert wl.default_s(512) == 27 and wl.default_s(16384) == 169
