@@ -1,0 +1,175 @@
+/*
+ * fastfact.h -- C ABI of the MI355X (gfx950) delayed-update Cholesky / LU library.
+ *
+ * The method is C. Camarero, "Simple, Fast and Practicable Algorithms for
+ * Cholesky, LU and QR Decomposition Using Fast Rectangular Matrix
+ * Multiplication" (arXiv 1812.02056), Sec. 2, Algorithms 1 and 2: columns are
+ * produced Crout-style and, every s columns, the pending block R of the factor
+ * is folded into the rest of the matrix with one rectangular product
+ * S = R R^T (LU: S = R_L R_U) that is subtracted from the trailing square.
+ * Over one block of w <= s columns that is, in the usual vocabulary, a w x w
+ * diagonal factorisation, a triangular solve of the m x w panel below it and
+ * the rank-w trailing update A22 -= L21 L21^T (LU: A22 -= L21 U12).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are column-major with a leading dimension ld >= max(1, rows);
+ *    element (i, j) of A is A[i + j*lda].
+ *  - Matrix pointers are DEVICE pointers (HIP device memory on the current
+ *    device) unless stated otherwise.  The library never allocates, frees or
+ *    retains caller memory; the caller owns every buffer.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *    stream).  Work is enqueued on it; nothing is synchronised unless stated.
+ *  - Return value: 0 = enqueued; -k = argument k (1-based) is invalid;
+ *    FF_ERR_HIP (-100) = a HIP runtime call failed; FF_ERR_WORKSPACE (-101) =
+ *    workspace too small; FF_ERR_UNSUPPORTED (-102) = valid but unsupported
+ *    combination (e.g. a dtype an entry point does not implement).
+ *    ff_status_string() names each code.
+ *  - Numerical failure is reported asynchronously through *d_info, a device
+ *    int32 that the call first sets to 0: k > 0 means the 1-based column k had
+ *    a pivot that was not > 0 (Cholesky, NaN included) or was zero or not
+ *    finite (LU).  The factorisation stops at the block containing column k;
+ *    entries from that block on are unspecified.
+ *  - Calls are reentrant: different streams may run different calls at once
+ *    provided their buffers do not overlap.
+ */
+#ifndef FASTFACT_H
+#define FASTFACT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic of the trailing update (and storage type of the factored matrix). */
+typedef enum {
+    FF_F64 = 0,  /* storage double, every step in binary64 */
+    FF_F32 = 1,  /* storage float; update and panel solve in binary32 MFMA;
+                    diagonal blocks factored in binary64 and rounded back */
+    FF_BF16 = 2  /* storage float; update operands rounded to bfloat16 (nearest,
+                    ties to even), products accumulated in binary32; panel solve
+                    in binary32; diagonal blocks in binary64 */
+} ff_dtype;
+
+/* Flags for the factorisations. */
+enum {
+    FF_FLAG_STRASSEN1 = 1u << 0,  /* one Strassen level in the trailing update
+                                      (Sec. 2, Strassen on rectangles) */
+    FF_FLAG_NO_LOOKAHEAD = 1u << 1 /* keep every step on `stream` in strict order */
+};
+
+enum {
+    FF_ERR_HIP = -100,
+    FF_ERR_WORKSPACE = -101,
+    FF_ERR_UNSUPPORTED = -102
+};
+
+const char *ff_status_string(int code);
+
+/* Library version string, e.g. "fastfact 0.1 gfx950". */
+const char *ff_version(void);
+
+/*
+ * Cholesky factorisation A = L L^T in place (Introduction; Sec. 2 Algorithm 1
+ * with step s).  Reads only the lower triangle of the n x n matrix A and
+ * overwrites it with L; the strict upper triangle is neither read nor written.
+ *   n      order, >= 0 (n = 0 is a no-op)
+ *   s      step size (columns per deferred update), >= 1; s >= n means no update
+ *   A      device pointer, double* for FF_F64, float* for FF_F32 / FF_BF16
+ *   lda    >= max(1, n)
+ *   dtype  ff_dtype
+ *   flags  FF_FLAG_*
+ *   ws     device workspace of ws_bytes bytes, >= ff_chol_workspace_size(...)
+ *          (may be NULL when that size is 0)
+ *   d_info device int32, see above
+ *   stream hipStream_t
+ */
+size_t ff_chol_workspace_size(int64_t n, int64_t s, int dtype, unsigned flags);
+int chol_factor(int64_t n, int64_t s, void *A, int64_t lda, int dtype, unsigned flags,
+                void *ws, size_t ws_bytes, int32_t *d_info, void *stream);
+
+/*
+ * LU factorisation without pivoting A = L U in place (Sec. 2 Algorithm 2 with
+ * step s; every leading principal minor of A must be nonzero).  The result is
+ * Doolittle-packed: the strict lower triangle holds the unit-lower L, the upper
+ * triangle including the diagonal holds U.  (Algorithm 2 returns the Crout form
+ * L_c = L D, U_c = D^-1 U with D = diag(U); the deferred products are equal in
+ * both forms.)  Only FF_F64 is implemented.
+ */
+size_t ff_lu_workspace_size(int64_t n, int64_t s, int dtype, unsigned flags);
+int lu_nopiv_factor(int64_t n, int64_t s, void *A, int64_t lda, int dtype, unsigned flags,
+                    void *ws, size_t ws_bytes, int32_t *d_info, void *stream);
+
+/* Outcome of chol_solve (host struct). */
+typedef struct {
+    int32_t info;          /* factorisation info (0 = ok), as d_info above */
+    int32_t iters;         /* refinement iterations performed */
+    int32_t converged;     /* 1 if the correction test was met */
+    int32_t dtype_used;    /* update precision of the factor that was used */
+    double last_correction;/* ||dX||_inf / ||X||_inf of the last iteration */
+    double backward_err;   /* max_j ||b_j - A x_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf) */
+} ff_solve_info;
+
+/*
+ * Solve A X = B for SPD A with mixed-precision iterative refinement.
+ *   A64   n x n binary64 SPD matrix (lower triangle read, never written)
+ *   W     n x n working factor in `dtype` storage (double* for FF_F64, float*
+ *         otherwise), leading dimension ldw.  If w_is_factored == 0 the call
+ *         copies tril(A64) into W (rounded for float storage) and factors it
+ *         with chol_factor(n, s, W, ldw, dtype, flags); otherwise W must hold
+ *         such a factor already (e.g. kept from an earlier request).
+ *   B     n x nrhs binary64 right-hand sides (read only), ldb >= n
+ *   X     n x nrhs binary64 solution (written), ldx >= n
+ *   tol   refinement stops once ||dX||_inf <= tol * ||X||_inf (per call, over
+ *         all columns); also on stagnation (the correction shrank by less
+ *         than half) or after max_iter iterations.  max_iter = 0 returns the
+ *         plain triangular-solve result.
+ *   ws    device workspace, >= ff_solve_workspace_size(n, s, nrhs, dtype)
+ *   out   host pointer, filled on return.
+ * The residual B - A X and the update X += dX are binary64; the triangular
+ * solves with W run in W's storage precision.  This call SYNCHRONISES `stream`
+ * (the stop test runs on the host) and returns 0 even if refinement did not
+ * converge (out->converged = 0) or the factorisation failed (out->info > 0).
+ */
+size_t ff_solve_workspace_size(int64_t n, int64_t s, int64_t nrhs, int dtype);
+int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double *A64, int64_t lda,
+               void *W, int64_t ldw, int dtype, unsigned flags, int w_is_factored,
+               const double *B, int64_t ldb, double *X, int64_t ldx,
+               double tol, int max_iter, void *ws, size_t ws_bytes, void *stream,
+               ff_solve_info *out);
+
+/*
+ * Triangular solve with a Cholesky factor: X = L^-T L^-1 X in place (forward
+ * then back substitution, in the storage precision of L: double for FF_F64,
+ * float otherwise; X has the same type).  L is n x n lower (only tril read).
+ * The solve works on 64-row blocks and first forms the inverses of the 64 x 64
+ * diagonal blocks of L in the workspace (binary64 arithmetic, stored in L's
+ * precision).  Asynchronous; a bounded wait that expired (which does not happen
+ * unless the device is shared with work that starves the launch) is reported
+ * in the workspace and by chol_solve.
+ *   ws   device workspace >= ff_trisolve_workspace_size(n, dtype)
+ */
+size_t ff_trisolve_workspace_size(int64_t n, int dtype);
+int chol_trisolve(int64_t n, int64_t nrhs, const void *L, int64_t ldl, int dtype,
+                  void *X, int64_t ldx, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The deferred update on its own (Sec. 2: S = R R^T, then A -= S over the
+ * trailing square), the library's hot kernel, exposed for tests and timing.
+ *   ff_update_syrk: C -= P P^T on the lower triangle (i >= j) of the m x m C;
+ *                   P is m x w.  The strict upper triangle of C is untouched.
+ *   ff_update_gemm: C -= X Y on all of the m x m C; X is m x w, Y is w x m
+ *                   (Algorithm 2's S = R_L R_U).
+ * C and the operands share the storage type of dtype (double for FF_F64,
+ * float otherwise).  Operands must not overlap C.  Asynchronous.
+ */
+int ff_update_syrk(int64_t m, int64_t w, void *C, int64_t ldc, const void *P, int64_t ldp,
+                   int dtype, unsigned flags, void *stream);
+int ff_update_gemm(int64_t m, int64_t w, void *C, int64_t ldc, const void *X, int64_t ldx,
+                   const void *Y, int64_t ldy, int dtype, unsigned flags, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTFACT_H */

@@ -1,0 +1,265 @@
+"""Thin Python binding of libfastfact (include/fastfact.h) over ctypes.
+
+Argument marshalling only: every step of the factorisations and solves runs in
+the HIP kernels of libfastfact.so.  PyTorch supplies device memory (tensors)
+and streams.  There is no fallback: if the library is missing, loading raises.
+
+Matrix convention: a matrix argument is a 2-D torch tensor M whose logical
+element (i, j) is M[i, j] and whose memory is column-major, i.e.
+M.stride(0) == 1 and M.stride(1) = ld >= rows (e.g. a Fortran-ordered numpy
+array moved with torch.from_numpy(a).to(device), or t.t() of a contiguous
+row-major tensor t).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfastfact.so")
+
+F64, F32, BF16 = 0, 1, 2
+FLAG_STRASSEN1 = 1
+FLAG_NO_LOOKAHEAD = 2
+ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED = -100, -101, -102
+
+_DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+_STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
+
+# Every symbol include/fastfact.h declares.
+EXPORTED = (
+    "ff_status_string", "ff_version", "ff_chol_workspace_size", "chol_factor",
+    "ff_lu_workspace_size", "lu_nopiv_factor", "ff_solve_workspace_size", "chol_solve",
+    "ff_trisolve_workspace_size", "chol_trisolve", "ff_update_syrk", "ff_update_gemm",
+)
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("info", ctypes.c_int32), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("dtype_used", ctypes.c_int32), ("last_correction", ctypes.c_double),
+                ("backward_err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FastFactError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load libfastfact.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FastFactError(f"{LIB_PATH} is missing: build it with `python -m paper_1812_02056_amd.build` "
+                            "(there is no non-HIP fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, u32, i32, vp, sz, dbl = (ctypes.c_int64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.c_double)
+    lib.ff_status_string.argtypes = [i32]
+    lib.ff_status_string.restype = ctypes.c_char_p
+    lib.ff_version.argtypes = []
+    lib.ff_version.restype = ctypes.c_char_p
+    lib.ff_chol_workspace_size.argtypes = [i64, i64, i32, u32]
+    lib.ff_chol_workspace_size.restype = sz
+    lib.chol_factor.argtypes = [i64, i64, vp, i64, i32, u32, vp, sz, vp, vp]
+    lib.chol_factor.restype = i32
+    lib.ff_lu_workspace_size.argtypes = [i64, i64, i32, u32]
+    lib.ff_lu_workspace_size.restype = sz
+    lib.lu_nopiv_factor.argtypes = [i64, i64, vp, i64, i32, u32, vp, sz, vp, vp]
+    lib.lu_nopiv_factor.restype = i32
+    lib.ff_solve_workspace_size.argtypes = [i64, i64, i64, i32]
+    lib.ff_solve_workspace_size.restype = sz
+    lib.chol_solve.argtypes = [i64, i64, i64, vp, i64, vp, i64, i32, u32, i32, vp, i64, vp, i64,
+                               dbl, i32, vp, sz, vp, ctypes.POINTER(SolveInfo)]
+    lib.chol_solve.restype = i32
+    lib.ff_trisolve_workspace_size.argtypes = [i64, i32]
+    lib.ff_trisolve_workspace_size.restype = sz
+    lib.chol_trisolve.argtypes = [i64, i64, vp, i64, i32, vp, i64, vp, sz, vp]
+    lib.chol_trisolve.restype = i32
+    lib.ff_update_syrk.argtypes = [i64, i64, vp, i64, vp, i64, i32, u32, vp]
+    lib.ff_update_syrk.restype = i32
+    lib.ff_update_gemm.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, i32, u32, vp]
+    lib.ff_update_gemm.restype = i32
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().ff_status_string(int(code)).decode()
+
+
+def version() -> str:
+    return load().ff_version().decode()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise FastFactError(f"{what} failed: {rc} ({status_string(rc)})")
+
+
+def _dt(dtype) -> int:
+    try:
+        return _DTYPES[dtype]
+    except KeyError:
+        raise ValueError(f"unknown dtype {dtype!r}") from None
+
+
+def _ld(M: torch.Tensor, name: str) -> int:
+    if M.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if M.shape[0] > 1 and M.stride(0) != 1:
+        raise ValueError(f"{name} must be column-major (stride(0) == 1)")
+    return max(int(M.stride(1)) if M.shape[1] > 1 else int(M.shape[0]), int(M.shape[0]), 1)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def colmajor_empty(rows: int, cols: int, dtype, device, ld: int | None = None) -> torch.Tensor:
+    """An uninitialised rows x cols column-major tensor with leading dimension ld."""
+    ld = rows if ld is None else ld
+    return torch.empty((cols, ld), dtype=dtype, device=device).t()[:rows]
+
+
+def to_device(a, device="cuda", dtype=None, ld: int | None = None) -> torch.Tensor:
+    """Copy a (numpy or torch) matrix to a column-major device tensor."""
+    t = torch.as_tensor(a)
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    dt = dtype or t.dtype
+    out = colmajor_empty(t.shape[0], t.shape[1], dt, device, ld)
+    out.copy_(t.to(dt))
+    return out
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor | None:
+    if nbytes == 0:
+        return None
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def chol_workspace_size(n: int, s: int, dtype="f64", strassen=False) -> int:
+    return int(load().ff_chol_workspace_size(n, s, _dt(dtype), FLAG_STRASSEN1 if strassen else 0))
+
+
+def chol_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_lookahead=False, stream=None,
+                ws: torch.Tensor | None = None, info: torch.Tensor | None = None, sync=False):
+    """In-place Cholesky A = L L^T (tril(A) read and overwritten).  Returns the
+    device int32 info tensor, or (sync=True) its value as a Python int."""
+    lib = load()
+    dt = _dt(dtype)
+    n = int(A.shape[0])
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    if A.dtype != _STORAGE[dt]:
+        raise ValueError(f"A must be {_STORAGE[dt]} for dtype {dtype}")
+    flags = (FLAG_STRASSEN1 if strassen else 0) | (FLAG_NO_LOOKAHEAD if no_lookahead else 0)
+    need = int(lib.ff_chol_workspace_size(n, s, dt, flags))
+    if ws is None:
+        ws = _workspace(need, A.device)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    rc = lib.chol_factor(n, s, _ptr(A), _ld(A, "A"), dt, flags, _ptr(ws), 0 if ws is None else ws.numel(),
+                         _ptr(info), _stream(stream))
+    _check(rc, "chol_factor")
+    if sync:
+        (stream or torch.cuda.current_stream()).synchronize()
+        return int(info.item())
+    return info
+
+
+def lu_nopiv_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_lookahead=False, stream=None,
+                    info: torch.Tensor | None = None, sync=False):
+    """In-place LU without pivoting, Doolittle packed (unit-lower L below the diagonal, U on and above)."""
+    lib = load()
+    dt = _dt(dtype)
+    n = int(A.shape[0])
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    flags = (FLAG_STRASSEN1 if strassen else 0) | (FLAG_NO_LOOKAHEAD if no_lookahead else 0)
+    need = int(lib.ff_lu_workspace_size(n, s, dt, flags))
+    ws = _workspace(need, A.device)
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    rc = lib.lu_nopiv_factor(n, s, _ptr(A), _ld(A, "A"), dt, flags, _ptr(ws), 0 if ws is None else ws.numel(),
+                             _ptr(info), _stream(stream))
+    _check(rc, "lu_nopiv_factor")
+    if sync:
+        (stream or torch.cuda.current_stream()).synchronize()
+        return int(info.item())
+    return info
+
+
+def solve_workspace_size(n: int, s: int, nrhs: int, dtype="f64") -> int:
+    return int(load().ff_solve_workspace_size(n, s, nrhs, _dt(dtype)))
+
+
+def chol_solve(A64: torch.Tensor, B: torch.Tensor, s: int, dtype="f32", W: torch.Tensor | None = None,
+               w_is_factored=False, X: torch.Tensor | None = None, tol=1e-13, max_iter=50, strassen=False,
+               stream=None, ws: torch.Tensor | None = None):
+    """Solve A64 X = B with a factor W in `dtype` and binary64 refinement.
+    Returns (X, W, info dict).  Synchronises the stream."""
+    lib = load()
+    dt = _dt(dtype)
+    n = int(A64.shape[0])
+    nrhs = int(B.shape[1])
+    if W is None:
+        if w_is_factored:
+            raise ValueError("w_is_factored requires W")
+        W = colmajor_empty(n, n, _STORAGE[dt], A64.device)
+    if X is None:
+        X = colmajor_empty(n, nrhs, torch.float64, A64.device)
+    if ws is None:
+        ws = _workspace(int(lib.ff_solve_workspace_size(n, s, nrhs, dt)), A64.device)
+    out = SolveInfo()
+    rc = lib.chol_solve(n, s, nrhs, _ptr(A64), _ld(A64, "A64"), _ptr(W), _ld(W, "W"), dt,
+                        FLAG_STRASSEN1 if strassen else 0, 1 if w_is_factored else 0,
+                        _ptr(B), _ld(B, "B"), _ptr(X), _ld(X, "X"), float(tol), int(max_iter),
+                        _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream), ctypes.byref(out))
+    _check(rc, "chol_solve")
+    return X, W, out.as_dict()
+
+
+def chol_trisolve(L: torch.Tensor, X: torch.Tensor, dtype="f64", stream=None, ws: torch.Tensor | None = None):
+    """X <- L^-T L^-1 X in place, in L's storage precision."""
+    lib = load()
+    dt = _dt(dtype)
+    n = int(L.shape[0])
+    if ws is None:
+        ws = _workspace(int(lib.ff_trisolve_workspace_size(n, dt)), L.device)
+    rc = lib.chol_trisolve(n, int(X.shape[1]), _ptr(L), _ld(L, "L"), dt, _ptr(X), _ld(X, "X"),
+                           _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream))
+    _check(rc, "chol_trisolve")
+    return X
+
+
+def update_syrk(C: torch.Tensor, P: torch.Tensor, dtype="f64", strassen=False, stream=None):
+    """tril(C) -= tril(P P^T) (Algorithm 1's deferred update) in place."""
+    rc = load().ff_update_syrk(int(C.shape[0]), int(P.shape[1]), _ptr(C), _ld(C, "C"), _ptr(P), _ld(P, "P"),
+                               _dt(dtype), FLAG_STRASSEN1 if strassen else 0, _stream(stream))
+    _check(rc, "ff_update_syrk")
+    return C
+
+
+def update_gemm(C: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, dtype="f64", strassen=False, stream=None):
+    """C -= X Y (Algorithm 2's deferred update) in place."""
+    rc = load().ff_update_gemm(int(C.shape[0]), int(X.shape[1]), _ptr(C), _ld(C, "C"), _ptr(X), _ld(X, "X"),
+                               _ptr(Y), _ld(Y, "Y"), _dt(dtype), FLAG_STRASSEN1 if strassen else 0,
+                               _stream(stream))
+    _check(rc, "ff_update_gemm")
+    return C

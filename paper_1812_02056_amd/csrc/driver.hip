@@ -1,0 +1,452 @@
+// driver.hip -- host side of libfastfact: argument checks, the block schedule of
+// Algorithms 1 and 2 (Sec. 2 of arXiv 1812.02056), workspace carving and the
+// refinement loop of chol_solve.  Implements include/fastfact.h.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "fastfact.h"
+#include "internal.hpp"
+
+namespace ff {
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Inner step used when a diagonal block is larger than the single-workgroup
+// diagonal kernels take: the block is itself factored by the same delayed-update
+// schedule with this step.
+constexpr int INNER_S = 256;
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+    template <typename T> T* take(size_t count) {
+        T* p = reinterpret_cast<T*>(base + off);
+        off += align_up(count * sizeof(T));
+        return p;
+    }
+};
+
+size_t diag_ws_bytes(int64_t n, int64_t s, int dtype) {
+    if (dtype == FF_F64 || n <= 0) return 0;
+    const int64_t w = std::min<int64_t>(s, n);
+    return align_up((size_t)w * (size_t)w * sizeof(double));
+}
+
+#define FF_TRY(expr)                                  \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return FF_ERR_HIP;      \
+    } while (0)
+
+// ---------------------------------------------------------------- Cholesky
+// Algorithm 1 as a block schedule: block k covers columns c0 = k*s .. c0+w-1;
+// the diagonal factorisation and the panel solve form those columns from the
+// matrix as updated so far, then the deferred product of the w new columns is
+// subtracted from the trailing square (the update of the paper's conditional,
+// which fires floor((n-1)/s) times).
+template <typename S>
+int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, double* ws64, int* info,
+                 int col_base, hipStream_t st);
+
+int chol_diag_f64(int w, double* A11, int64_t lda, int* info, int col_base, hipStream_t st) {
+    if (w <= DIAG_MAX) {
+        FF_TRY(launch_potrf_diag<double>(w, A11, lda, nullptr, info, col_base, st));
+        return 0;
+    }
+    return chol_blocked<double>(w, INNER_S, A11, lda, FF_F64, 0, nullptr, info, col_base, st);
+}
+
+template <typename S>
+int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, double* ws64, int* info,
+                 int col_base, hipStream_t st) {
+    for (int c0 = 0; c0 < n; c0 += s) {
+        const int w = std::min(s, n - c0);
+        const int m = n - c0 - w;
+        S* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
+        if constexpr (sizeof(S) == sizeof(double)) {
+            int rc = chol_diag_f64(w, reinterpret_cast<double*>(A11), lda, info, col_base + c0, st);
+            if (rc) return rc;
+        } else {
+            if (w <= DIAG_MAX) {
+                FF_TRY(launch_potrf_diag<float>(w, A11, lda, ws64, info, col_base + c0, st));
+            } else {
+                // widen the block, factor it in binary64, round it back
+                FF_TRY(launch_widen_lower<float>(w, A11, lda, ws64, w, st));
+                int rc = chol_diag_f64(w, ws64, w, info, col_base + c0, st);
+                if (rc) return rc;
+                FF_TRY(launch_narrow_lower<float>(w, ws64, w, A11, lda, st));
+            }
+        }
+        if (m <= 0) break;
+        S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
+        S* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
+        // L21 = A21 L11^-T: X T = B with T(k, j) = L11(j, k)
+        FF_TRY(launch_trsm<S>(m, w, A21, 1, lda, A11, lda, 1, 0, info, st));
+        if constexpr (sizeof(S) == sizeof(double)) {
+            if (flags & FF_FLAG_STRASSEN1)
+                FF_TRY(launch_update_syrk_strassen_f64(m, w, reinterpret_cast<double*>(A22), lda,
+                                                       reinterpret_cast<const double*>(A21), lda, info, st));
+            else
+                FF_TRY(launch_update_syrk<double>(m, w, reinterpret_cast<double*>(A22), lda,
+                                                  reinterpret_cast<const double*>(A21), lda, info, st));
+        } else {
+            if (dtype == FF_BF16)
+                FF_TRY(launch_update_syrk_bf16(m, w, A22, lda, A21, lda, info, st));
+            else
+                FF_TRY(launch_update_syrk<float>(m, w, A22, lda, A21, lda, info, st));
+        }
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------- LU
+// Algorithm 2 as a block schedule (Doolittle packing): diagonal GETRF, then
+// L21 = A21 U11^-1 and U12 = L11^-1 A12, then A22 -= L21 U12.
+int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st) {
+    for (int c0 = 0; c0 < n; c0 += s) {
+        const int w = std::min(s, n - c0);
+        const int m = n - c0 - w;
+        double* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
+        if (w <= DIAG_MAX) {
+            FF_TRY(launch_getrf_diag(w, A11, lda, info, col_base + c0, st));
+        } else {
+            int rc = lu_blocked(w, INNER_S, A11, lda, 0, info, col_base + c0, st);
+            if (rc) return rc;
+        }
+        if (m <= 0) break;
+        double* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
+        double* A12 = A + (int64_t)c0 + (int64_t)(c0 + w) * lda;
+        double* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
+        // L21 U11 = A21: T(k, j) = U11(k, j) = A11[k + j*lda]
+        FF_TRY(launch_trsm<double>(m, w, A21, 1, lda, A11, 1, lda, 0, info, st));
+        // L11 U12 = A12  <=>  U12^T L11^T = A12^T: rows of X are columns of A12,
+        // T(k, j) = L11(j, k) with unit diagonal
+        FF_TRY(launch_trsm<double>(m, w, A12, lda, 1, A11, lda, 1, 1, info, st));
+        if (flags & FF_FLAG_STRASSEN1)
+            FF_TRY(launch_update_gemm_strassen_f64(m, w, A22, lda, A21, lda, A12, lda, info, st));
+        else
+            FF_TRY(launch_update_gemm<double>(m, w, A22, lda, A21, lda, A12, lda, info, st));
+    }
+    return 0;
+}
+
+int check_common(int64_t n, int64_t s, const void* A, int64_t lda, int dtype, unsigned flags) {
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return -1;
+    if (s < 1) return -2;
+    if (n > 0 && A == nullptr) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -5;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD)) return -6;
+    return 0;
+}
+
+template <typename S>
+struct SolveWs {
+    double* diag64;
+    int* d_info;
+    S* linv;
+    int* flags;
+    double* R;
+    S* D;
+    double* rowsum;
+    double* norms;
+    size_t bytes;
+};
+
+template <typename S>
+SolveWs<S> carve_solve(void* base, int64_t n, int64_t s, int64_t nrhs, int dtype) {
+    Carver cv(base);
+    SolveWs<S> w;
+    w.diag64 = cv.take<double>(diag_ws_bytes(n, s, dtype) / sizeof(double));
+    w.d_info = cv.take<int>(1);
+    w.linv = cv.take<S>(trisolve_linv_elems((int)n));
+    w.flags = cv.take<int>(trisolve_flag_ints((int)n));
+    w.R = cv.take<double>((size_t)n * (size_t)nrhs);
+    w.D = cv.take<S>((size_t)n * (size_t)nrhs);
+    w.rowsum = cv.take<double>((size_t)n);
+    w.norms = cv.take<double>(3 + 3 * (size_t)nrhs);
+    w.bytes = cv.off;
+    return w;
+}
+
+template <typename S>
+int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int64_t ldw, int dtype,
+               unsigned flags, int w_is_factored, const double* B, int64_t ldb, double* X, int64_t ldx,
+               double tol, int max_iter, void* ws, hipStream_t st, ff_solve_info* out) {
+    SolveWs<S> w = carve_solve<S>(ws, n, s, nrhs, dtype);
+    out->info = 0;
+    out->iters = 0;
+    out->converged = 0;
+    out->dtype_used = dtype;
+    out->last_correction = 0.0;
+    out->backward_err = 0.0;
+    if (!w_is_factored) {
+        FF_TRY(launch_copy_lower_from_f64<S>(n, A64, lda, W, ldw, st));
+        FF_TRY(launch_set_int(w.d_info, 0, st));
+        int rc = chol_blocked<S>(n, s, W, ldw, dtype, flags, w.diag64, w.d_info, 0, st);
+        if (rc) return rc;
+        int info = 0;
+        FF_TRY(hipMemcpyAsync(&info, w.d_info, sizeof(int), hipMemcpyDeviceToHost, st));
+        FF_TRY(hipStreamSynchronize(st));
+        if (info != 0) {
+            out->info = info;
+            return 0;
+        }
+    }
+    const int nblk = trisolve_nblk(n);
+    // iteration 0: X = W^-T W^-1 B in the factor's precision
+    FF_TRY(launch_convert_from_f64<S>(n, nrhs, B, ldb, w.D, n, st));
+    FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.linv, w.flags, true, st));
+    FF_TRY(launch_widen<S>(n, nrhs, w.D, n, X, ldx, st));
+    double prev = -1.0;
+    double host[2];
+    int bad_wait = 0;
+    for (int it = 1; it <= max_iter; ++it) {
+        FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, nullptr, st));
+        FF_TRY(launch_convert_from_f64<S>(n, nrhs, w.R, n, w.D, n, st));
+        FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.linv, w.flags, false, st));
+        FF_TRY(launch_axpy_max<S>(n, nrhs, w.D, n, X, ldx, w.norms, st));
+        FF_TRY(hipMemcpyAsync(host, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        FF_TRY(hipStreamSynchronize(st));
+        out->iters = it;
+        const double corr = (host[1] > 0.0) ? host[0] / host[1] : host[0];
+        out->last_correction = corr;
+        if (corr <= tol) {
+            out->converged = 1;
+            break;
+        }
+        if (prev >= 0.0 && corr > 0.5 * prev) break;   // stagnation
+        prev = corr;
+    }
+    // backward error of the returned X
+    FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, w.rowsum, st));
+    FF_TRY(launch_norms(n, nrhs, w.rowsum, X, ldx, nullptr, 0, w.R, n, B, ldb, w.norms, st));
+    std::vector<double> nh(3 + 3 * (size_t)nrhs);
+    int wait_err[2] = {0, 0};
+    FF_TRY(hipMemcpyAsync(nh.data(), w.norms, nh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    FF_TRY(hipMemcpyAsync(&wait_err[0], w.flags + nblk + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    FF_TRY(hipMemcpyAsync(&wait_err[1], w.flags + 2 * nblk + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+    FF_TRY(hipStreamSynchronize(st));
+    bad_wait = wait_err[0] | wait_err[1];
+    if (bad_wait) return FF_ERR_HIP;
+    const double anorm = nh[2];
+    double be = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        const double den = anorm * nh[4 + 3 * c] + nh[5 + 3 * c];
+        const double v = den > 0.0 ? nh[3 + 3 * c] / den : nh[3 + 3 * c];
+        be = std::max(be, v);
+    }
+    out->backward_err = be;
+    if (max_iter == 0) out->converged = 0;
+    return 0;
+}
+
+}  // namespace
+}  // namespace ff
+
+using namespace ff;
+
+extern "C" {
+
+const char* ff_status_string(int code) {
+    switch (code) {
+        case 0: return "success";
+        case FF_ERR_HIP: return "HIP runtime error";
+        case FF_ERR_WORKSPACE: return "workspace too small";
+        case FF_ERR_UNSUPPORTED: return "unsupported argument combination";
+        default: break;
+    }
+    if (code < 0 && code > -100) return "invalid argument (index = -code)";
+    return "unknown status";
+}
+
+const char* ff_version(void) { return "fastfact 0.1 gfx950"; }
+
+size_t ff_chol_workspace_size(int64_t n, int64_t s, int dtype, unsigned flags) {
+    (void)flags;
+    if (n <= 0 || s < 1) return 0;
+    return diag_ws_bytes(n, s, dtype);
+}
+
+int chol_factor(int64_t n, int64_t s, void* A, int64_t lda, int dtype, unsigned flags, void* ws, size_t ws_bytes,
+                int32_t* d_info, void* stream) {
+    int rc = check_common(n, s, A, lda, dtype, flags);
+    if (rc) return rc;
+    if (d_info == nullptr) return -9;
+    if ((flags & FF_FLAG_STRASSEN1) && dtype != FF_F64) return FF_ERR_UNSUPPORTED;
+    const size_t need = ff_chol_workspace_size(n, s, dtype, flags);
+    if (need > 0 && (ws == nullptr || ws_bytes < need)) return FF_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (launch_set_int(d_info, 0, st) != hipSuccess) return FF_ERR_HIP;
+    if (n == 0) return 0;
+    const int si = (int)std::min<int64_t>(s, n);
+    if (dtype == FF_F64)
+        return chol_blocked<double>((int)n, si, static_cast<double*>(A), lda, dtype, flags, nullptr, d_info, 0, st);
+    return chol_blocked<float>((int)n, si, static_cast<float*>(A), lda, dtype, flags, static_cast<double*>(ws), d_info,
+                               0, st);
+}
+
+size_t ff_lu_workspace_size(int64_t n, int64_t s, int dtype, unsigned flags) {
+    (void)n; (void)s; (void)dtype; (void)flags;
+    return 0;
+}
+
+int lu_nopiv_factor(int64_t n, int64_t s, void* A, int64_t lda, int dtype, unsigned flags, void* ws, size_t ws_bytes,
+                    int32_t* d_info, void* stream) {
+    (void)ws; (void)ws_bytes;
+    int rc = check_common(n, s, A, lda, dtype, flags);
+    if (rc) return rc;
+    if (d_info == nullptr) return -9;
+    if (dtype != FF_F64) return FF_ERR_UNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (launch_set_int(d_info, 0, st) != hipSuccess) return FF_ERR_HIP;
+    if (n == 0) return 0;
+    const int si = (int)std::min<int64_t>(s, n);
+    return lu_blocked((int)n, si, static_cast<double*>(A), lda, flags, d_info, 0, st);
+}
+
+size_t ff_solve_workspace_size(int64_t n, int64_t s, int64_t nrhs, int dtype) {
+    if (n <= 0 || nrhs <= 0 || s < 1) return 0;
+    if (dtype == FF_F64) return carve_solve<double>(nullptr, n, s, nrhs, dtype).bytes;
+    return carve_solve<float>(nullptr, n, s, nrhs, dtype).bytes;
+}
+
+int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t lda, void* W, int64_t ldw, int dtype,
+               unsigned flags, int w_is_factored, const double* B, int64_t ldb, double* X, int64_t ldx, double tol,
+               int max_iter, void* ws, size_t ws_bytes, void* stream, ff_solve_info* out) {
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return -1;
+    if (s < 1) return -2;
+    if (nrhs < 0) return -3;
+    if (n > 0 && A64 == nullptr) return -4;
+    if (lda < std::max<int64_t>(1, n)) return -5;
+    if (n > 0 && W == nullptr) return -6;
+    if (ldw < std::max<int64_t>(1, n)) return -7;
+    if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -8;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD)) return -9;
+    if (n > 0 && nrhs > 0 && B == nullptr) return -11;
+    if (ldb < std::max<int64_t>(1, n)) return -12;
+    if (n > 0 && nrhs > 0 && X == nullptr) return -13;
+    if (ldx < std::max<int64_t>(1, n)) return -14;
+    if (!(tol >= 0.0)) return -15;
+    if (max_iter < 0) return -16;
+    if (out == nullptr) return -20;
+    if ((flags & FF_FLAG_STRASSEN1) && dtype != FF_F64) return FF_ERR_UNSUPPORTED;
+    memset(out, 0, sizeof(*out));
+    out->dtype_used = dtype;
+    if (n == 0 || nrhs == 0) return 0;
+    const size_t need = ff_solve_workspace_size(n, s, nrhs, dtype);
+    if (ws == nullptr || ws_bytes < need) return FF_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int si = (int)std::min<int64_t>(s, n);
+    if (dtype == FF_F64)
+        return solve_impl<double>((int)n, si, (int)nrhs, A64, lda, static_cast<double*>(W), ldw, dtype, flags,
+                                  w_is_factored, B, ldb, X, ldx, tol, max_iter, ws, st, out);
+    return solve_impl<float>((int)n, si, (int)nrhs, A64, lda, static_cast<float*>(W), ldw, dtype, flags,
+                             w_is_factored, B, ldb, X, ldx, tol, max_iter, ws, st, out);
+}
+
+size_t ff_trisolve_workspace_size(int64_t n, int dtype) {
+    if (n <= 0) return 0;
+    const size_t es = (dtype == FF_F64) ? sizeof(double) : sizeof(float);
+    return align_up(trisolve_linv_elems((int)n) * es) + align_up(trisolve_flag_ints((int)n) * sizeof(int));
+}
+
+int chol_trisolve(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtype, void* X, int64_t ldx, void* ws,
+                  size_t ws_bytes, void* stream) {
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return -1;
+    if (nrhs < 0) return -2;
+    if (n > 0 && L == nullptr) return -3;
+    if (ldl < std::max<int64_t>(1, n)) return -4;
+    if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -5;
+    if (n > 0 && nrhs > 0 && X == nullptr) return -6;
+    if (ldx < std::max<int64_t>(1, n)) return -7;
+    if (n == 0 || nrhs == 0) return 0;
+    if (ws == nullptr || ws_bytes < ff_trisolve_workspace_size(n, dtype)) return FF_ERR_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver cv(ws);
+    if (dtype == FF_F64) {
+        double* linv = cv.take<double>(trisolve_linv_elems((int)n));
+        int* flags = cv.take<int>(trisolve_flag_ints((int)n));
+        if (trisolve_impl<double>((int)n, (int)nrhs, static_cast<const double*>(L), ldl, static_cast<double*>(X), ldx,
+                                  linv, flags, true, st) != hipSuccess)
+            return FF_ERR_HIP;
+    } else {
+        float* linv = cv.take<float>(trisolve_linv_elems((int)n));
+        int* flags = cv.take<int>(trisolve_flag_ints((int)n));
+        if (trisolve_impl<float>((int)n, (int)nrhs, static_cast<const float*>(L), ldl, static_cast<float*>(X), ldx,
+                                 linv, flags, true, st) != hipSuccess)
+            return FF_ERR_HIP;
+    }
+    return 0;
+}
+
+int ff_update_syrk(int64_t m, int64_t w, void* C, int64_t ldc, const void* P, int64_t ldp, int dtype, unsigned flags,
+                   void* stream) {
+    if (m < 0 || m > (int64_t)INT32_MAX / 2) return -1;
+    if (w < 0 || w > (int64_t)INT32_MAX / 2) return -2;
+    if (m > 0 && C == nullptr) return -3;
+    if (ldc < std::max<int64_t>(1, m)) return -4;
+    if (m > 0 && w > 0 && P == nullptr) return -5;
+    if (ldp < std::max<int64_t>(1, m)) return -6;
+    if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -7;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD)) return -8;
+    if ((flags & FF_FLAG_STRASSEN1) && dtype != FF_F64) return FF_ERR_UNSUPPORTED;
+    if (m == 0 || w == 0) return 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (dtype == FF_F64) {
+        if (flags & FF_FLAG_STRASSEN1)
+            e = launch_update_syrk_strassen_f64((int)m, (int)w, static_cast<double*>(C), ldc,
+                                                static_cast<const double*>(P), ldp, nullptr, st);
+        else
+            e = launch_update_syrk<double>((int)m, (int)w, static_cast<double*>(C), ldc, static_cast<const double*>(P),
+                                           ldp, nullptr, st);
+    } else if (dtype == FF_F32) {
+        e = launch_update_syrk<float>((int)m, (int)w, static_cast<float*>(C), ldc, static_cast<const float*>(P), ldp,
+                                      nullptr, st);
+    } else {
+        e = launch_update_syrk_bf16((int)m, (int)w, static_cast<float*>(C), ldc, static_cast<const float*>(P), ldp,
+                                    nullptr, st);
+    }
+    return e == hipSuccess ? 0 : FF_ERR_HIP;
+}
+
+int ff_update_gemm(int64_t m, int64_t w, void* C, int64_t ldc, const void* X, int64_t ldx, const void* Y, int64_t ldy,
+                   int dtype, unsigned flags, void* stream) {
+    if (m < 0 || m > (int64_t)INT32_MAX / 2) return -1;
+    if (w < 0 || w > (int64_t)INT32_MAX / 2) return -2;
+    if (m > 0 && C == nullptr) return -3;
+    if (ldc < std::max<int64_t>(1, m)) return -4;
+    if (m > 0 && w > 0 && X == nullptr) return -5;
+    if (ldx < std::max<int64_t>(1, m)) return -6;
+    if (m > 0 && w > 0 && Y == nullptr) return -7;
+    if (ldy < std::max<int64_t>(1, w)) return -8;
+    if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -9;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD)) return -10;
+    if (dtype == FF_BF16) return FF_ERR_UNSUPPORTED;
+    if ((flags & FF_FLAG_STRASSEN1) && dtype != FF_F64) return FF_ERR_UNSUPPORTED;
+    if (m == 0 || w == 0) return 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (dtype == FF_F64) {
+        if (flags & FF_FLAG_STRASSEN1)
+            e = launch_update_gemm_strassen_f64((int)m, (int)w, static_cast<double*>(C), ldc,
+                                                static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy,
+                                                nullptr, st);
+        else
+            e = launch_update_gemm<double>((int)m, (int)w, static_cast<double*>(C), ldc, static_cast<const double*>(X),
+                                           ldx, static_cast<const double*>(Y), ldy, nullptr, st);
+    } else {
+        e = launch_update_gemm<float>((int)m, (int)w, static_cast<float*>(C), ldc, static_cast<const float*>(X), ldx,
+                                      static_cast<const float*>(Y), ldy, nullptr, st);
+    }
+    return e == hipSuccess ? 0 : FF_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// internal.hpp -- launchers shared between the kernel files and the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ff {
+
+// Largest diagonal block the single-workgroup diagonal kernels take; larger
+// blocks are factored recursively by the host driver.
+constexpr int DIAG_MAX = 512;
+
+hipError_t launch_set_int(int* p, int v, hipStream_t st);
+
+// Trailing updates (update.hip).
+// `info` (may be null): the kernels do nothing when *info != 0.
+template <typename T>
+hipError_t launch_update_syrk(int m, int w, T* C, int64_t ldc, const T* P, int64_t ldp, const int* info,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_update_gemm(int m, int w, T* C, int64_t ldc, const T* X, int64_t ldx,
+                              const T* Y, int64_t ldy, const int* info, hipStream_t st);
+hipError_t launch_update_syrk_bf16(int m, int w, float* C, int64_t ldc, const float* P, int64_t ldp,
+                                   const int* info, hipStream_t st);
+// One Strassen level over 2x2 super-tiles of output tiles (strassen.hip).
+hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc, const double* P, int64_t ldp,
+                                           const int* info, hipStream_t st);
+hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc, const double* X, int64_t ldx,
+                                           const double* Y, int64_t ldy, const int* info, hipStream_t st);
+
+// Diagonal factorisations and panel solves (panel.hip).
+template <typename S>
+hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, double* ws, int* info, int col_base, hipStream_t st);
+hipError_t launch_getrf_diag(int w, double* a, int64_t ld, int* info, int col_base, hipStream_t st);
+template <typename T>
+hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, int64_t tk, int64_t tj,
+                       int unit, const int* info, hipStream_t st);
+
+// Solve-side kernels (solve.hip).
+template <typename S>
+hipError_t launch_copy_lower_from_f64(int n, const double* A, int64_t lda, S* W, int64_t ldw, hipStream_t st);
+template <typename S>
+hipError_t launch_convert_from_f64(int n, int nrhs, const double* B, int64_t ldb, S* X, int64_t ldx, hipStream_t st);
+// Solve L L^T X = X in place with 64-row blocks; Linv holds (or, when
+// make_inverses, receives) the inverses of the 64 x 64 diagonal blocks
+// (trisolve_linv_elems(n) elements); flags needs trisolve_flag_ints(n) ints.
+// flags[nblk + 1] / flags[2*nblk + 3] become nonzero if a bounded wait expired.
+inline int trisolve_nblk(int n) { return (n + 63) / 64; }
+inline size_t trisolve_linv_elems(int n) { return (size_t)trisolve_nblk(n) * 64 * 64; }
+inline size_t trisolve_flag_ints(int n) { return 2 * ((size_t)trisolve_nblk(n) + 2); }
+template <typename S>
+hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, S* Linv, int* flags,
+                         bool make_inverses, hipStream_t st);
+hipError_t launch_residual_f64(int n, int nrhs, const double* A, int64_t lda, const double* X, int64_t ldx,
+                               const double* B, int64_t ldb, double* R, int64_t ldr, double* rowsum,
+                               hipStream_t st);
+template <typename S>
+hipError_t launch_axpy_update(int n, int nrhs, const S* D, int64_t ldd, double* X, int64_t ldx, hipStream_t st);
+// X += D, out[0] = max|D|, out[1] = max|X|.
+template <typename S>
+hipError_t launch_axpy_max(int n, int nrhs, const S* D, int64_t ldd, double* X, int64_t ldx, double* out,
+                           hipStream_t st);
+template <typename S>
+hipError_t launch_widen(int n, int nrhs, const S* D, int64_t ldd, double* X, int64_t ldx, hipStream_t st);
+template <typename S>
+hipError_t launch_widen_lower(int w, const S* a, int64_t lda, double* d, int64_t ldd, hipStream_t st);
+template <typename S>
+hipError_t launch_narrow_lower(int w, const double* d, int64_t ldd, S* a, int64_t lda, hipStream_t st);
+hipError_t launch_norms(int n, int nrhs, const double* rowsum, const double* X, int64_t ldx, const double* D,
+                        int64_t ldd, const double* R, int64_t ldr, const double* B, int64_t ldb, double* out,
+                        hipStream_t st);
+
+}  // namespace ff

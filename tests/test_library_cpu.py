@@ -1,0 +1,76 @@
+"""Host-side checks of libfastfact that need no GPU: the C ABI loads, exports every
+symbol include/fastfact.h declares, and rejects invalid arguments before any
+device work (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastfact.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1812_02056_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1812_02056_amd import build
+        build.build()
+    return binding.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "sizeof")))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for n in ("chol_factor", "lu_nopiv_factor", "chol_solve"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1812_02056_amd import binding
+    names = _declared_functions()
+    assert sorted(names) == sorted(binding.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n), n
+        assert ctypes.cast(getattr(lib, n), ctypes.c_void_p).value
+
+
+def test_version_and_status_strings(lib):
+    from paper_1812_02056_amd import binding
+    assert "gfx950" in binding.version()
+    assert binding.status_string(0) == "success"
+    assert "workspace" in binding.status_string(-101)
+    assert "invalid argument" in binding.status_string(-4)
+
+
+def test_invalid_arguments_are_rejected_on_the_host(lib):
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    assert lib.chol_factor(-1, 4, fake, 1, 0, 0, null, 0, fake, null) == -1
+    assert lib.chol_factor(8, 0, fake, 8, 0, 0, null, 0, fake, null) == -2
+    assert lib.chol_factor(8, 4, null, 8, 0, 0, null, 0, fake, null) == -3
+    assert lib.chol_factor(8, 4, fake, 7, 0, 0, null, 0, fake, null) == -4
+    assert lib.chol_factor(8, 4, fake, 8, 7, 0, null, 0, fake, null) == -5
+    assert lib.chol_factor(8, 4, fake, 8, 0, 1 << 9, null, 0, fake, null) == -6
+    assert lib.chol_factor(8, 4, fake, 8, 0, 0, null, 0, null, null) == -9
+    # binary32 storage needs a binary64 workspace for the diagonal blocks
+    assert lib.chol_factor(8, 4, fake, 8, 1, 0, null, 0, fake, null) == -101
+    assert lib.lu_nopiv_factor(8, 4, fake, 8, 1, 0, null, 0, fake, null) == -102
+    assert lib.ff_update_syrk(8, 4, fake, 7, fake, 8, 0, 0, null) == -4
+    assert lib.ff_update_gemm(8, 4, fake, 8, fake, 8, fake, 3, 0, 0, null) == -8
+
+
+def test_workspace_sizes(lib):
+    assert lib.ff_chol_workspace_size(100, 27, 0, 0) == 0
+    assert lib.ff_chol_workspace_size(100, 27, 1, 0) >= 27 * 27 * 8
+    assert lib.ff_chol_workspace_size(10, 27, 2, 0) >= 10 * 10 * 8
+    assert lib.ff_trisolve_workspace_size(130, 0) >= 3 * 64 * 64 * 8
+    assert lib.ff_solve_workspace_size(1000, 64, 4, 1) > lib.ff_solve_workspace_size(1000, 64, 1, 1)
+    assert lib.ff_solve_workspace_size(0, 64, 4, 1) == 0
