@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "fastfact.h"
@@ -44,6 +46,89 @@ size_t diag_ws_bytes(int64_t n, int64_t s, int dtype) {
         if (e_ != hipSuccess) return FF_ERR_HIP;      \
     } while (0)
 
+// ---------------------------------------------------------------- side streams
+// Lookahead runs the diagonal factorisation and panel solve of block k+1 on a
+// second stream while the rest of update k runs on the caller's stream.  Side
+// streams (default priority, non-blocking) are created once per device and
+// pooled; ordering between the two streams is carried by events created per
+// call, so concurrent calls stay correct even when they share a side stream.
+struct SidePool {
+    std::mutex mu;
+    std::vector<std::pair<int, hipStream_t>> free_list;
+};
+SidePool& side_pool() {
+    static SidePool p;
+    return p;
+}
+hipStream_t acquire_side(int dev) {
+    SidePool& p = side_pool();
+    {
+        std::lock_guard<std::mutex> lk(p.mu);
+        for (size_t i = 0; i < p.free_list.size(); ++i)
+            if (p.free_list[i].first == dev) {
+                hipStream_t s = p.free_list[i].second;
+                p.free_list.erase(p.free_list.begin() + i);
+                return s;
+            }
+    }
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    return s;
+}
+void release_side(int dev, hipStream_t s) {
+    SidePool& p = side_pool();
+    std::lock_guard<std::mutex> lk(p.mu);
+    p.free_list.emplace_back(dev, s);
+}
+
+struct Events {
+    std::vector<hipEvent_t> ev;
+    ~Events() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    hipEvent_t make() {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        ev.push_back(e);
+        return e;
+    }
+};
+
+// ---------------------------------------------------------------- panel solves
+// X T = B for the m x w panel, T upper triangular (see launch_trsm), solved in
+// column chunks of TRSM_MAX when w is wider: chunk [c0, c1) first subtracts the
+// solved columns, X[:, c0:c1] -= X[:, 0:c0] T[0:c0, c0:c1], then is solved with
+// the diagonal block T[c0:c1, c0:c1].  xcol: X column-major (xi = 1, xj = ldx);
+// otherwise X(i, j) = x[j + i*ldx] (rows of X are columns of x).
+template <typename T>
+int trsm_blocked(int m, int w, T* x, int64_t ldx, bool xcol, const T* t, int64_t ldt, bool t_is_rows, int unit,
+                 const int* info, hipStream_t st) {
+    // t_is_rows: T(k, j) = t[j + k*ldt] (T = L^T of a lower factor); else T(k, j) = t[k + j*ldt]
+    const int64_t tk = t_is_rows ? ldt : 1, tj = t_is_rows ? 1 : ldt;
+    const int64_t xi = xcol ? 1 : ldx, xj = xcol ? ldx : 1;
+    for (int c0 = 0; c0 < w; c0 += TRSM_MAX) {
+        const int c1 = std::min(w, c0 + TRSM_MAX);
+        const int wc = c1 - c0;
+        if (c0 > 0) {
+            if (xcol) {
+                // C = X[:, c0:c1] (m x wc), K = c0, Y(j, k) = T(k, c0 + j)
+                const T* ybase = t_is_rows ? t + c0 : t + (int64_t)c0 * ldt;
+                FF_TRY(launch_update<T>(m, wc, c0, x + (int64_t)c0 * ldx, ldx, x, ldx, ybase, ldt, t_is_rows, false,
+                                        0, info, st));
+            } else {
+                // transposed form on the stored matrix x (rows [c0, c1) of x, all m columns):
+                // x[c0 + i', j'] -= sum_k T(k, c0 + i') x[k, j'];  X operand (i', k) = T(k, c0 + i')
+                if (!t_is_rows) return FF_ERR_UNSUPPORTED;
+                FF_TRY(launch_update<T>(wc, m, c0, x + c0, ldx, t + c0, ldt, x, ldx, false, false, 0, info, st));
+            }
+        }
+        T* xc = xcol ? x + (int64_t)c0 * ldx : x + c0;
+        const T* tc = t + (int64_t)c0 * tk + (int64_t)c0 * tj;
+        FF_TRY(launch_trsm<T>(m, wc, xc, xi, xj, tc, tk, tj, unit, info, st));
+    }
+    return 0;
+}
+
 // ---------------------------------------------------------------- Cholesky
 // Algorithm 1 as a block schedule: block k covers columns c0 = k*s .. c0+w-1;
 // the diagonal factorisation and the panel solve form those columns from the
@@ -51,58 +136,128 @@ size_t diag_ws_bytes(int64_t n, int64_t s, int dtype) {
 // subtracted from the trailing square (the update of the paper's conditional,
 // which fires floor((n-1)/s) times).
 template <typename S>
-int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, double* ws64, int* info,
-                 int col_base, hipStream_t st);
+int chol_diag(int w, S* A11, int64_t lda, int dtype, double* ws64, int* info, int col_base, hipStream_t st);
 
-int chol_diag_f64(int w, double* A11, int64_t lda, int* info, int col_base, hipStream_t st) {
-    if (w <= DIAG_MAX) {
-        FF_TRY(launch_potrf_diag<double>(w, A11, lda, nullptr, info, col_base, st));
-        return 0;
+template <typename S>
+int chol_panel(int n, int c0, int w, S* A, int64_t lda, int dtype, double* ws64, int* info, int col_base,
+               hipStream_t st) {
+    S* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
+    int rc = chol_diag<S>(w, A11, lda, dtype, ws64, info, col_base + c0, st);
+    if (rc) return rc;
+    const int m = n - c0 - w;
+    if (m > 0) {
+        S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
+        // L21 = A21 L11^-T: x T = b with T(k, j) = L11(j, k)
+        rc = trsm_blocked<S>(m, w, A21, lda, true, A11, lda, true, 0, info, st);
     }
-    return chol_blocked<double>(w, INNER_S, A11, lda, FF_F64, 0, nullptr, info, col_base, st);
+    return rc;
+}
+
+// A22 region update: C(i, j) -= sum_k P(i, k) P(j, k) over rows [r0, m) and
+// columns [q0, q1) of the m x m trailing matrix, lower part only.
+template <typename S>
+int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, int q1, int dtype, unsigned flags,
+                const int* info, hipStream_t st) {
+    const int M = m - r0, N = q1 - q0;
+    if (M <= 0 || N <= 0) return 0;
+    S* C = A22 + (int64_t)r0 + (int64_t)q0 * lda;
+    const int shift = q0 - r0;     // global i >= j  <=>  local i' - j' >= q0 - r0
+    if constexpr (sizeof(S) == sizeof(double)) {
+        if ((flags & FF_FLAG_STRASSEN1) && M == N && shift == 0) {
+            FF_TRY(launch_update_syrk_strassen_f64(M, w, reinterpret_cast<double*>(C), lda,
+                                                   reinterpret_cast<const double*>(P + r0), lda, info, st));
+            return 0;
+        }
+        FF_TRY(launch_update<double>(M, N, w, reinterpret_cast<double*>(C), lda,
+                                     reinterpret_cast<const double*>(P + r0), lda,
+                                     reinterpret_cast<const double*>(P + q0), lda, true, true, shift, info, st));
+    } else {
+        if (dtype == FF_BF16)
+            FF_TRY(launch_update_bf16(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, shift, info, st));
+        else
+            FF_TRY(launch_update<float>(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, true, shift, info, st));
+    }
+    return 0;
 }
 
 template <typename S>
 int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, double* ws64, int* info,
-                 int col_base, hipStream_t st) {
+                 int col_base, hipStream_t st, bool lookahead) {
+    if (n <= 0) return 0;
+    hipStream_t side = nullptr;
+    int dev = 0;
+    Events evs;
+    if (lookahead && n > s) {
+        if (hipGetDevice(&dev) != hipSuccess) return FF_ERR_HIP;
+        side = acquire_side(dev);
+        if (!side) return FF_ERR_HIP;
+    }
+    int rc = 0;
+    if (!side) {
+        for (int c0 = 0; c0 < n && !rc; c0 += s) {
+            const int w = std::min(s, n - c0);
+            const int m = n - c0 - w;
+            rc = chol_panel<S>(n, c0, w, A, lda, dtype, ws64, info, col_base, st);
+            if (rc || m <= 0) break;
+            S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
+            S* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
+            rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, m, dtype, flags, info, st);
+        }
+        return rc;
+    }
+    // lookahead schedule
+    hipEvent_t e0 = evs.make();
+    if (!e0) { release_side(dev, side); return FF_ERR_HIP; }
+    auto fail = [&](int code) { release_side(dev, side); return code; };
+    if (hipEventRecord(e0, st) != hipSuccess || hipStreamWaitEvent(side, e0, 0) != hipSuccess) return fail(FF_ERR_HIP);
+    rc = chol_panel<S>(n, 0, std::min(s, n), A, lda, dtype, ws64, info, col_base, side);
+    if (rc) return fail(rc);
+    hipEvent_t ep = evs.make();
+    if (!ep || hipEventRecord(ep, side) != hipSuccess || hipStreamWaitEvent(st, ep, 0) != hipSuccess)
+        return fail(FF_ERR_HIP);
     for (int c0 = 0; c0 < n; c0 += s) {
         const int w = std::min(s, n - c0);
         const int m = n - c0 - w;
-        S* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
-        if constexpr (sizeof(S) == sizeof(double)) {
-            int rc = chol_diag_f64(w, reinterpret_cast<double*>(A11), lda, info, col_base + c0, st);
-            if (rc) return rc;
-        } else {
-            if (w <= DIAG_MAX) {
-                FF_TRY(launch_potrf_diag<float>(w, A11, lda, ws64, info, col_base + c0, st));
-            } else {
-                // widen the block, factor it in binary64, round it back
-                FF_TRY(launch_widen_lower<float>(w, A11, lda, ws64, w, st));
-                int rc = chol_diag_f64(w, ws64, w, info, col_base + c0, st);
-                if (rc) return rc;
-                FF_TRY(launch_narrow_lower<float>(w, ws64, w, A11, lda, st));
-            }
-        }
         if (m <= 0) break;
         S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
         S* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
-        // L21 = A21 L11^-T: X T = B with T(k, j) = L11(j, k)
-        FF_TRY(launch_trsm<S>(m, w, A21, 1, lda, A11, lda, 1, 0, info, st));
-        if constexpr (sizeof(S) == sizeof(double)) {
-            if (flags & FF_FLAG_STRASSEN1)
-                FF_TRY(launch_update_syrk_strassen_f64(m, w, reinterpret_cast<double*>(A22), lda,
-                                                       reinterpret_cast<const double*>(A21), lda, info, st));
-            else
-                FF_TRY(launch_update_syrk<double>(m, w, reinterpret_cast<double*>(A22), lda,
-                                                  reinterpret_cast<const double*>(A21), lda, info, st));
-        } else {
-            if (dtype == FF_BF16)
-                FF_TRY(launch_update_syrk_bf16(m, w, A22, lda, A21, lda, info, st));
-            else
-                FF_TRY(launch_update_syrk<float>(m, w, A22, lda, A21, lda, info, st));
-        }
+        const int wn = std::min(s, m);        // width of the next block
+        // 1) the next block's columns of the update, then hand them to the side stream
+        rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, wn, dtype, flags & ~FF_FLAG_STRASSEN1, info, st);
+        if (rc) return fail(rc);
+        hipEvent_t en = evs.make();
+        if (!en || hipEventRecord(en, st) != hipSuccess || hipStreamWaitEvent(side, en, 0) != hipSuccess)
+            return fail(FF_ERR_HIP);
+        rc = chol_panel<S>(n, c0 + w, wn, A, lda, dtype, ws64, info, col_base, side);
+        if (rc) return fail(rc);
+        hipEvent_t ep2 = evs.make();
+        if (!ep2 || hipEventRecord(ep2, side) != hipSuccess) return fail(FF_ERR_HIP);
+        // 2) the rest of the update, concurrently with the next panel
+        rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, st);
+        if (rc) return fail(rc);
+        if (hipStreamWaitEvent(st, ep2, 0) != hipSuccess) return fail(FF_ERR_HIP);
     }
+    release_side(dev, side);
     return 0;
+}
+
+template <typename S>
+int chol_diag(int w, S* A11, int64_t lda, int dtype, double* ws64, int* info, int col_base, hipStream_t st) {
+    if (w <= LDS_DIAG_MAX) {
+        FF_TRY(launch_potrf_diag<S>(w, A11, lda, info, col_base, st));
+        return 0;
+    }
+    if constexpr (sizeof(S) == sizeof(double)) {
+        return chol_blocked<double>(w, LDS_DIAG_MAX, reinterpret_cast<double*>(A11), lda, FF_F64, 0, nullptr, info,
+                                    col_base, st, false);
+    } else {
+        // widen the block, factor it in binary64, round it back
+        FF_TRY(launch_widen_lower<float>(w, A11, lda, ws64, w, st));
+        int rc = chol_blocked<double>(w, LDS_DIAG_MAX, ws64, w, FF_F64, 0, nullptr, info, col_base, st, false);
+        if (rc) return rc;
+        FF_TRY(launch_narrow_lower<float>(w, ws64, w, A11, lda, st));
+        return 0;
+    }
 }
 
 // ---------------------------------------------------------------- LU
@@ -113,7 +268,7 @@ int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, 
         const int w = std::min(s, n - c0);
         const int m = n - c0 - w;
         double* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
-        if (w <= DIAG_MAX) {
+        if (w <= GETRF_DIAG_MAX) {
             FF_TRY(launch_getrf_diag(w, A11, lda, info, col_base + c0, st));
         } else {
             int rc = lu_blocked(w, INNER_S, A11, lda, 0, info, col_base + c0, st);
@@ -124,14 +279,16 @@ int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, 
         double* A12 = A + (int64_t)c0 + (int64_t)(c0 + w) * lda;
         double* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
         // L21 U11 = A21: T(k, j) = U11(k, j) = A11[k + j*lda]
-        FF_TRY(launch_trsm<double>(m, w, A21, 1, lda, A11, 1, lda, 0, info, st));
+        int rc = trsm_blocked<double>(m, w, A21, lda, true, A11, lda, false, 0, info, st);
+        if (rc) return rc;
         // L11 U12 = A12  <=>  U12^T L11^T = A12^T: rows of X are columns of A12,
         // T(k, j) = L11(j, k) with unit diagonal
-        FF_TRY(launch_trsm<double>(m, w, A12, lda, 1, A11, lda, 1, 1, info, st));
+        rc = trsm_blocked<double>(m, w, A12, lda, false, A11, lda, true, 1, info, st);
+        if (rc) return rc;
         if (flags & FF_FLAG_STRASSEN1)
             FF_TRY(launch_update_gemm_strassen_f64(m, w, A22, lda, A21, lda, A12, lda, info, st));
         else
-            FF_TRY(launch_update_gemm<double>(m, w, A22, lda, A21, lda, A12, lda, info, st));
+            FF_TRY(launch_update<double>(m, m, w, A22, lda, A21, lda, A12, lda, false, false, 0, info, st));
     }
     return 0;
 }
@@ -189,7 +346,8 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
     if (!w_is_factored) {
         FF_TRY(launch_copy_lower_from_f64<S>(n, A64, lda, W, ldw, st));
         FF_TRY(launch_set_int(w.d_info, 0, st));
-        int rc = chol_blocked<S>(n, s, W, ldw, dtype, flags, w.diag64, w.d_info, 0, st);
+        int rc = chol_blocked<S>(n, s, W, ldw, dtype, flags, w.diag64, w.d_info, 0, st,
+                                 !(flags & FF_FLAG_NO_LOOKAHEAD));
         if (rc) return rc;
         int info = 0;
         FF_TRY(hipMemcpyAsync(&info, w.d_info, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -286,10 +444,12 @@ int chol_factor(int64_t n, int64_t s, void* A, int64_t lda, int dtype, unsigned 
     if (launch_set_int(d_info, 0, st) != hipSuccess) return FF_ERR_HIP;
     if (n == 0) return 0;
     const int si = (int)std::min<int64_t>(s, n);
+    const bool la = !(flags & FF_FLAG_NO_LOOKAHEAD);
     if (dtype == FF_F64)
-        return chol_blocked<double>((int)n, si, static_cast<double*>(A), lda, dtype, flags, nullptr, d_info, 0, st);
+        return chol_blocked<double>((int)n, si, static_cast<double*>(A), lda, dtype, flags, nullptr, d_info, 0, st,
+                                    la);
     return chol_blocked<float>((int)n, si, static_cast<float*>(A), lda, dtype, flags, static_cast<double*>(ws), d_info,
-                               0, st);
+                               0, st, la);
 }
 
 size_t ff_lu_workspace_size(int64_t n, int64_t s, int dtype, unsigned flags) {
@@ -400,19 +560,21 @@ int ff_update_syrk(int64_t m, int64_t w, void* C, int64_t ldc, const void* P, in
     if (m == 0 || w == 0) return 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e;
+    const int mi = (int)m, wi = (int)w;
     if (dtype == FF_F64) {
+        const double* Pd = static_cast<const double*>(P);
         if (flags & FF_FLAG_STRASSEN1)
-            e = launch_update_syrk_strassen_f64((int)m, (int)w, static_cast<double*>(C), ldc,
-                                                static_cast<const double*>(P), ldp, nullptr, st);
+            e = launch_update_syrk_strassen_f64(mi, wi, static_cast<double*>(C), ldc, Pd, ldp, nullptr, st);
         else
-            e = launch_update_syrk<double>((int)m, (int)w, static_cast<double*>(C), ldc, static_cast<const double*>(P),
-                                           ldp, nullptr, st);
-    } else if (dtype == FF_F32) {
-        e = launch_update_syrk<float>((int)m, (int)w, static_cast<float*>(C), ldc, static_cast<const float*>(P), ldp,
+            e = launch_update<double>(mi, mi, wi, static_cast<double*>(C), ldc, Pd, ldp, Pd, ldp, true, true, 0,
                                       nullptr, st);
+    } else if (dtype == FF_F32) {
+        const float* Pf = static_cast<const float*>(P);
+        e = launch_update<float>(mi, mi, wi, static_cast<float*>(C), ldc, Pf, ldp, Pf, ldp, true, true, 0, nullptr,
+                                 st);
     } else {
-        e = launch_update_syrk_bf16((int)m, (int)w, static_cast<float*>(C), ldc, static_cast<const float*>(P), ldp,
-                                    nullptr, st);
+        const float* Pf = static_cast<const float*>(P);
+        e = launch_update_bf16(mi, mi, wi, static_cast<float*>(C), ldc, Pf, ldp, Pf, ldp, true, 0, nullptr, st);
     }
     return e == hipSuccess ? 0 : FF_ERR_HIP;
 }
@@ -440,11 +602,12 @@ int ff_update_gemm(int64_t m, int64_t w, void* C, int64_t ldc, const void* X, in
                                                 static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy,
                                                 nullptr, st);
         else
-            e = launch_update_gemm<double>((int)m, (int)w, static_cast<double*>(C), ldc, static_cast<const double*>(X),
-                                           ldx, static_cast<const double*>(Y), ldy, nullptr, st);
+            e = launch_update<double>((int)m, (int)m, (int)w, static_cast<double*>(C), ldc,
+                                      static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy, false,
+                                      false, 0, nullptr, st);
     } else {
-        e = launch_update_gemm<float>((int)m, (int)w, static_cast<float*>(C), ldc, static_cast<const float*>(X), ldx,
-                                      static_cast<const float*>(Y), ldy, nullptr, st);
+        e = launch_update<float>((int)m, (int)m, (int)w, static_cast<float*>(C), ldc, static_cast<const float*>(X), ldx,
+                                 static_cast<const float*>(Y), ldy, false, false, 0, nullptr, st);
     }
     return e == hipSuccess ? 0 : FF_ERR_HIP;
 }

@@ -5,22 +5,27 @@
 
 namespace ff {
 
-// Largest diagonal block the single-workgroup diagonal kernels take; larger
-// blocks are factored recursively by the host driver.
-constexpr int DIAG_MAX = 512;
+// Largest diagonal block the single-workgroup diagonal kernels take (the
+// Cholesky one keeps the block in LDS); larger blocks are factored recursively
+// by the host driver.  TRSM_MAX bounds the columns of one panel-solve launch;
+// wider panels are solved in column chunks by the host.
+constexpr int LDS_DIAG_MAX = 192;
+constexpr int GETRF_DIAG_MAX = 512;
+constexpr int TRSM_MAX = 192;
 
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
 
 // Trailing updates (update.hip).
-// `info` (may be null): the kernels do nothing when *info != 0.
+// C(i, j) -= sum_k X(i, k) Y(j, k) for i < M, j < N; X column-major M x K;
+// Y(j, k) = Y[j + k*ldy] when yrows, else Y[k + j*ldy]; with `lower` only
+// entries with i - j >= shift are written.  `info` (may be null): the kernels do
+// nothing when *info != 0.
 template <typename T>
-hipError_t launch_update_syrk(int m, int w, T* C, int64_t ldc, const T* P, int64_t ldp, const int* info,
-                              hipStream_t st);
-template <typename T>
-hipError_t launch_update_gemm(int m, int w, T* C, int64_t ldc, const T* X, int64_t ldx,
-                              const T* Y, int64_t ldy, const int* info, hipStream_t st);
-hipError_t launch_update_syrk_bf16(int m, int w, float* C, int64_t ldc, const float* P, int64_t ldp,
-                                   const int* info, hipStream_t st);
+hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
+                         bool yrows, bool lower, int shift, const int* info, hipStream_t st);
+// bfloat16-operand form (yrows only), binary32 storage and accumulation.
+hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const float* X, int64_t ldx,
+                              const float* Y, int64_t ldy, bool lower, int shift, const int* info, hipStream_t st);
 // One Strassen level over 2x2 super-tiles of output tiles (strassen.hip).
 hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc, const double* P, int64_t ldp,
                                            const int* info, hipStream_t st);
@@ -29,7 +34,7 @@ hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc,
 
 // Diagonal factorisations and panel solves (panel.hip).
 template <typename S>
-hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, double* ws, int* info, int col_base, hipStream_t st);
+hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, int* info, int col_base, hipStream_t st);
 hipError_t launch_getrf_diag(int w, double* a, int64_t ld, int* info, int col_base, hipStream_t st);
 template <typename T>
 hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, int64_t tk, int64_t tj,

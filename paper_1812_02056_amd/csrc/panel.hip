@@ -27,7 +27,7 @@ namespace {
 
 constexpr int PNT = 256;     // threads of the single-workgroup diagonal kernels
 constexpr int PB = 16;       // panel width
-constexpr int MAXR = DIAG_MAX / PNT;   // rows per thread in the diagonal kernels
+constexpr int MAXR = GETRF_DIAG_MAX / PNT;   // rows per thread in getrf_diag_kernel
 
 __global__ void set_int_kernel(int* p, int v) { if (threadIdx.x == 0) *p = v; }
 
@@ -63,108 +63,6 @@ __device__ __forceinline__ void tile_update_f64(double* a, int64_t ld, const dou
         const int gj = q0 + acc_traits<double>::col(lane, r);
         if (gi < rmax && gj < qmax && (!lower_only || gi >= gj))
             a[(int64_t)gi + (int64_t)gj * ld] -= (acc0[r] + acc1[r]);
-    }
-}
-
-// Cholesky of the w x w diagonal block (w <= DIAG_MAX).  S is the storage type;
-// for float storage the lower triangle is widened into ws (w x w, ld = w).
-template <typename S>
-__global__ __launch_bounds__(PNT)
-void potrf_diag_kernel(int w, S* blk, int64_t ldb, double* ws, int* info, int col_base)
-{
-    if (*info != 0) return;
-    __shared__ double top[PB][PB + 1];
-    __shared__ int fail;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    double* a;
-    int64_t ld;
-    if constexpr (sizeof(S) == sizeof(double)) {
-        a = reinterpret_cast<double*>(blk);
-        ld = ldb;
-    } else {
-        a = ws;
-        ld = w;
-        for (int j = 0; j < w; ++j)
-            for (int i = j + tid; i < w; i += PNT) a[i + (int64_t)j * ld] = (double)blk[i + (int64_t)j * ldb];
-    }
-    if (tid == 0) fail = 0;
-    __syncthreads();
-
-    for (int c = 0; c < w; c += PB) {
-        const int nbc = min(PB, w - c);
-        const int pe = c + nbc;
-        if (c > 0) {
-            const int ntile = (w - c + 15) / 16;
-            for (int t = wave; t < ntile; t += PNT / 64)
-                tile_update_f64(a, ld, a, ld, 1, c + 16 * t, c, c, w, pe, true, lane);  // U(k,j) = L(j,k)
-        }
-        __syncthreads();
-        // factor panel columns c..pe-1 over rows c..w-1; thread owns rows c+tid, c+tid+PNT, ...
-        double p[MAXR][PB];
-#pragma unroll
-        for (int q = 0; q < MAXR; ++q) {
-            const int i = c + tid + q * PNT;
-#pragma unroll
-            for (int j = 0; j < PB; ++j)
-                p[q][j] = (i < w && j < nbc && (i - c) >= j) ? a[i + (int64_t)(c + j) * ld] : 0.0;
-        }
-bool failed = false;
-#pragma unroll
-        for (int j = 0; j < PB; ++j) {
-            if (j < nbc && !failed) {
-                if (tid == j) {
-                    const double d = p[0][j];
-                    if (!(d > 0.0)) {
-                        fail = 1;
-                        *info = col_base + c + j + 1;
-                    } else {
-                        p[0][j] = sqrt(d);
-                        top[j][j] = p[0][j];
-                    }
-                }
-                __syncthreads();
-                failed = fail != 0;
-                if (!failed) {
-                    const double ljj = top[j][j];
-#pragma unroll
-                    for (int q = 0; q < MAXR; ++q) {
-                        const int li = tid + q * PNT;
-                        if (c + li < w && li > j) {
-                            p[q][j] = p[q][j] / ljj;
-                            if (li < PB) top[li][j] = p[q][j];
-                        }
-                    }
-                    __syncthreads();
-#pragma unroll
-                    for (int q = 0; q < MAXR; ++q) {
-                        const int li = tid + q * PNT;
-                        if (c + li < w && li > j) {
-                            const double lij = p[q][j];
-#pragma unroll
-                            for (int k = 0; k < PB; ++k)
-                                if (k > j && k < nbc && k <= li) p[q][k] -= lij * top[k][j];
-                        }
-                    }
-                }
-            }
-        }
-        if (failed) return;
-#pragma unroll
-        for (int q = 0; q < MAXR; ++q) {
-            const int li = tid + q * PNT;
-            const int i = c + li;
-            if (i < w) {
-#pragma unroll
-                for (int j = 0; j < PB; ++j)
-                    if (j < nbc && li >= j) a[i + (int64_t)(c + j) * ld] = p[q][j];
-            }
-        }
-        __syncthreads();
-    }
-    if constexpr (sizeof(S) != sizeof(double)) {
-        for (int j = 0; j < w; ++j)
-            for (int i = j + tid; i < w; i += PNT) blk[i + (int64_t)j * ldb] = (S)a[i + (int64_t)j * ld];
     }
 }
 
@@ -265,80 +163,241 @@ bool failed = false;
     }
 }
 
-// Triangular solve X T = B in place (B overwritten by X), T upper triangular
-// w x w: x_j = (b_j - sum_{k<j} x_k T(k,j)) / T(j,j) (no division if unit).
-// X(i, j) = x[i*xi + j*xj] (m rows), T(k, j) = t[k*tk + j*tj].
-// Each wave owns 16 rows and walks the w columns in panels of 16: an MFMA product
-// brings the panel up to date with the solved columns left of it, then 16 lanes
-// finish the panel by substitution, one row each.
+
+// ---------------------------------------------------------------------------
+// 16 x 16 tile primitives in the MFMA output layout: for the transposed tile
+// D'[a][b] = M(b, a), lane l holds row b = l % 16 and, in register r, column
+// a = acc_traits<T>::col(l, r).  These run on one wave.
+
+template <typename T>
+__device__ __forceinline__ int tcol(int lane, int r) { return acc_traits<T>::col(lane, r); }
+// lane group and register that hold column a
+template <typename T> __device__ __forceinline__ int grp_of(int a);
+template <typename T> __device__ __forceinline__ int reg_of(int a);
+template <> __device__ __forceinline__ int grp_of<double>(int a) { return a & 3; }
+template <> __device__ __forceinline__ int reg_of<double>(int a) { return a >> 2; }
+template <> __device__ __forceinline__ int grp_of<float>(int a) { return a >> 2; }
+template <> __device__ __forceinline__ int reg_of<float>(int a) { return a & 3; }
+
+// Row-wise substitution x * U = v for a 16 x 16 upper-triangular U whose element
+// (k, a) is u[a + 16 k] (LDS); v holds the tile in the layout above and is
+// overwritten by x:  x_a = (v_a - sum_{k<a} x_k U(k, a)) / U(a, a), the
+// subtractions applied in increasing k.
+template <typename T, typename V>
+__device__ __forceinline__ void tile_rsolve_upper(V& v, const T* u, bool unit, int lane) {
+    const int b = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+        const int ga = grp_of<T>(a), ra = reg_of<T>(a);
+        T xa = __shfl(v[ra], b + 16 * ga);
+        if (!unit) xa = xa / u[a + 16 * a];
+        if (g == ga) v[ra] = xa;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = tcol<T>(lane, r);
+            if (c > a) v[r] -= xa * u[c + 16 * a];
+        }
+    }
+}
+
+// In-register Cholesky of a 16 x 16 tile (lower part meaningful).  Returns the
+// first column j (0-based) whose pivot was not > 0, or -1.  Every lane computes
+// the same pivots, so the result is uniform across the wave.
+__device__ __forceinline__ int tile_potrf(d4_t& v, int lane) {
+    const int b = lane & 15;
+    int bad = -1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int gj = grp_of<double>(j), rj = reg_of<double>(j);
+        double colj = __shfl(v[rj], b + 16 * gj);     // M(b, j)
+        const double d = __shfl(colj, j);              // M(j, j)
+        if (!(d > 0.0) && bad < 0) bad = j;
+        const double ljj = sqrt(d);
+        const double lbj = (b == j) ? ljj : colj / ljj;
+        if ((lane >> 4) == gj && b >= j) v[rj] = lbj;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = tcol<double>(lane, r);
+            const double lcj = __shfl(v[rj], c + 16 * gj);   // L(c, j) (lane c of group gj)
+            if (c > j && b >= c) v[r] -= lbj * lcj;
+        }
+    }
+    return bad;
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of the w x w diagonal block (w <= LDS_DIAG_MAX) in ONE workgroup of
+// 1024 threads.  The lower triangle is held in LDS as 16 x 16 tiles (tile (i, j),
+// i >= j, at index i(i+1)/2 + j, element (r, c) at r + 16 c) padded with the
+// identity beyond w, and factored right-looking over tile columns: one wave
+// factors the diagonal tile, the waves solve the tiles below it, then update the
+// trailing tiles with 16 x 16 x 16 MFMA products.  S is the storage type; the
+// arithmetic is binary64 in every case.
+constexpr int DT = 16;
+constexpr int LDS_TMAX = LDS_DIAG_MAX / DT;
+constexpr int LDS_NTILE = LDS_TMAX * (LDS_TMAX + 1) / 2;
+constexpr int PT = 1024;
+
+__device__ __forceinline__ int ltile(int i, int j) { return (i * (i + 1) / 2 + j) * 256; }
+
+template <typename S>
+__global__ __launch_bounds__(PT)
+void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int col_base)
+{
+    if (*info != 0) return;
+    __shared__ double tl[LDS_NTILE * 256];
+    __shared__ int fail;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int T = (w + DT - 1) / DT;
+    const int ntile = T * (T + 1) / 2;
+    if (tid == 0) fail = -1;
+    for (int e = tid; e < ntile * 256; e += PT) {
+        const int t = e >> 8, rc = e & 255;
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        const int j = t - i * (i + 1) / 2;
+        const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
+        double v;
+        if (gr < w && gc < w) v = (gr >= gc) ? (double)blk[gr + (int64_t)gc * ldb] : 0.0;
+        else v = (gr == gc) ? 1.0 : 0.0;
+        tl[e] = v;
+    }
+    __syncthreads();
+    const int b = lane & 15;
+    for (int kt = 0; kt < T; ++kt) {
+        double* dtile = tl + ltile(kt, kt);
+        if (wave == 0) {
+            d4_t v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = dtile[b + 16 * tcol<double>(lane, r)];
+            const int bad = tile_potrf(v, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dtile[b + 16 * tcol<double>(lane, r)] = v[r];
+            if (bad >= 0 && lane == 0) {
+                fail = bad;
+                if (DT * kt + bad < w) *info = col_base + DT * kt + bad + 1;
+            }
+        }
+        __syncthreads();
+        if (fail >= 0) return;
+        // tiles below: X L_kk^T = A  <=>  x * U = v with U(k, a) = L_kk(a, k) = dtile[a + 16 k]
+        for (int it = kt + 1 + wave; it < T; it += PT / 64) {
+            double* t = tl + ltile(it, kt);
+            d4_t v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = t[b + 16 * tcol<double>(lane, r)];
+            tile_rsolve_upper<double>(v, dtile, false, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t[b + 16 * tcol<double>(lane, r)] = v[r];
+        }
+        __syncthreads();
+        // trailing tiles (it, jt), kt < jt <= it: A -= L_it,kt L_jt,kt^T
+        const int nr = T - kt - 1;
+        const int npair = nr * (nr + 1) / 2;
+        for (int p = wave; p < npair; p += PT / 64) {
+            int ii = 0;
+            while ((ii + 1) * (ii + 2) / 2 <= p) ++ii;
+            const int jj = p - ii * (ii + 1) / 2;
+            const int it = kt + 1 + ii, jt = kt + 1 + jj;
+            double* c = tl + ltile(it, jt);
+            const double* li = tl + ltile(it, kt);
+            const double* lj = tl + ltile(jt, kt);
+            d4_t acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = c[b + 16 * tcol<double>(lane, r)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = tcol<double>(lane, i);
+                acc = mfma_f64(-lj[b + 16 * k], li[b + 16 * k], acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c[b + 16 * tcol<double>(lane, r)] = acc[r];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < ntile * 256; e += PT) {
+        const int t = e >> 8, rc = e & 255;
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        const int j = t - i * (i + 1) / 2;
+        const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
+        if (gr < w && gc < w && gr >= gc) blk[gr + (int64_t)gc * ldb] = (S)tl[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solve X T = B in place (X overwrites B), T upper triangular w x w
+// (w <= TRSM_MAX): x_j = (b_j - sum_{k<j} x_k T(k, j)) / T(j, j), no division
+// when unit.  X(i, j) = x[i*xi + j*xj] (m rows), T(k, j) = t[k*tk + j*tj].
+// T's upper tiles are staged in LDS (tile (j, t), j <= t, at index t(t+1)/2 + j,
+// element (k, a) = T(16j + k, 16t + a) at a + 16 k).  Each wave owns 16 rows,
+// kept in registers as 16-column tiles, and works right-looking: substitute
+// within tile column j, then subtract its contribution from the later tile
+// columns with MFMA products (K = 16).
+constexpr int TRSM_TMAX = TRSM_MAX / DT;
+
 template <typename T>
 __global__ __launch_bounds__(256)
-void trsm_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, int64_t tk, int64_t tj,
-                 int unit, const int* info)
+void trsm_reg_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* __restrict__ t, int64_t tk,
+                     int64_t tj, int unit, const int* info)
 {
     if (info && *info != 0) return;
     typedef acc_traits<T> AT;
     typedef typename AT::vec V;
-    __shared__ T tile[4][PB][PB + 1];
-    __shared__ T tdg[4][PB][PB + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = (blockIdx.x * 4 + wave) * PB;
+    __shared__ T tu[TRSM_TMAX * (TRSM_TMAX + 1) / 2 * 256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int Tn = (w + DT - 1) / DT;
+    const int ntile = Tn * (Tn + 1) / 2;
+    for (int e = tid; e < ntile * 256; e += 256) {
+        const int q = e >> 8, ak = e & 255;
+        int tt = 0;
+        while ((tt + 1) * (tt + 2) / 2 <= q) ++tt;
+        const int jj = q - tt * (tt + 1) / 2;
+        const int gk = DT * jj + (ak >> 4), ga = DT * tt + (ak & 15);
+        T v;
+        if (gk < w && ga < w) v = (gk <= ga) ? t[(int64_t)gk * tk + (int64_t)ga * tj] : T(0);
+        else v = (gk == ga) ? T(1) : T(0);
+        tu[e] = v;
+    }
+    __syncthreads();
+    const int r0 = (blockIdx.x * 4 + wave) * DT;
     if (r0 >= m) return;
-    const int ra = r0 + (lane & 15);
-    const bool rok = ra < m;
-
-    for (int c = 0; c < w; c += PB) {
-        const int nbc = min(PB, w - c);
-        const int qa = c + (lane & 15);
-        const bool qok = qa < w;
-        V acc0 = zero_vec<V>(), acc1 = zero_vec<V>();
-        int k = 0;
-        for (; k + 8 <= c; k += 8) {
-            const int k1 = k + (lane >> 4), k2 = k1 + 4;
-            const T fa1 = qok ? t[(int64_t)k1 * tk + (int64_t)qa * tj] : T(0);
-            const T fb1 = rok ? x[(int64_t)ra * xi + (int64_t)k1 * xj] : T(0);
-            const T fa2 = qok ? t[(int64_t)k2 * tk + (int64_t)qa * tj] : T(0);
-            const T fb2 = rok ? x[(int64_t)ra * xi + (int64_t)k2 * xj] : T(0);
-            acc0 = AT::mfma(fa1, fb1, acc0);
-            acc1 = AT::mfma(fa2, fb2, acc1);
-        }
-        for (; k < c; k += 4) {
-            const int k1 = k + (lane >> 4);
-            const T fa1 = (qok && k1 < c) ? t[(int64_t)k1 * tk + (int64_t)qa * tj] : T(0);
-            const T fb1 = (rok && k1 < c) ? x[(int64_t)ra * xi + (int64_t)k1 * xj] : T(0);
-            acc0 = AT::mfma(fa1, fb1, acc0);
-        }
-        // stage the partially reduced panel rows and the diagonal block of T
+    const int b = lane & 15;
+    const int row = r0 + b;
+    const bool rok = row < m;
+    V xr[TRSM_TMAX];
+#pragma unroll
+    for (int q = 0; q < TRSM_TMAX; ++q) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int a = AT::col(lane, r);
-            if (rok && a < nbc)
-                tile[wave][lane & 15][a] = x[(int64_t)ra * xi + (int64_t)(c + a) * xj] - (acc0[r] + acc1[r]);
+            const int col = DT * q + tcol<T>(lane, r);
+            xr[q][r] = (q < Tn && rok && col < w) ? x[(int64_t)row * xi + (int64_t)col * xj] : T(0);
         }
+    }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = lane + 64 * e;
-            const int kk = idx & 15, jj = idx >> 4;
-            if (kk < nbc && jj < nbc && kk <= jj)
-                tdg[wave][kk][jj] = t[(int64_t)(c + kk) * tk + (int64_t)(c + jj) * tj];
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane < 16 && rok) {
-            for (int j = 0; j < nbc; ++j) {
-                T v = tile[wave][lane][j];
-                for (int kq = 0; kq < j; ++kq) v -= tile[wave][lane][kq] * tdg[wave][kq][j];
-                if (!unit) v = v / tdg[wave][j][j];
-                tile[wave][lane][j] = v;
+    for (int jq = 0; jq < TRSM_TMAX; ++jq) {
+        if (jq < Tn) {
+            tile_rsolve_upper<T>(xr[jq], tu + (jq * (jq + 1) / 2 + jq) * 256, unit != 0, lane);
+#pragma unroll
+            for (int q = jq + 1; q < TRSM_TMAX; ++q) {
+                if (q < Tn) {
+                    const T* ut = tu + (q * (q + 1) / 2 + jq) * 256;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = tcol<T>(lane, i);
+                        xr[q] = AT::mfma(-ut[b + 16 * k], xr[jq][i], xr[q]);
+                    }
+                }
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // write the solved panel back: lane group g writes columns g, g+4, ...
-        for (int j = (lane >> 4); j < nbc; j += 4)
-            if (rok) x[(int64_t)ra * xi + (int64_t)(c + j) * xj] = tile[wave][lane & 15][j];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+#pragma unroll
+    for (int q = 0; q < TRSM_TMAX; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int col = DT * q + tcol<T>(lane, r);
+            if (q < Tn && rok && col < w) x[(int64_t)row * xi + (int64_t)col * xj] = xr[q][r];
+        }
     }
 }
 
@@ -350,16 +409,16 @@ hipError_t launch_set_int(int* p, int v, hipStream_t st) {
 }
 
 template <typename S>
-hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, double* ws, int* info, int col_base, hipStream_t st) {
+hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, int* info, int col_base, hipStream_t st) {
     if (w <= 0) return hipSuccess;
-    if (w > DIAG_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((potrf_diag_kernel<S>), dim3(1), dim3(PNT), 0, st, w, blk, ldb, ws, info, col_base);
+    if (w > LDS_DIAG_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((potrf_lds_kernel<S>), dim3(1), dim3(PT), 0, st, w, blk, ldb, info, col_base);
     return hipGetLastError();
 }
 
 hipError_t launch_getrf_diag(int w, double* a, int64_t ld, int* info, int col_base, hipStream_t st) {
     if (w <= 0) return hipSuccess;
-    if (w > DIAG_MAX) return hipErrorInvalidValue;
+    if (w > GETRF_DIAG_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(getrf_diag_kernel, dim3(1), dim3(PNT), 0, st, w, a, ld, info, col_base);
     return hipGetLastError();
 }
@@ -368,14 +427,17 @@ template <typename T>
 hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, int64_t tk, int64_t tj,
                        int unit, const int* info, hipStream_t st) {
     if (m <= 0 || w <= 0) return hipSuccess;
+    if (w > TRSM_MAX) return hipErrorInvalidValue;
     const int grid = (m + 63) / 64;
-    hipLaunchKernelGGL((trsm_kernel<T>), dim3(grid), dim3(256), 0, st, m, w, x, xi, xj, t, tk, tj, unit, info);
+    hipLaunchKernelGGL((trsm_reg_kernel<T>), dim3(grid), dim3(256), 0, st, m, w, x, xi, xj, t, tk, tj, unit, info);
     return hipGetLastError();
 }
 
-template hipError_t launch_potrf_diag<double>(int, double*, int64_t, double*, int*, int, hipStream_t);
-template hipError_t launch_potrf_diag<float>(int, float*, int64_t, double*, int*, int, hipStream_t);
-template hipError_t launch_trsm<double>(int, int, double*, int64_t, int64_t, const double*, int64_t, int64_t, int, const int*, hipStream_t);
-template hipError_t launch_trsm<float>(int, int, float*, int64_t, int64_t, const float*, int64_t, int64_t, int, const int*, hipStream_t);
+template hipError_t launch_potrf_diag<double>(int, double*, int64_t, int*, int, hipStream_t);
+template hipError_t launch_potrf_diag<float>(int, float*, int64_t, int*, int, hipStream_t);
+template hipError_t launch_trsm<double>(int, int, double*, int64_t, int64_t, const double*, int64_t, int64_t, int,
+                                        const int*, hipStream_t);
+template hipError_t launch_trsm<float>(int, int, float*, int64_t, int64_t, const float*, int64_t, int64_t, int,
+                                       const int*, hipStream_t);
 
 }  // namespace ff

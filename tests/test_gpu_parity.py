@@ -306,3 +306,29 @@ def test_chol_solve_resident_factor_reuse():
     Lo, _ = oracle.chol(A)
     assert oracle.fwd_x(host(X2), oracle.chol_solve(Lo, B2)) <= 1e-12
     assert i2["converged"] == 1
+
+
+# --------------------------------------------------------------------------- schedule invariance
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,s", [(1000, 64), (1000, 200), (1300, 256)])
+def test_chol_lookahead_matches_in_order_bitwise(dtype, n, s):
+    """Lookahead only reorders independent work and splits the update into two
+    launches; every element sees the same operations, so the factor is bitwise
+    the same as with the strictly ordered schedule."""
+    A = wl.spd_scaled(n, seed=21)
+    st = torch.float64 if dtype == "f64" else torch.float32
+    A1, A2 = dev(A, dtype=st), dev(A, dtype=st)
+    assert ff.chol_factor(A1, s, dtype=dtype, sync=True) == 0
+    assert ff.chol_factor(A2, s, dtype=dtype, no_lookahead=True, sync=True) == 0
+    assert torch.equal(A1, A2)
+
+
+def test_chol_deterministic_repeat():
+    A = wl.spd_scaled(1500, seed=22)
+    outs = []
+    for _ in range(2):
+        Ad = dev(A)
+        assert ff.chol_factor(Ad, 168, dtype="f64", sync=True) == 0
+        outs.append(Ad)
+    assert torch.equal(outs[0], outs[1])
