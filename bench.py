@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--quick", action="store_true", help="headline only: no LU / Strassen / mixed / CPU legs")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-extras", action="store_true")
-    p.add_argument("--cpu-n", type=int, default=6144)
+    p.add_argument("--cpu-n", type=int, default=12288)
     return p.parse_args()
 
 

@@ -54,6 +54,47 @@ template <typename V> __device__ __forceinline__ V zero_vec() { V v; v[0] = 0; v
 // Round binary32 to bfloat16, nearest with ties to even (the hardware conversion).
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
 
+// Raw buffer access.  A buffer resource covers [base, base + BUF_RECORDS) bytes;
+// a load whose offset lies at or past BUF_RECORDS returns zero and such a store
+// is dropped by the hardware.  Kernels point the resource at the corner of the
+// tile they touch and send out-of-matrix elements to BUF_OOB, which gives masked
+// loads and stores with no branches.  Hosts keep every in-range byte offset
+// below BUF_RECORDS.
+constexpr int BUF_RECORDS = 0x7FFFFFF0;
+constexpr int BUF_OOB = 0x7FFFFFF0;
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, BUF_RECORDS, 0x00020000);
+}
+// off: per-lane byte offset; soff: wave-uniform byte offset (added to off);
+// AUX: cache policy (2 = non-temporal, for data streamed once).
+template <typename T, int AUX = 0> struct bufop;
+template <int AUX> struct bufop<double, AUX> {
+    __device__ static __forceinline__ double load(rsrc_t r, int off, int soff) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, AUX));
+    }
+    __device__ static __forceinline__ void store(rsrc_t r, int off, double v, int soff) {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, soff, AUX);
+    }
+};
+template <int AUX> struct bufop<float, AUX> {
+    __device__ static __forceinline__ float load(rsrc_t r, int off, int soff) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, AUX));
+    }
+    __device__ static __forceinline__ void store(rsrc_t r, int off, float v, int soff) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, soff, AUX);
+    }
+};
+template <typename T> __device__ __forceinline__ T buf_load(rsrc_t r, int off, int soff = 0) {
+    return bufop<T, 0>::load(r, off, soff);
+}
+template <typename T> __device__ __forceinline__ void buf_store(rsrc_t r, int off, T v, int soff = 0) {
+    bufop<T, 0>::store(r, off, v, soff);
+}
+constexpr int AUX_NT = 2;
+
 // Grid geometry of the update kernels: output tiles of 128 x 128 grouped into
 // 8 x 8 super-tiles; every XCD of the chip (workgroups are dealt to the 8 XCDs
 // round-robin) works through whole super-tiles so the 16 panel blocks a

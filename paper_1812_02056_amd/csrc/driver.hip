@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -157,7 +158,7 @@ int chol_panel(int n, int c0, int w, S* A, int64_t lda, int dtype, double* ws64,
 // columns [q0, q1) of the m x m trailing matrix, lower part only.
 template <typename S>
 int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, int q1, int dtype, unsigned flags,
-                const int* info, hipStream_t st) {
+                const int* info, hipStream_t st, int reserve = 0) {
     const int M = m - r0, N = q1 - q0;
     if (M <= 0 || N <= 0) return 0;
     S* C = A22 + (int64_t)r0 + (int64_t)q0 * lda;
@@ -170,14 +171,37 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
         }
         FF_TRY(launch_update<double>(M, N, w, reinterpret_cast<double*>(C), lda,
                                      reinterpret_cast<const double*>(P + r0), lda,
-                                     reinterpret_cast<const double*>(P + q0), lda, true, true, shift, info, st));
+                                     reinterpret_cast<const double*>(P + q0), lda, true, true, shift, info, st,
+                                     reserve));
     } else {
         if (dtype == FF_BF16)
-            FF_TRY(launch_update_bf16(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, shift, info, st));
+            FF_TRY(launch_update_bf16(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, shift, info, st, reserve));
         else
-            FF_TRY(launch_update<float>(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, true, shift, info, st));
+            FF_TRY(launch_update<float>(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, true, shift, info, st,
+                                        reserve));
     }
     return 0;
+}
+
+// CUs to keep free for the next block's diagonal factorisation and panel solve
+// while the rest of the update runs: the smallest of 8/16/32/64 whose panel-solve
+// estimate (one 64-row workgroup per free CU per round) fits under the update's
+// estimate, else the one that minimises the longer of the two.
+int lookahead_reserve(int mr, int w, int wn, size_t sz) {
+    const double rate = (sz == sizeof(double) ? 45e12 : 90e12);
+    const double round_us = 20.0, potrf_us = 30.0;
+    const int cus = update_workers(0);
+    int best = 8;
+    double best_t = 1e30;
+    for (int r : {8, 16, 32, 64}) {
+        const double upd_us = (double)mr * (double)mr * (double)w / (rate * (double)(cus - r) / cus) * 1e6;
+        const double rows_blocks = std::ceil((double)mr / 64.0);
+        const double pan_us = potrf_us + std::ceil(rows_blocks / r) * round_us * (wn > 96 ? 1.0 : 0.6);
+        const double t = std::max(upd_us, pan_us);
+        if (pan_us <= upd_us) return r;
+        if (t < best_t) { best_t = t; best = r; }
+    }
+    return best;
 }
 
 template <typename S>
@@ -232,8 +256,10 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         if (rc) return fail(rc);
         hipEvent_t ep2 = evs.make();
         if (!ep2 || hipEventRecord(ep2, side) != hipSuccess) return fail(FF_ERR_HIP);
-        // 2) the rest of the update, concurrently with the next panel
-        rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, st);
+        // 2) the rest of the update, concurrently with the next panel, on all but
+        //    `reserve` CUs so the panel kernels find free CUs
+        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S));
+        rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, st, reserve);
         if (rc) return fail(rc);
         if (hipStreamWaitEvent(st, ep2, 0) != hipSuccess) return fail(FF_ERR_HIP);
     }

@@ -19,13 +19,17 @@ hipError_t launch_set_int(int* p, int v, hipStream_t st);
 // C(i, j) -= sum_k X(i, k) Y(j, k) for i < M, j < N; X column-major M x K;
 // Y(j, k) = Y[j + k*ldy] when yrows, else Y[k + j*ldy]; with `lower` only
 // entries with i - j >= shift are written.  `info` (may be null): the kernels do
-// nothing when *info != 0.
+// nothing when *info != 0.  reserve_cus: number of CUs the (persistent) update
+// leaves free for work on other streams.
 template <typename T>
 hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
-                         bool yrows, bool lower, int shift, const int* info, hipStream_t st);
+                         bool yrows, bool lower, int shift, const int* info, hipStream_t st, int reserve_cus = 0);
 // bfloat16-operand form (yrows only), binary32 storage and accumulation.
 hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const float* X, int64_t ldx,
-                              const float* Y, int64_t ldy, bool lower, int shift, const int* info, hipStream_t st);
+                              const float* Y, int64_t ldy, bool lower, int shift, const int* info, hipStream_t st,
+                              int reserve_cus = 0);
+// Persistent workgroups an update launch uses when reserve_cus CUs are kept free.
+int update_workers(int reserve_cus);
 // One Strassen level over 2x2 super-tiles of output tiles (strassen.hip).
 hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc, const double* P, int64_t ldp,
                                            const int* info, hipStream_t st);
