@@ -38,14 +38,19 @@ __device__ __forceinline__ f4_t mfma_bf16(bf8_t a, bf8_t b, f4_t c) {
 // Accumulator traits: which output column of the 16x16 transposed tile a lane's
 // register r holds (the row is always lane % 16).
 template <typename T> struct acc_traits;
+// col = col_lane(lane) + col_reg(r).
 template <> struct acc_traits<double> {
     typedef d4_t vec;
     __device__ static __forceinline__ int col(int lane, int r) { return 4 * r + (lane >> 4); }
+    __device__ static __forceinline__ int col_lane(int lane) { return lane >> 4; }
+    static constexpr int col_reg(int r) { return 4 * r; }
     __device__ static __forceinline__ vec mfma(double a, double b, vec c) { return mfma_f64(a, b, c); }
 };
 template <> struct acc_traits<float> {
     typedef f4_t vec;
     __device__ static __forceinline__ int col(int lane, int r) { return 4 * (lane >> 4) + r; }
+    __device__ static __forceinline__ int col_lane(int lane) { return 4 * (lane >> 4); }
+    static constexpr int col_reg(int r) { return r; }
     __device__ static __forceinline__ vec mfma(float a, float b, vec c) { return mfma_f32(a, b, c); }
 };
 
@@ -66,6 +71,10 @@ typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, BUF_RECORDS, 0x00020000);
+}
+// Resource covering [base, base + bytes): accesses at or past `bytes` read zero.
+__device__ __forceinline__ rsrc_t make_rsrc_n(const void* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
 }
 // off: per-lane byte offset; soff: wave-uniform byte offset (added to off);
 // AUX: cache policy (2 = non-temporal, for data streamed once).
@@ -95,13 +104,12 @@ template <typename T> __device__ __forceinline__ void buf_store(rsrc_t r, int of
 }
 constexpr int AUX_NT = 2;
 
-// Grid geometry of the update kernels: output tiles of 128 x 128 grouped into
-// 8 x 8 super-tiles; every XCD of the chip (workgroups are dealt to the 8 XCDs
-// round-robin) works through whole super-tiles so the 16 panel blocks a
-// super-tile reads stay in that XCD's L2.
+// Grid geometry of the update kernels: output tiles grouped into square
+// super-tiles (8 x 8 tiles for square tiles); every XCD of the chip (workgroups
+// are dealt to the 8 XCDs round-robin) works through whole super-tiles so the
+// panel blocks a super-tile reads stay in that XCD's L2.
 constexpr int UPD_TILE = 128;
 constexpr int UPD_GROUP = 8;
 constexpr int N_XCD = 8;
-constexpr int UPD_WG_PER_SUPER = UPD_GROUP * UPD_GROUP;
 
 }  // namespace ff

@@ -103,7 +103,7 @@ struct Events {
 // otherwise X(i, j) = x[j + i*ldx] (rows of X are columns of x).
 template <typename T>
 int trsm_blocked(int m, int w, T* x, int64_t ldx, bool xcol, const T* t, int64_t ldt, bool t_is_rows, int unit,
-                 const int* info, hipStream_t st) {
+                 const int* info, hipStream_t st, int max_wg = 0) {
     // t_is_rows: T(k, j) = t[j + k*ldt] (T = L^T of a lower factor); else T(k, j) = t[k + j*ldt]
     const int64_t tk = t_is_rows ? ldt : 1, tj = t_is_rows ? 1 : ldt;
     const int64_t xi = xcol ? 1 : ldx, xj = xcol ? ldx : 1;
@@ -115,7 +115,7 @@ int trsm_blocked(int m, int w, T* x, int64_t ldx, bool xcol, const T* t, int64_t
                 // C = X[:, c0:c1] (m x wc), K = c0, Y(j, k) = T(k, c0 + j)
                 const T* ybase = t_is_rows ? t + c0 : t + (int64_t)c0 * ldt;
                 FF_TRY(launch_update<T>(m, wc, c0, x + (int64_t)c0 * ldx, ldx, x, ldx, ybase, ldt, t_is_rows, false,
-                                        0, info, st));
+                                        0, info, st, 0, max_wg));
             } else {
                 // transposed form on the stored matrix x (rows [c0, c1) of x, all m columns):
                 // x[c0 + i', j'] -= sum_k T(k, c0 + i') x[k, j'];  X operand (i', k) = T(k, c0 + i')
@@ -125,7 +125,7 @@ int trsm_blocked(int m, int w, T* x, int64_t ldx, bool xcol, const T* t, int64_t
         }
         T* xc = xcol ? x + (int64_t)c0 * ldx : x + c0;
         const T* tc = t + (int64_t)c0 * tk + (int64_t)c0 * tj;
-        FF_TRY(launch_trsm<T>(m, wc, xc, xi, xj, tc, tk, tj, unit, info, st));
+        FF_TRY(launch_trsm<T>(m, wc, xc, xi, xj, tc, tk, tj, unit, info, st, max_wg));
     }
     return 0;
 }
@@ -141,7 +141,7 @@ int chol_diag(int w, S* A11, int64_t lda, int dtype, double* ws64, int* info, in
 
 template <typename S>
 int chol_panel(int n, int c0, int w, S* A, int64_t lda, int dtype, double* ws64, int* info, int col_base,
-               hipStream_t st) {
+               hipStream_t st, int max_wg = 0) {
     S* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
     int rc = chol_diag<S>(w, A11, lda, dtype, ws64, info, col_base + c0, st);
     if (rc) return rc;
@@ -149,7 +149,7 @@ int chol_panel(int n, int c0, int w, S* A, int64_t lda, int dtype, double* ws64,
     if (m > 0) {
         S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
         // L21 = A21 L11^-T: x T = b with T(k, j) = L11(j, k)
-        rc = trsm_blocked<S>(m, w, A21, lda, true, A11, lda, true, 0, info, st);
+        rc = trsm_blocked<S>(m, w, A21, lda, true, A11, lda, true, 0, info, st, max_wg);
     }
     return rc;
 }
@@ -184,19 +184,24 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
 }
 
 // CUs to keep free for the next block's diagonal factorisation and panel solve
-// while the rest of the update runs: the smallest of 8/16/32/64 whose panel-solve
-// estimate (one 64-row workgroup per free CU per round) fits under the update's
-// estimate, else the one that minimises the longer of the two.
+// while the rest of the update runs: the smallest of 8/16/32/64 whose panel
+// estimate fits under the update's estimate, else the one that minimises the
+// longer of the two.  Model: the diagonal block costs about diag_us; the panel
+// solve takes 128 rows per free CU per round, a round being two 16-row blocks
+// per SIMD of 4 T(T+1)/2 MFMAs of 64 cycles each (T = 16-column tiles), issued
+// at about half the peak rate.
 int lookahead_reserve(int mr, int w, int wn, size_t sz) {
     const double rate = (sz == sizeof(double) ? 45e12 : 90e12);
-    const double round_us = 20.0, potrf_us = 30.0;
+    const int tiles = (std::min(wn, TRSM_MAX) + 15) / 16;
+    // measured rounds run at about half the MFMA issue rate (dependent MFMA chains)
+    const double round_us = 2.0 * (double)tiles * (tiles + 1) * 4.0 * 64.0 / 2400.0 * (sz == sizeof(double) ? 1.0 : 0.5);
+    const double diag_us = wn <= 64 ? 20.0 : wn <= 128 ? 50.0 : wn <= 192 ? 110.0 : 220.0;
     const int cus = update_workers(0);
     int best = 8;
     double best_t = 1e30;
     for (int r : {8, 16, 32, 64}) {
         const double upd_us = (double)mr * (double)mr * (double)w / (rate * (double)(cus - r) / cus) * 1e6;
-        const double rows_blocks = std::ceil((double)mr / 64.0);
-        const double pan_us = potrf_us + std::ceil(rows_blocks / r) * round_us * (wn > 96 ? 1.0 : 0.6);
+        const double pan_us = diag_us + std::ceil((double)mr / (128.0 * r)) * round_us * (wn > TRSM_MAX ? 1.3 : 1.0);
         const double t = std::max(upd_us, pan_us);
         if (pan_us <= upd_us) return r;
         if (t < best_t) { best_t = t; best = r; }
@@ -252,13 +257,13 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         hipEvent_t en = evs.make();
         if (!en || hipEventRecord(en, st) != hipSuccess || hipStreamWaitEvent(side, en, 0) != hipSuccess)
             return fail(FF_ERR_HIP);
-        rc = chol_panel<S>(n, c0 + w, wn, A, lda, dtype, ws64, info, col_base, side);
+        // 2) the rest of the update, concurrently with the next panel, on all but
+        //    `reserve` CUs; the panel solve's grid is sized to those free CUs
+        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S));
+        rc = chol_panel<S>(n, c0 + w, wn, A, lda, dtype, ws64, info, col_base, side, reserve);
         if (rc) return fail(rc);
         hipEvent_t ep2 = evs.make();
         if (!ep2 || hipEventRecord(ep2, side) != hipSuccess) return fail(FF_ERR_HIP);
-        // 2) the rest of the update, concurrently with the next panel, on all but
-        //    `reserve` CUs so the panel kernels find free CUs
-        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S));
         rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, st, reserve);
         if (rc) return fail(rc);
         if (hipStreamWaitEvent(st, ep2, 0) != hipSuccess) return fail(FF_ERR_HIP);

@@ -20,10 +20,12 @@ hipError_t launch_set_int(int* p, int v, hipStream_t st);
 // Y(j, k) = Y[j + k*ldy] when yrows, else Y[k + j*ldy]; with `lower` only
 // entries with i - j >= shift are written.  `info` (may be null): the kernels do
 // nothing when *info != 0.  reserve_cus: number of CUs the (persistent) update
-// leaves free for work on other streams.
+// leaves free for work on other streams.  max_cus (> 0): the launch sizes its
+// grid for that many CUs (work on a stream that owns only the reserved CUs).
 template <typename T>
 hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
-                         bool yrows, bool lower, int shift, const int* info, hipStream_t st, int reserve_cus = 0);
+                         bool yrows, bool lower, int shift, const int* info, hipStream_t st, int reserve_cus = 0,
+                         int max_cus = 0);
 // bfloat16-operand form (yrows only), binary32 storage and accumulation.
 hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const float* X, int64_t ldx,
                               const float* Y, int64_t ldy, bool lower, int shift, const int* info, hipStream_t st,
@@ -42,7 +44,7 @@ hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, int* info, int col_base
 hipError_t launch_getrf_diag(int w, double* a, int64_t ld, int* info, int col_base, hipStream_t st);
 template <typename T>
 hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, int64_t tk, int64_t tj,
-                       int unit, const int* info, hipStream_t st);
+                       int unit, const int* info, hipStream_t st, int max_wg = 0);
 
 // Solve-side kernels (solve.hip).
 template <typename S>

@@ -181,16 +181,18 @@ template <> __device__ __forceinline__ int reg_of<float>(int a) { return a & 3; 
 
 // Row-wise substitution x * U = v for a 16 x 16 upper-triangular U whose element
 // (k, a) is u[a + 16 k] (LDS); v holds the tile in the layout above and is
-// overwritten by x:  x_a = (v_a - sum_{k<a} x_k U(k, a)) / U(a, a), the
-// subtractions applied in increasing k.
+// overwritten by x:  x_a = (v_a - sum_{k<a} x_k U(k, a)) * (1 / U(a, a)), the
+// subtractions applied in increasing k.  uinv[a] holds 1 / U(a, a) (correctly
+// rounded, so a power-of-two pivot gives the exact quotient); null for a unit
+// diagonal.
 template <typename T, typename V>
-__device__ __forceinline__ void tile_rsolve_upper(V& v, const T* u, bool unit, int lane) {
+__device__ __forceinline__ void tile_rsolve_upper(V& v, const T* u, const T* uinv, int lane) {
     const int b = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
         const int ga = grp_of<T>(a), ra = reg_of<T>(a);
         T xa = __shfl(v[ra], b + 16 * ga);
-        if (!unit) xa = xa / u[a + 16 * a];
+        if (uinv) xa = xa * uinv[a];
         if (g == ga) v[ra] = xa;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -202,8 +204,10 @@ __device__ __forceinline__ void tile_rsolve_upper(V& v, const T* u, bool unit, i
 
 // In-register Cholesky of a 16 x 16 tile (lower part meaningful).  Returns the
 // first column j (0-based) whose pivot was not > 0, or -1.  Every lane computes
-// the same pivots, so the result is uniform across the wave.
-__device__ __forceinline__ int tile_potrf(d4_t& v, int lane) {
+// the same pivots, so the result is uniform across the wave.  The column below
+// the pivot is scaled by the correctly rounded reciprocal of L(j, j), which is
+// also returned in rinv[j] for the solves that follow.
+__device__ __forceinline__ int tile_potrf(d4_t& v, int lane, double (&rinv)[16]) {
     const int b = lane & 15;
     int bad = -1;
 #pragma unroll
@@ -213,7 +217,8 @@ __device__ __forceinline__ int tile_potrf(d4_t& v, int lane) {
         const double d = __shfl(colj, j);              // M(j, j)
         if (!(d > 0.0) && bad < 0) bad = j;
         const double ljj = sqrt(d);
-        const double lbj = (b == j) ? ljj : colj / ljj;
+        rinv[j] = 1.0 / ljj;
+        const double lbj = (b == j) ? ljj : colj * rinv[j];
         if ((lane >> 4) == gj && b >= j) v[rj] = lbj;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -240,27 +245,52 @@ constexpr int PT = 1024;
 
 __device__ __forceinline__ int ltile(int i, int j) { return (i * (i + 1) / 2 + j) * 256; }
 
+// Row i of the packed triangle index t = i(i+1)/2 + j (0 <= j <= i): a float
+// estimate corrected by one step either way (exact for t < 2^20).
+__device__ __forceinline__ int tri_row(int t) {
+    int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    if ((i + 1) * (i + 2) / 2 <= t) ++i;
+    if (i * (i + 1) / 2 > t) --i;
+    return i;
+}
+
+// Tiles staged per thread per batch: that many global loads are in flight at
+// once, where a loop of one element per iteration would wait on each in turn.
+constexpr int STG = 8;
+
 template <typename S>
 __global__ __launch_bounds__(PT)
 void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int col_base)
 {
     if (*info != 0) return;
     __shared__ double tl[LDS_NTILE * 256];
+    __shared__ double dinv[16];       // 1 / L(j, j) of the current diagonal tile
     __shared__ int fail;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int T = (w + DT - 1) / DT;
     const int ntile = T * (T + 1) / 2;
     if (tid == 0) fail = -1;
-    for (int e = tid; e < ntile * 256; e += PT) {
-        const int t = e >> 8, rc = e & 255;
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= t) ++i;
-        const int j = t - i * (i + 1) / 2;
-        const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
-        double v;
-        if (gr < w && gc < w) v = (gr >= gc) ? (double)blk[gr + (int64_t)gc * ldb] : 0.0;
-        else v = (gr == gc) ? 1.0 : 0.0;
-        tl[e] = v;
+    // Stage the lower triangle; thread owns entry rc of tiles tid/256 + (PT/256) u.
+    // Entries outside the block read a valid address and are replaced by the identity.
+    {
+        const int rc = tid & 255;
+        for (int t0 = tid >> 8; t0 < ntile; t0 += (PT / 256) * STG) {
+            double v[STG];
+#pragma unroll
+            for (int u = 0; u < STG; ++u) {
+                const int t = t0 + (PT / 256) * u;
+                const int i = tri_row(t), j = t - i * (i + 1) / 2;
+                const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
+                const bool in = t < ntile && gr < w && gc < w && gr >= gc;
+                const double x = (double)blk[in ? gr + (int64_t)gc * ldb : 0];
+                v[u] = in ? x : (gr == gc ? 1.0 : 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < STG; ++u) {
+                const int t = t0 + (PT / 256) * u;
+                if (t < ntile) tl[t * 256 + rc] = v[u];
+            }
+        }
     }
     __syncthreads();
     const int b = lane & 15;
@@ -270,9 +300,13 @@ void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int co
             d4_t v;
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = dtile[b + 16 * tcol<double>(lane, r)];
-            const int bad = tile_potrf(v, lane);
+            double rinv[16];
+            const int bad = tile_potrf(v, lane, rinv);
 #pragma unroll
             for (int r = 0; r < 4; ++r) dtile[b + 16 * tcol<double>(lane, r)] = v[r];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (lane == j) dinv[j] = rinv[j];
             if (bad >= 0 && lane == 0) {
                 fail = bad;
                 if (DT * kt + bad < w) *info = col_base + DT * kt + bad + 1;
@@ -286,7 +320,7 @@ void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int co
             d4_t v;
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = t[b + 16 * tcol<double>(lane, r)];
-            tile_rsolve_upper<double>(v, dtile, false, lane);
+            tile_rsolve_upper<double>(v, dtile, dinv, lane);
 #pragma unroll
             for (int r = 0; r < 4; ++r) t[b + 16 * tcol<double>(lane, r)] = v[r];
         }
@@ -295,8 +329,7 @@ void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int co
         const int nr = T - kt - 1;
         const int npair = nr * (nr + 1) / 2;
         for (int p = wave; p < npair; p += PT / 64) {
-            int ii = 0;
-            while ((ii + 1) * (ii + 2) / 2 <= p) ++ii;
+            const int ii = tri_row(p);
             const int jj = p - ii * (ii + 1) / 2;
             const int it = kt + 1 + ii, jt = kt + 1 + jj;
             double* c = tl + ltile(it, jt);
@@ -317,9 +350,7 @@ void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int co
     }
     for (int e = tid; e < ntile * 256; e += PT) {
         const int t = e >> 8, rc = e & 255;
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= t) ++i;
-        const int j = t - i * (i + 1) / 2;
+        const int i = tri_row(t), j = t - i * (i + 1) / 2;
         const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
         if (gr < w && gc < w && gr >= gc) blk[gr + (int64_t)gc * ldb] = (S)tl[e];
     }
@@ -327,17 +358,23 @@ void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int co
 
 // ---------------------------------------------------------------------------
 // Triangular solve X T = B in place (X overwrites B), T upper triangular w x w
-// (w <= TRSM_MAX): x_j = (b_j - sum_{k<j} x_k T(k, j)) / T(j, j), no division
-// when unit.  X(i, j) = x[i*xi + j*xj] (m rows), T(k, j) = t[k*tk + j*tj].
+// (w <= TRSM_MAX): row by row, x_j = (b_j - sum_{k<j} x_k T(k, j)) / T(j, j)
+// (unit: no division).  X(i, j) = x[i*xi + j*xj] (m rows), T(k, j) = t[k*tk + j*tj].
 // T's upper tiles are staged in LDS (tile (j, t), j <= t, at index t(t+1)/2 + j,
-// element (k, a) = T(16j + k, 16t + a) at a + 16 k).  Each wave owns 16 rows,
-// kept in registers as 16-column tiles, and works right-looking: substitute
-// within tile column j, then subtract its contribution from the later tile
-// columns with MFMA products (K = 16).
+// element (k, a) = T(16j + k, 16t + a) at a + 16 k), and each diagonal tile is
+// replaced by its inverse, formed once per workgroup by back substitution with
+// the correctly rounded reciprocals of the pivots.  Waves walk 16-row blocks of
+// X, kept in registers as 16-column tiles, right-looking over tile columns:
+// tile j becomes (B_j - sum_{k<j} X_k T_kj) T_jj^-1 (one 16 x 16 x 16 MFMA
+// product with the inverse), then its contribution is subtracted from the later
+// tile columns (MFMA products, K = 16).  With integer data and pivots 1 or 2 the
+// tile inverses are dyadic rationals of fewer than 53 significant bits, so every
+// intermediate stays exact.
 constexpr int TRSM_TMAX = TRSM_MAX / DT;
+constexpr int TRSM_NT = 512;
 
-template <typename T>
-__global__ __launch_bounds__(256)
+template <typename T, bool XCOL>
+__global__ __launch_bounds__(TRSM_NT)
 void trsm_reg_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* __restrict__ t, int64_t tk,
                      int64_t tj, int unit, const int* info)
 {
@@ -345,58 +382,115 @@ void trsm_reg_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* __rest
     typedef acc_traits<T> AT;
     typedef typename AT::vec V;
     __shared__ T tu[TRSM_TMAX * (TRSM_TMAX + 1) / 2 * 256];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ T tinv[TRSM_MAX];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int Tn = (w + DT - 1) / DT;
     const int ntile = Tn * (Tn + 1) / 2;
-    for (int e = tid; e < ntile * 256; e += 256) {
-        const int q = e >> 8, ak = e & 255;
-        int tt = 0;
-        while ((tt + 1) * (tt + 2) / 2 <= q) ++tt;
-        const int jj = q - tt * (tt + 1) / 2;
-        const int gk = DT * jj + (ak >> 4), ga = DT * tt + (ak & 15);
-        T v;
-        if (gk < w && ga < w) v = (gk <= ga) ? t[(int64_t)gk * tk + (int64_t)ga * tj] : T(0);
-        else v = (gk == ga) ? T(1) : T(0);
-        tu[e] = v;
-    }
-    __syncthreads();
-    const int r0 = (blockIdx.x * 4 + wave) * DT;
-    if (r0 >= m) return;
-    const int b = lane & 15;
-    const int row = r0 + b;
-    const bool rok = row < m;
-    V xr[TRSM_TMAX];
+    // Stage T's upper tiles: thread owns entry ak of tiles tid/256 + 2u.
+    {
+        const int ak = tid & 255;
+        for (int q0 = tid >> 8; q0 < ntile; q0 += (TRSM_NT / 256) * STG) {
+            T v[STG];
 #pragma unroll
-    for (int q = 0; q < TRSM_TMAX; ++q) {
+            for (int u = 0; u < STG; ++u) {
+                const int q = q0 + (TRSM_NT / 256) * u;
+                const int tt = tri_row(q), jj = q - tt * (tt + 1) / 2;
+                const int gk = DT * jj + (ak >> 4), ga = DT * tt + (ak & 15);
+                const bool in = q < ntile && gk < w && ga < w && gk <= ga;
+                const T xv = t[in ? (int64_t)gk * tk + (int64_t)ga * tj : 0];
+                v[u] = in ? xv : (gk == ga ? T(1) : T(0));
+            }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int col = DT * q + tcol<T>(lane, r);
-            xr[q][r] = (q < Tn && rok && col < w) ? x[(int64_t)row * xi + (int64_t)col * xj] : T(0);
-        }
-    }
-#pragma unroll
-    for (int jq = 0; jq < TRSM_TMAX; ++jq) {
-        if (jq < Tn) {
-            tile_rsolve_upper<T>(xr[jq], tu + (jq * (jq + 1) / 2 + jq) * 256, unit != 0, lane);
-#pragma unroll
-            for (int q = jq + 1; q < TRSM_TMAX; ++q) {
-                if (q < Tn) {
-                    const T* ut = tu + (q * (q + 1) / 2 + jq) * 256;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int k = tcol<T>(lane, i);
-                        xr[q] = AT::mfma(-ut[b + 16 * k], xr[jq][i], xr[q]);
-                    }
-                }
+            for (int u = 0; u < STG; ++u) {
+                const int q = q0 + (TRSM_NT / 256) * u;
+                if (q < ntile) tu[q * 256 + ak] = v[u];
             }
         }
     }
+    // reciprocals of the pivots (1 past w, where the padding is the identity)
+    for (int j = tid; j < Tn * DT; j += TRSM_NT)
+        tinv[j] = (j < w && !unit) ? T(1) / t[(int64_t)j * tk + (int64_t)j * tj] : T(1);
+    __syncthreads();
+    // Invert the diagonal tiles, one wave per tile, lane a < 16 owning column a of
+    // the inverse: v_a = 1/U(a,a), v_k = -(sum_{j>k} U(k,j) v_j) / U(k,k) for k < a.
+    for (int jq = wave; jq < Tn; jq += TRSM_NT / 64) {
+        T* dt = tu + (jq * (jq + 1) / 2 + jq) * 256;
+        const T* ri = tinv + DT * jq;
+        const int a = lane & 15;
+        T v[16];
 #pragma unroll
-    for (int q = 0; q < TRSM_TMAX; ++q) {
+        for (int k = 15; k >= 0; --k) {
+            T acc = T(0);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+            for (int j = k + 1; j < 16; ++j) acc += dt[j + 16 * k] * v[j];   // v_j = 0 for j > a
+            v[k] = k > a ? T(0) : (k == a ? ri[k] : -acc * ri[k]);
+        }
+        if (lane < 16) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) dt[a + 16 * k] = v[k];
+        }
+    }
+    __syncthreads();
+    // Each wave walks 16-row blocks grid-stride; T stays staged for all of them.
+    const int b = lane & 15;
+    constexpr int SZ = sizeof(T);
+    for (int r0 = (blockIdx.x * (TRSM_NT / 64) + wave) * DT; r0 < m; r0 += gridDim.x * (TRSM_NT / 64) * DT) {
+        const int row = r0 + b;
+        const bool rok = row < m;
+        V xr[TRSM_TMAX];
+        // Column-major X: one register offset per lane (row, lane-group column),
+        // the tile column in the scalar offset; columns at or past w lie past the
+        // resource's records and rows past m get an out-of-range offset.
+        const rsrc_t rx = make_rsrc_n(x + (int64_t)r0 * xi, XCOL ? (int)((int64_t)w * xj * SZ) : BUF_RECORDS);
+        const int vx = rok ? (int)((b * xi + AT::col_lane(lane) * xj) * SZ) : BUF_OOB;
+        auto xoff = [&](int q, int r) -> int {   // row-major X: mask every entry
             const int col = DT * q + tcol<T>(lane, r);
-            if (q < Tn && rok && col < w) x[(int64_t)row * xi + (int64_t)col * xj] = xr[q][r];
+            return (rok && col < w) ? (int)((b * xi + col * xj) * SZ) : BUF_OOB;
+        };
+#pragma unroll
+        for (int q = 0; q < TRSM_TMAX; ++q) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (XCOL) xr[q][r] = q < Tn ? buf_load<T>(rx, vx, (int)((DT * q + AT::col_reg(r)) * xj * SZ)) : T(0);
+                else xr[q][r] = q < Tn ? buf_load<T>(rx, xoff(q, r), 0) : T(0);
+            }
+        }
+#pragma unroll
+        for (int jq = 0; jq < TRSM_TMAX; ++jq) {
+            if (jq < Tn) {
+                const T* vt = tu + (jq * (jq + 1) / 2 + jq) * 256;
+                V y = zero_vec<V>();
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = tcol<T>(lane, i);
+                    y = AT::mfma(vt[b + 16 * k], xr[jq][i], y);
+                }
+                xr[jq] = y;
+#pragma unroll
+                for (int q = jq + 1; q < TRSM_TMAX; ++q) {
+                    if (q < Tn) {
+                        const T* ut = tu + (q * (q + 1) / 2 + jq) * 256;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int k = tcol<T>(lane, i);
+                            xr[q] = AT::mfma(-ut[b + 16 * k], xr[jq][i], xr[q]);
+                        }
+                    }
+                    // keep the scheduler from hoisting every tile's LDS reads at once
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < TRSM_TMAX; ++q) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (q < Tn) {
+                    if (XCOL) buf_store<T>(rx, vx, xr[q][r], (int)((DT * q + AT::col_reg(r)) * xj * SZ));
+                    else buf_store<T>(rx, xoff(q, r), xr[q][r], 0);
+                }
+            }
         }
     }
 }
@@ -425,19 +519,28 @@ hipError_t launch_getrf_diag(int w, double* a, int64_t ld, int* info, int col_ba
 
 template <typename T>
 hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, int64_t tk, int64_t tj,
-                       int unit, const int* info, hipStream_t st) {
+                       int unit, const int* info, hipStream_t st, int max_wg) {
     if (m <= 0 || w <= 0) return hipSuccess;
     if (w > TRSM_MAX) return hipErrorInvalidValue;
-    const int grid = (m + 63) / 64;
-    hipLaunchKernelGGL((trsm_reg_kernel<T>), dim3(grid), dim3(256), 0, st, m, w, x, xi, xj, t, tk, tj, unit, info);
+    // byte offsets inside one 16-row block (padded to whole tiles) must fit the buffer records
+    const int64_t span = (16 * xi + (int64_t)(w + 16) * xj) * (int64_t)sizeof(T);
+    if (span >= (int64_t)BUF_RECORDS) return hipErrorInvalidValue;
+    int grid = (m + TRSM_NT / 4 - 1) / (TRSM_NT / 4);     // 16 rows per wave
+    if (max_wg > 0 && grid > max_wg) grid = max_wg;
+    if (xi == 1)
+        hipLaunchKernelGGL((trsm_reg_kernel<T, true>), dim3(grid), dim3(TRSM_NT), 0, st, m, w, x, xi, xj, t, tk, tj,
+                           unit, info);
+    else
+        hipLaunchKernelGGL((trsm_reg_kernel<T, false>), dim3(grid), dim3(TRSM_NT), 0, st, m, w, x, xi, xj, t, tk,
+                           tj, unit, info);
     return hipGetLastError();
 }
 
 template hipError_t launch_potrf_diag<double>(int, double*, int64_t, int*, int, hipStream_t);
 template hipError_t launch_potrf_diag<float>(int, float*, int64_t, int*, int, hipStream_t);
 template hipError_t launch_trsm<double>(int, int, double*, int64_t, int64_t, const double*, int64_t, int64_t, int,
-                                        const int*, hipStream_t);
+                                        const int*, hipStream_t, int);
 template hipError_t launch_trsm<float>(int, int, float*, int64_t, int64_t, const float*, int64_t, int64_t, int,
-                                       const int*, hipStream_t);
+                                       const int*, hipStream_t, int);
 
 }  // namespace ff

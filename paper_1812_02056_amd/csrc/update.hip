@@ -16,16 +16,13 @@
 // skipped, and for a square lower region (shift 0) the tiles on or below the
 // diagonal are enumerated as a triangle.
 //
-// Two shapes:
-//   TILE 128, persistent: one 8-wave workgroup per CU (two waves per SIMD),
-//     looping over tiles.  Each wave owns a 64 x 32 part of the tile (8 MFMA
-//     blocks).  The tile's C is loaded into registers at the start of the tile
-//     so its HBM traffic overlaps the K loop; the write-back is then a subtract
-//     and a store.  The grid can be made smaller than the CU count, which leaves
-//     whole CUs free for other streams.
-//   TILE 64: one tile per 4-wave workgroup (32 x 32 per wave), several
-//     workgroups per CU; for narrow regions where 128-wide tiles would leave most
-//     of the chip idle.
+// Shapes of the one kernel template (every wave computes a WW x WW part of the
+// tile with 16 x 16 MFMA blocks):
+//   128 x 128 tiles, 4 waves, two workgroups per CU: wide regions;
+//   256 x 128 tiles, 8 waves, one workgroup per CU: wide regions while another
+//     stream needs whole CUs (the grid is sized to leave them free);
+//   64 x 64 tiles of 32 x 32 wave parts: narrow regions, where wider tiles would
+//     leave most of the chip idle.
 //
 // Element types: double (v_mfma_f64_16x16x4f64), float (v_mfma_f32_16x16x4f32),
 // and bf16 operands (binary32 storage, operands rounded to bfloat16 while staged
@@ -37,21 +34,14 @@ namespace ff {
 
 namespace {
 
-constexpr int NT = 256;    // threads of the 64-tile and bfloat16 shapes (2 x 2 waves)
-
-// Wave arrangement of a shape: WAVES_M x WAVES_N waves over a TILE x TILE tile.
-template <int TILE, bool PERSIST> struct shape {
-    static constexpr int WAVES_M = 2;
-    static constexpr int WAVES_N = PERSIST ? 4 : 2;
-    static constexpr int THREADS = 64 * WAVES_M * WAVES_N;
-    static constexpr int WM = TILE / WAVES_M;     // rows per wave
-    static constexpr int WN = TILE / WAVES_N;     // columns per wave
-};
+constexpr int NT = 256;    // threads of the bfloat16 shape (2 x 2 waves)
 
 struct Grid {
-    int tile;          // output tile edge
+    int tm, tn;        // output tile rows, columns
+    int gm, gn;        // tiles per super-tile along M and N
     int nbm, nbn;      // tiles along M and N
     int nsm, nsn;      // super-tiles along M and N
+    int flat;          // 1: slot = bi + bj * nbm, no super-tiles (small regions)
     int tri;           // 1: square lower region enumerated as a triangle of super-tiles
     int shift;         // LOWER: write only i - j >= shift
     int nslots;        // flat slots covering every super-tile
@@ -59,13 +49,20 @@ struct Grid {
 
 // Map a flat slot to an output tile (bi, bj).  Returns false when the slot is
 // empty.  Workgroups are dealt to the 8 XCDs round-robin, so slot % 8 is the XCD;
-// each XCD works through whole 8 x 8 super-tiles and the 16 operand blocks of a
+// each XCD works through whole super-tiles and the operand blocks of a
 // super-tile stay in that XCD's L2.
 __device__ __forceinline__ bool tile_of_slot(const Grid& g, int slot, bool lower, int& bi, int& bj) {
+    if (g.flat) {
+        bi = slot % g.nbm;
+        bj = slot / g.nbm;
+        if (bj >= g.nbn) return false;
+        return !(lower && (bi * g.tm + g.tm - 1) - bj * g.tn < g.shift);
+    }
+    const int per = g.gm * g.gn;
     const int xcd = slot % N_XCD;
     const int k = slot / N_XCD;
-    int u = (k / UPD_WG_PER_SUPER) * N_XCD + xcd;
-    const int within = k % UPD_WG_PER_SUPER;
+    int u = (k / per) * N_XCD + xcd;
+    const int within = k % per;
     int SI, SJ;
     if (g.tri) {
         const int nsup = g.nsm * (g.nsm + 1) / 2;
@@ -78,327 +75,219 @@ __device__ __forceinline__ bool tile_of_slot(const Grid& g, int slot, bool lower
         SI = u % g.nsm;
         SJ = u / g.nsm;
     }
-    bi = SI * UPD_GROUP + (within % UPD_GROUP);
-    bj = SJ * UPD_GROUP + (within / UPD_GROUP);
+    bi = SI * g.gm + (within % g.gm);
+    bj = SJ * g.gn + (within / g.gm);
     if (bi >= g.nbm || bj >= g.nbn) return false;
-    if (lower && (bi * g.tile + g.tile - 1) - bj * g.tile < g.shift) return false;   // wholly above the line
+    if (lower && (bi * g.tm + g.tm - 1) - bj * g.tn < g.shift) return false;   // wholly above the line
     return true;
 }
 
-// K depth of one LDS stage.  The binary64 persistent shape keeps 16 so that the
-// accumulators, the prefetched C tile and the next stage fit in the register file.
-template <typename T, bool PERSIST> struct stage_depth { static constexpr int BK = 32; };
-template <> struct stage_depth<double, true> { static constexpr int BK = 16; };
+// Wide-region kernel: the product shape that carries almost all of a
+// factorisation's flops.  WMW x 2 waves own a (64 WMW) x 128 tile; each wave
+// computes a 64 x 64 part of it: 16 MFMA blocks fed by 8 LDS fragment reads per
+// 4-deep K step, with the fragments of the next step read while the current
+// step's MFMAs run.  Stages of BK columns are double-buffered in LDS and staged
+// through registers one stage ahead; loads past K return zeros (the buffer
+// record count ends at column K), so only the final stage needs depth guards.
+//   WMW = 2: 256 threads, 64 KB of LDS, two workgroups per CU (two waves per
+//     SIMD from different workgroups, so one workgroup's barrier waits and
+//     write-back are covered by the other's MFMAs);
+//   WMW = 4: 512 threads, 96 KB of LDS, so at most one workgroup fits a CU: a
+//     grid of C - R workgroups leaves R whole CUs free for kernels on another
+//     stream (the lookahead panel work).
+// The grid may be smaller than the tile count; each workgroup then walks the
+// slots grid-stride.
+template <typename T> struct wide_depth { static constexpr int BK = 16; };
+template <> struct wide_depth<float> { static constexpr int BK = 32; };
 
-template <typename T, int TILE, bool YROWS, bool LOWER, bool PERSIST>
-__global__ __launch_bounds__((shape<TILE, PERSIST>::THREADS), (PERSIST ? 1 : 2))
-void update_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc,
-                   const T* __restrict__ X, int64_t ldx,
-                   const T* __restrict__ Y, int64_t ldy, Grid g, const int* __restrict__ info)
-{
-    if (info && *info != 0) return;
-    typedef shape<TILE, PERSIST> SH;
-    constexpr int NTH = SH::THREADS;
-    constexpr int BK = stage_depth<T, PERSIST>::BK;
-    constexpr int WM = SH::WM, WN = SH::WN;
-    constexpr int NBR = WM / 16, NBC = WN / 16;   // MFMA blocks per wave along rows / columns
-    constexpr int NLD = BK * TILE / NTH;          // operand elements each thread stages per K step
-    constexpr int SZ = sizeof(T);
-    typedef acc_traits<T> AT;
-    typedef typename AT::vec V;
-
-    __shared__ T As[2][BK][TILE];   // row operand X[row0 + r, k]   stored [k][r]
-    __shared__ T Bs[2][BK][TILE];   // column operand               stored [k][c ^ (k % 16)]
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wr = wave % SH::WAVES_M, wc = wave / SH::WAVES_M;
-    const int nk = (K + BK - 1) / BK;
-
-    for (int slot = blockIdx.x; slot < g.nslots; slot += (PERSIST ? gridDim.x : g.nslots)) {
-        int bi, bj;
-        if (!tile_of_slot(g, slot, LOWER, bi, bj)) continue;
-        const int row0 = bi * TILE, col0 = bj * TILE;
-        const int mrem = M - row0, nrem = N - col0;
-        // a wave whose part lies wholly above the line computes nothing
-        const bool active = !LOWER || (row0 + WM * wr + WM - 1) - (col0 + WN * wc) >= g.shift;
-
-        const rsrc_t rx = make_rsrc(X + row0);
-        const rsrc_t ry = YROWS ? make_rsrc(Y + col0) : make_rsrc(Y + (int64_t)col0 * ldy);
-        const rsrc_t rc = make_rsrc(C + row0 + (int64_t)col0 * ldc);
-
-        T ra[NLD], rb[NLD];
-        auto load = [&](int kt) {
-            const int k0 = kt * BK;
-#pragma unroll
-            for (int q = 0; q < NLD; ++q) {
-                const int idx = tid + NTH * q;
-                const int kk = idx / TILE, r = idx % TILE;
-                const int gk = k0 + kk;
-                ra[q] = buf_load<T>(rx, (r < mrem && gk < K) ? (r + gk * (int)ldx) * SZ : BUF_OOB);
-            }
-#pragma unroll
-            for (int q = 0; q < NLD; ++q) {
-                const int idx = tid + NTH * q;
-                if (YROWS) {
-                    const int kk = idx / TILE, c = idx % TILE;
-                    const int gk = k0 + kk;
-                    rb[q] = buf_load<T>(ry, (c < nrem && gk < K) ? (c + gk * (int)ldy) * SZ : BUF_OOB);
-                } else {
-                    const int kk = idx % BK, c = idx / BK;
-                    const int gk = k0 + kk;
-                    rb[q] = buf_load<T>(ry, (c < nrem && gk < K) ? (gk + c * (int)ldy) * SZ : BUF_OOB);
-                }
-            }
-        };
-        auto store = [&](int buf) {
-#pragma unroll
-            for (int q = 0; q < NLD; ++q) {
-                const int idx = tid + NTH * q;
-                As[buf][idx / TILE][idx % TILE] = ra[q];
-            }
-#pragma unroll
-            for (int q = 0; q < NLD; ++q) {
-                const int idx = tid + NTH * q;
-                int kk, c;
-                if (YROWS) { kk = idx / TILE; c = idx % TILE; }
-                else { kk = idx % BK; c = idx / BK; }
-                Bs[buf][kk][c ^ (kk & 15)] = rb[q];
-            }
-        };
-        auto c_off = [&](int cb, int r4, int r) -> int {
-            const int li = WM * wr + 16 * r4 + (lane & 15);
-            const int lj = WN * wc + 16 * cb + AT::col(lane, r);
-            const bool ok = active && li < mrem && lj < nrem && (!LOWER || (row0 + li) - (col0 + lj) >= g.shift);
-            return ok ? (li + lj * (int)ldc) * SZ : BUF_OOB;
-        };
-
-        V acc[NBC][NBR];
-#pragma unroll
-        for (int a = 0; a < NBC; ++a)
-#pragma unroll
-            for (int b = 0; b < NBR; ++b) acc[a][b] = zero_vec<V>();
-
-        load(0);
-        // C of this tile, in flight during the K loop (PERSIST shape only)
-        T cv[PERSIST ? NBC : 1][PERSIST ? NBR : 1][4];
-        if constexpr (PERSIST) {
-#pragma unroll
-            for (int cb = 0; cb < NBC; ++cb)
-#pragma unroll
-                for (int r4 = 0; r4 < NBR; ++r4)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) cv[cb][r4][r] = buf_load<T>(rc, c_off(cb, r4, r));
-        }
-        store(0);
-        __syncthreads();
-        for (int kt = 0; kt < nk; ++kt) {
-            const int buf = kt & 1;
-            if (kt + 1 < nk) load(kt + 1);
-            if (active) {
-                const int k0 = kt * BK;
-#pragma unroll
-                for (int k4 = 0; k4 < BK / 4; ++k4) {
-                    if (k0 + 4 * k4 < K) {
-                        const int kk = 4 * k4 + (lane >> 4);
-                        T fa[NBC], fb[NBR];
-#pragma unroll
-                        for (int cb = 0; cb < NBC; ++cb)
-                            fa[cb] = Bs[buf][kk][(WN * wc + 16 * cb + (lane & 15)) ^ (kk & 15)];
-#pragma unroll
-                        for (int r4 = 0; r4 < NBR; ++r4)
-                            fb[r4] = As[buf][kk][WM * wr + 16 * r4 + (lane & 15)];
-#pragma unroll
-                        for (int cb = 0; cb < NBC; ++cb)
-#pragma unroll
-                            for (int r4 = 0; r4 < NBR; ++r4)
-                                acc[cb][r4] = AT::mfma(fa[cb], fb[r4], acc[cb][r4]);
-                    }
-                }
-            }
-            if (kt + 1 < nk) store(buf ^ 1);
-            __syncthreads();
-        }
-
-        // Fused write-back: C[i, j] -= S[i, j]; out-of-region entries are neither
-        // read nor written (their offsets lie past the buffer's records).
-        if constexpr (PERSIST) {
-#pragma unroll
-            for (int cb = 0; cb < NBC; ++cb)
-#pragma unroll
-                for (int r4 = 0; r4 < NBR; ++r4)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        buf_store<T>(rc, c_off(cb, r4, r), cv[cb][r4][r] - acc[cb][r4][r]);
-        } else {
-#pragma unroll
-            for (int cb = 0; cb < NBC; ++cb) {
-                T cw[NBR][4];
-#pragma unroll
-                for (int r4 = 0; r4 < NBR; ++r4)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) cw[r4][r] = buf_load<T>(rc, c_off(cb, r4, r));
-#pragma unroll
-                for (int r4 = 0; r4 < NBR; ++r4)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) buf_store<T>(rc, c_off(cb, r4, r), cw[r4][r] - acc[cb][r4][r]);
-            }
-        }
-    }
-}
-
-// Persistent YROWS kernel for the wide regions that dominate a factorisation.
-// One 8-wave workgroup per CU walks 128 x 128 tiles; each wave owns a 64 x 32
-// part (8 MFMA blocks).  Operand stages are staged through registers two deep
-// (the loads of stage k+2 are in flight while stage k is multiplied and stage
-// k+1 is written to LDS), and the per-lane row offsets are computed once per
-// tile: the K position of a load travels in the scalar offset.  The tile's C is
-// loaded into registers at the start of the tile and written back as C - S at
-// its end.
-constexpr int PT_TILE = 128;
-constexpr int PT_THREADS = 512;
-constexpr int PT_WM = 64, PT_WN = 32;
-
-template <typename T> struct pers_depth { static constexpr int BK = 16; };
-template <> struct pers_depth<float> { static constexpr int BK = 32; };
-
-template <typename T, bool LOWER>
-__global__ __launch_bounds__(PT_THREADS, 1)
-void update_rows_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, const T* __restrict__ X, int64_t ldx,
+template <typename T, int WW, int WMW, bool YROWS, bool LOWER>
+__global__ __launch_bounds__(128 * WMW, 4 / WMW)
+void update_wide_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, const T* __restrict__ X, int64_t ldx,
                         const T* __restrict__ Y, int64_t ldy, Grid g, const int* __restrict__ info)
 {
     if (info && *info != 0) return;
-    constexpr int BK = pers_depth<T>::BK;
+    constexpr int TM = WW * WMW, TN = 2 * WW;
+    constexpr int NTH = 128 * WMW;
+    constexpr int BK = wide_depth<T>::BK;
     constexpr int SZ = sizeof(T);
-    constexpr int NLD = BK * PT_TILE / PT_THREADS;          // elements per thread per operand per stage
-    constexpr int NBR = PT_WM / 16, NBC = PT_WN / 16;
+    constexpr int NLX = BK * TM / NTH;            // staged X elements per thread per stage
+    constexpr int NLY = BK * TN / NTH;            // staged Y elements per thread per stage
+    constexpr int XSTEP = NTH / TM, YSTEP = NTH / TN;
+    static_assert(TM % 64 == 0 && TN % 64 == 0 && NLX * XSTEP == BK && NLY * YSTEP == BK, "staging map");
+    constexpr int NB = WW / 16;                   // MFMA blocks per wave edge
     typedef acc_traits<T> AT;
     typedef typename AT::vec V;
 
-    __shared__ T As[2][BK][PT_TILE];
-    __shared__ T Bs[2][BK][PT_TILE];
+    __shared__ T As[2][BK][TM];   // row operand X(row0 + r, k)    stored [k][r]
+    __shared__ T Bs[2][BK][TN];   // column operand Y(col0 + c, k) stored [k][c]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wr = wave % 2, wc = wave / 2;
-    const int sr = tid % PT_TILE;                 // staging row of this thread
-    const int skk = wave / 2;                     // first staging K index (uniform per wave)
+    const int wr = wave % WMW, wc = wave / WMW;
+    // X staging (and Y when YROWS): thread owns one row and K positions k0 + step*q
+    const int sxr = tid % TM, sxk = wave * 64 / TM;      // tid / TM, uniform per wave (TM % 64 == 0)
+    const int syr = tid % TN, syk = wave * 64 / TN;      // tid / TN, uniform per wave (TN % 64 == 0)
+    // Y staging when K runs down the columns: thread owns column yc, K positions yk0 + e
+    const int yc = tid / YSTEP;
+    const int yk0 = (tid % YSTEP) * NLY;
     const int nk = (K + BK - 1) / BK;
     const int xs = (int)ldx * SZ, ys = (int)ldy * SZ;
 
     for (int slot = blockIdx.x; slot < g.nslots; slot += gridDim.x) {
         int bi, bj;
         if (!tile_of_slot(g, slot, LOWER, bi, bj)) continue;
-        const int row0 = bi * PT_TILE, col0 = bj * PT_TILE;
+        const int row0 = bi * TM, col0 = bj * TN;
         const int mrem = M - row0, nrem = N - col0;
-        const bool active = !LOWER || (row0 + PT_WM * wr + PT_WM - 1) - (col0 + PT_WN * wc) >= g.shift;
-        const rsrc_t rx = make_rsrc(X + row0);
-        const rsrc_t ry = make_rsrc(Y + col0);
-        const rsrc_t rc = make_rsrc(C + row0 + (int64_t)col0 * ldc);
-        const int vx = sr < mrem ? sr * SZ : BUF_OOB;
-        const int vy = sr < nrem ? sr * SZ : BUF_OOB;
+        const bool active = !LOWER || (row0 + WW * wr + WW - 1) - (col0 + WW * wc) >= g.shift;
+        const int vx = sxr < mrem ? sxr * SZ : BUF_OOB;
+        const int vy = YROWS ? (syr < nrem ? syr * SZ : BUF_OOB) : (yc < nrem ? yc * ys : BUF_OOB);
+        const T* Xt = X + row0;
+        const T* Yt = YROWS ? Y + col0 : Y + (int64_t)col0 * ldy;
 
-        T xa0[NLD], ya0[NLD], xa1[NLD], ya1[NLD];
-        // K columns past the end get an offset at or beyond the records (the OR with
-        // BUF_OOB), written without a select so every load issues unconditionally.
-        auto load = [&](int kt, T (&xa)[NLD], T (&ya)[NLD]) {
-#pragma unroll
-            for (int q = 0; q < NLD; ++q) {
-                const int gk = kt * BK + skk + 4 * q;
-                const int past = (K - 1 - gk) >> 31;            // all ones when gk >= K
-                xa[q] = buf_load<T>(rx, vx, (gk * xs) | (past & BUF_OOB));
-                ya[q] = buf_load<T>(ry, vy, (gk * ys) | (past & BUF_OOB));
-            }
-        };
-        auto store = [&](int buf, const T (&xa)[NLD], const T (&ya)[NLD]) {
-#pragma unroll
-            for (int q = 0; q < NLD; ++q) {
-                As[buf][skk + 4 * q][sr] = xa[q];
-                Bs[buf][skk + 4 * q][sr] = ya[q];
-            }
-        };
-
-        V acc[NBC][NBR];
-#pragma unroll
-        for (int a = 0; a < NBC; ++a)
-#pragma unroll
-            for (int b = 0; b < NBR; ++b) acc[a][b] = zero_vec<V>();
-        auto compute = [&](int kt, int buf) {
-            if (!active) return;
+        // Stage kt: a resource starting at K column kt*BK whose record count ends
+        // at column K, so K columns past the end read zero; rows past M read zero
+        // through vx / vy.
+        T xa[NLX], ya[NLY];
+        auto load = [&](int kt) {
             const int k0 = kt * BK;
+            const int kv = K - k0 > 0 ? K - k0 : 0;
+            const rsrc_t rx = make_rsrc_n(Xt + (int64_t)k0 * ldx, kv * xs);
+#pragma unroll
+            for (int q = 0; q < NLX; ++q) xa[q] = buf_load<T>(rx, vx, (sxk + XSTEP * q) * xs);
+            if (YROWS) {
+                const rsrc_t ry = make_rsrc_n(Yt + (int64_t)k0 * ldy, kv * ys);
+#pragma unroll
+                for (int q = 0; q < NLY; ++q) ya[q] = buf_load<T>(ry, vy, (syk + YSTEP * q) * ys);
+            } else {
+                const rsrc_t ry = make_rsrc(Yt + k0);
+#pragma unroll
+                for (int e = 0; e < NLY; ++e) ya[e] = buf_load<T>(ry, yk0 + e < kv ? vy + (yk0 + e) * SZ : BUF_OOB, 0);
+            }
+        };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < NLX; ++q) As[buf][sxk + XSTEP * q][sxr] = xa[q];
+            if (YROWS) {
+#pragma unroll
+                for (int q = 0; q < NLY; ++q) Bs[buf][syk + YSTEP * q][syr] = ya[q];
+            } else {
+#pragma unroll
+                for (int e = 0; e < NLY; ++e) Bs[buf][yk0 + e][yc] = ya[e];
+            }
+        };
+
+        V acc[NB][NB];
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = zero_vec<V>();
+
+        // fa: column-operand fragments (the MFMA A input), fb: row-operand
+        // fragments; the product tile is the transposed one (lanes along rows).
+        auto frags = [&](int buf, int k4, T (&fa)[NB], T (&fb)[NB]) {
+            const int kk = 4 * k4 + (lane >> 4);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) fa[b] = Bs[buf][kk][WW * wc + 16 * b + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) fb[b] = As[buf][kk][WW * wr + 16 * b + (lane & 15)];
+        };
+        auto mma = [&](const T (&fa)[NB], const T (&fb)[NB]) {
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                for (int r4 = 0; r4 < NB; ++r4) acc[cb][r4] = AT::mfma(fa[cb], fb[r4], acc[cb][r4]);
+        };
+        auto compute_full = [&](int buf) {
+            T fa0[NB], fb0[NB], fa1[NB], fb1[NB];
+            frags(buf, 0, fa0, fb0);
+#pragma unroll
+            for (int k4 = 0; k4 < BK / 4; k4 += 2) {
+                frags(buf, k4 + 1, fa1, fb1);
+                mma(fa0, fb0);
+                if (k4 + 2 < BK / 4) frags(buf, k4 + 2, fa0, fb0);
+                mma(fa1, fb1);
+            }
+        };
+        auto compute_tail = [&](int buf, int nk4) {
 #pragma unroll
             for (int k4 = 0; k4 < BK / 4; ++k4) {
-                if (k0 + 4 * k4 < K) {
-                    const int kk = 4 * k4 + (lane >> 4);
-                    T fa[NBC], fb[NBR];
-#pragma unroll
-                    for (int cb = 0; cb < NBC; ++cb) fa[cb] = Bs[buf][kk][PT_WN * wc + 16 * cb + (lane & 15)];
-#pragma unroll
-                    for (int r4 = 0; r4 < NBR; ++r4) fb[r4] = As[buf][kk][PT_WM * wr + 16 * r4 + (lane & 15)];
-#pragma unroll
-                    for (int cb = 0; cb < NBC; ++cb)
-#pragma unroll
-                        for (int r4 = 0; r4 < NBR; ++r4) acc[cb][r4] = AT::mfma(fa[cb], fb[r4], acc[cb][r4]);
+                if (k4 < nk4) {
+                    T fa[NB], fb[NB];
+                    frags(buf, k4, fa, fb);
+                    mma(fa, fb);
                 }
             }
         };
 
-        // C offsets: interior tiles take a per-lane base plus uniform column steps;
-        // tiles on an edge or on the diagonal mask each entry.
-        const bool full = mrem >= PT_TILE && nrem >= PT_TILE &&
-                          (!LOWER || row0 - (col0 + PT_TILE - 1) >= g.shift);
-        const int li0 = PT_WM * wr + (lane & 15);
-        auto c_off = [&](int cb, int r4, int r) -> int {
-            const int li = li0 + 16 * r4;
-            const int lj = PT_WN * wc + 16 * cb + AT::col(lane, r);
-            if (full) return (li + lj * (int)ldc) * SZ;
-            const bool ok = active && li < mrem && lj < nrem && (!LOWER || (row0 + li) - (col0 + lj) >= g.shift);
-            return ok ? (li + lj * (int)ldc) * SZ : BUF_OOB;
-        };
-
-        load(0, xa0, ya0);
-        load(1, xa1, ya1);
-        store(0, xa0, ya0);
+        load(0);
+        store(0);
         __syncthreads();
-        T cv[NBC][NBR][4];
-#pragma unroll
-        for (int cb = 0; cb < NBC; ++cb)
-#pragma unroll
-            for (int r4 = 0; r4 < NBR; ++r4)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) cv[cb][r4][r] = bufop<T, AUX_NT>::load(rc, c_off(cb, r4, r), 0);
-
-        // The prefetch is issued unconditionally (stages past the end load zeros
-        // without touching memory) so the compiler's wait before the LDS store
-        // only covers the stage being stored.
-        for (int kt = 0; kt < nk;) {
-            // even step: registers 0 free, registers 1 hold stage kt+1
-            load(kt + 2, xa0, ya0);
-            compute(kt, 0);
-            if (kt + 1 < nk) store(1, xa1, ya1);
+        // No branch around the MFMAs: a conditional compute lets the compiler sink
+        // the next stage's loads below it, next to their LDS stores, which exposes
+        // the full load latency every stage.  Waves wholly outside the written
+        // region (diagonal tiles only) compute and discard.
+        for (int kt = 0; kt + 1 < nk; ++kt) {
+            load(kt + 1);
+            compute_full(kt & 1);
+            store((kt + 1) & 1);
             __syncthreads();
-            if (++kt >= nk) break;
-            // odd step: registers 1 free, registers 0 hold stage kt+1
-            load(kt + 2, xa1, ya1);
-            compute(kt, 1);
-            if (kt + 1 < nk) store(0, xa0, ya0);
-            __syncthreads();
-            ++kt;
         }
+        compute_tail((nk - 1) & 1, (K - (nk - 1) * BK + 3) / 4);
 
         if (active) {
+            // Write-back C - S.  Lane part of the offset in a register, the block
+            // column in the scalar offset, the block row in the immediate.  Tiles
+            // on an edge or crossing the written region's boundary mask each entry.
+            const rsrc_t rc = make_rsrc(C + row0 + (int64_t)col0 * ldc);
+            const int li0 = WW * wr + (lane & 15);
+            const int lj0 = WW * wc + AT::col_lane(lane);
+            const int cs = (int)ldc * SZ;
+            const int cbase = (li0 + lj0 * (int)ldc) * SZ;
+            const bool full = mrem >= TM && nrem >= TN && (!LOWER || row0 - (col0 + TN - 1) >= g.shift);
+            if (full) {
 #pragma unroll
-            for (int cb = 0; cb < NBC; ++cb)
-#pragma unroll
-                for (int r4 = 0; r4 < NBR; ++r4)
+                for (int cb = 0; cb < NB; ++cb) {
+                    T cv[NB][4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        bufop<T, AUX_NT>::store(rc, c_off(cb, r4, r), cv[cb][r4][r] - acc[cb][r4][r], 0);
+#pragma unroll
+                        for (int r4 = 0; r4 < NB; ++r4)
+                            cv[r4][r] = bufop<T, AUX_NT>::load(rc, cbase + 16 * r4 * SZ, (16 * cb + AT::col_reg(r)) * cs);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int r4 = 0; r4 < NB; ++r4)
+                            bufop<T, AUX_NT>::store(rc, cbase + 16 * r4 * SZ, cv[r4][r] - acc[cb][r4][r],
+                                                    (16 * cb + AT::col_reg(r)) * cs);
+                }
+            } else {
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb) {
+                    T cv[NB][4];
+                    int off[NB][4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int r4 = 0; r4 < NB; ++r4) {
+                            const int li = li0 + 16 * r4;
+                            const int lj = lj0 + 16 * cb + AT::col_reg(r);
+                            const bool ok = li < mrem && lj < nrem && (!LOWER || (row0 + li) - (col0 + lj) >= g.shift);
+                            off[r4][r] = ok ? cbase + (16 * r4 + (16 * cb + AT::col_reg(r)) * (int)ldc) * SZ : BUF_OOB;
+                            cv[r4][r] = bufop<T, AUX_NT>::load(rc, off[r4][r], 0);
+                        }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int r4 = 0; r4 < NB; ++r4)
+                            bufop<T, AUX_NT>::store(rc, off[r4][r], cv[r4][r] - acc[cb][r4][r], 0);
+                }
+            }
         }
+        __syncthreads();   // the next tile's first stage reuses buffer 0
     }
 }
+
 
 // bfloat16-operand variant (YROWS form, optional LOWER, persistent 128 tiles);
 // binary32 storage and accumulation.  Operand tiles are stored row-major
@@ -511,18 +400,31 @@ void update_bf16_kernel(int M, int N, int K, float* __restrict__ C, int64_t ldc,
     }
 }
 
-Grid make_grid(int tile, int M, int N, bool lower, int shift) {
+// Super-tiles are square (gm * tm == gn * tn) so that a square lower region can be
+// enumerated as a triangle of them.
+Grid make_grid(int tm, int tn, int gm, int gn, int M, int N, bool lower, int shift) {
     Grid g;
-    g.tile = tile;
-    g.nbm = (M + tile - 1) / tile;
-    g.nbn = (N + tile - 1) / tile;
-    g.nsm = (g.nbm + UPD_GROUP - 1) / UPD_GROUP;
-    g.nsn = (g.nbn + UPD_GROUP - 1) / UPD_GROUP;
-    g.tri = (lower && M == N && shift == 0) ? 1 : 0;
+    g.tm = tm;
+    g.tn = tn;
+    g.gm = gm;
+    g.gn = gn;
+    g.nbm = (M + tm - 1) / tm;
+    g.nbn = (N + tn - 1) / tn;
+    g.nsm = (g.nbm + gm - 1) / gm;
+    g.nsn = (g.nbn + gn - 1) / gn;
+    g.tri = (lower && M == N && shift == 0 && gm * tm == gn * tn) ? 1 : 0;
     g.shift = shift;
     const int nsup = g.tri ? g.nsm * (g.nsm + 1) / 2 : g.nsm * g.nsn;
-    g.nslots = ((nsup + N_XCD - 1) / N_XCD) * N_XCD * UPD_WG_PER_SUPER;
+    g.nslots = ((nsup + N_XCD - 1) / N_XCD) * N_XCD * gm * gn;
+    // Regions of fewer tiles than the chip has CUs gain nothing from the L2
+    // grouping, and the rounding up to whole super-tiles per XCD would launch
+    // mostly empty workgroups.
+    g.flat = (int64_t)g.nbm * g.nbn < 256 ? 1 : 0;
+    if (g.flat) g.nslots = g.nbm * g.nbn;
     return g;
+}
+Grid make_grid(int tile, int M, int N, bool lower, int shift) {
+    return make_grid(tile, tile, UPD_GROUP, UPD_GROUP, M, N, lower, shift);
 }
 
 // Largest K for which every in-range operand byte offset of one tile stays below
@@ -548,21 +450,20 @@ int cu_count() {
     return cached[dev];
 }
 
-template <typename T, int TILE, bool PERSIST>
-hipError_t launch_shape(int M, int N, int Kc, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
-                        bool yrows, bool lower, const Grid& g, int nwg, const int* info, hipStream_t st) {
-#define FF_UPD_LAUNCH(YR, LO)                                                                                     \
-    hipLaunchKernelGGL((update_kernel<T, TILE, YR, LO, PERSIST>), dim3(nwg), dim3(shape<TILE, PERSIST>::THREADS), 0, \
-                       st, M, N, Kc, C, ldc, X, \
-                       ldx, Y, ldy, g, info)
+template <typename T, int WW, int WMW>
+hipError_t launch_wide(int M, int N, int Kc, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
+                       bool yrows, bool lower, const Grid& g, int nwg, const int* info, hipStream_t st) {
+#define FF_WIDE_LAUNCH(YR, LO)                                                                                       \
+    hipLaunchKernelGGL((update_wide_kernel<T, WW, WMW, YR, LO>), dim3(nwg), dim3(128 * WMW), 0, st, M, N, Kc, C, ldc, \
+                       X, ldx, Y, ldy, g, info)
     if (yrows) {
-        if (lower) FF_UPD_LAUNCH(true, true);
-        else FF_UPD_LAUNCH(true, false);
+        if (lower) FF_WIDE_LAUNCH(true, true);
+        else FF_WIDE_LAUNCH(true, false);
     } else {
-        if (lower) FF_UPD_LAUNCH(false, true);
-        else FF_UPD_LAUNCH(false, false);
+        if (lower) FF_WIDE_LAUNCH(false, true);
+        else FF_WIDE_LAUNCH(false, false);
     }
-#undef FF_UPD_LAUNCH
+#undef FF_WIDE_LAUNCH
     return hipGetLastError();
 }
 
@@ -577,7 +478,8 @@ int update_workers(int reserve_cus) {
 
 template <typename T>
 hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
-                         bool yrows, bool lower, int shift, const int* info, hipStream_t st, int reserve_cus) {
+                         bool yrows, bool lower, int shift, const int* info, hipStream_t st, int reserve_cus,
+                         int max_cus) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
     if (!ld_fits(ldc, sizeof(T)) || (!yrows && !ld_fits(ldy, sizeof(T)))) return hipErrorInvalidValue;
     const int kc = max_k_chunk(ldx, ldy, yrows, sizeof(T));
@@ -591,24 +493,24 @@ hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int
         const T* Yk = yrows ? Y + (int64_t)k0 * ldy : Y + k0;
         hipError_t e;
         if (narrow) {
+            // 64 x 64 tiles of 32 x 32 wave parts, one tile per workgroup
             const Grid g = make_grid(64, M, N, lower, shift);
-            e = launch_shape<T, 64, false>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, g.nslots, info, st);
-        } else if (yrows) {
-            const Grid g = make_grid(PT_TILE, M, N, lower, shift);
+            int nwg = g.nslots;
+            if (max_cus > 0 && nwg > 4 * max_cus) nwg = 4 * max_cus;     // four 64-tile workgroups fit a CU
+            e = launch_wide<T, 32, 2>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
+        } else if (reserve_cus > 0) {
+            // one workgroup per CU on all but reserve_cus CUs
+            const Grid g = make_grid(256, 128, 4, 8, M, N, lower, shift);
             int nwg = update_workers(reserve_cus);
             if (nwg > g.nslots) nwg = g.nslots;
-            if (lower)
-                hipLaunchKernelGGL((update_rows_kernel<T, true>), dim3(nwg), dim3(PT_THREADS), 0, st, M, N, Kc, C, ldc,
-                                   Xk, ldx, Yk, ldy, g, info);
-            else
-                hipLaunchKernelGGL((update_rows_kernel<T, false>), dim3(nwg), dim3(PT_THREADS), 0, st, M, N, Kc, C,
-                                   ldc, Xk, ldx, Yk, ldy, g, info);
-            e = hipGetLastError();
+            e = launch_wide<T, 64, 4>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
         } else {
+            // two workgroups per CU
             const Grid g = make_grid(128, M, N, lower, shift);
-            int nwg = update_workers(reserve_cus);
+            int nwg = 2 * update_workers(0);
+            if (max_cus > 0 && nwg > 2 * max_cus) nwg = 2 * max_cus;
             if (nwg > g.nslots) nwg = g.nslots;
-            e = launch_shape<T, 128, true>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
+            e = launch_wide<T, 64, 2>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
         }
         if (e != hipSuccess) return e;
     }
@@ -642,8 +544,8 @@ hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const 
 }
 
 template hipError_t launch_update<double>(int, int, int, double*, int64_t, const double*, int64_t, const double*,
-                                          int64_t, bool, bool, int, const int*, hipStream_t, int);
+                                          int64_t, bool, bool, int, const int*, hipStream_t, int, int);
 template hipError_t launch_update<float>(int, int, int, float*, int64_t, const float*, int64_t, const float*,
-                                         int64_t, bool, bool, int, const int*, hipStream_t, int);
+                                         int64_t, bool, bool, int, const int*, hipStream_t, int, int);
 
 }  // namespace ff
