@@ -10,8 +10,9 @@ reported value is the best s.  Metric: TFLOP/s counted as n^3/3 per factorisatio
 Inputs are resident in HBM (one fresh copy of A per timed step) before the timed
 region starts.
 
-Also reported on the same JSON line: the trailing-update kernel against its
-roofline (binary64 MFMA peak), the CPU oracle's rate on a bounded sample of the
+Also reported on the same JSON line: the dominant trailing-update kernel of the
+timed steps against its roofline (binary64 MFMA peak; its launches are timed
+with HIP events the library records on its own stream), the CPU oracle's rate on a bounded sample of the
 same workload, LU without pivoting (n = 16384, s = 168, 2n^3/3), the one-level
 Strassen update, and the mixed-precision solves with binary64 refinement against
 the plain binary64 solve.
@@ -33,7 +34,10 @@ sys.path.insert(0, ROOT)
 MI355X_HBM_GBS = 8000.0
 MI355X_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 UPDATE_SRC = os.path.join(ROOT, "paper_1812_02056_amd", "csrc", "update.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_f64_n16384_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_wide_f64_n16384_traffic.json")
+KERNEL_OF_SHAPE = {"64x64": "update_wide_kernel<double, 32, 2, ...>",
+                   "128x128": "update_wide_kernel<double, 64, 2, ...>",
+                   "256x128": "update_wide_kernel<double, 64, 4, ...>"}
 
 
 def log(msg):
@@ -51,49 +55,14 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--cpu-n", type=int, default=12288)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device copy 3 times (reference kernel for HBM counter scaling)")
     return p.parse_args()
-
-
-def update_shapes(n, s):
-    """(m, w) of every trailing update of Algorithm 1 with step s."""
-    out = []
-    c0 = 0
-    while c0 < n:
-        w = min(s, n - c0)
-        m = n - c0 - w
-        if m > 0:
-            out.append((m, w))
-        c0 += s
-    return out
 
 
 def source_hash(path):
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
-def time_update_kernel(ff, torch, n, s, dev, reps=1):
-    """Average duration of the binary64 trailing-update kernel over the launches of
-    one factorisation (same shapes), timed with HIP events on the launch stream."""
-    P = torch.randn(s, n, dtype=torch.float64, device=dev).t()         # n x s column-major
-    C = torch.randn(n, n, dtype=torch.float64, device=dev).t()
-    st = torch.cuda.current_stream()
-    shapes = update_shapes(n, s)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in shapes]
-    tot_ms, tot_flops, launches = 0.0, 0.0, 0
-    for _ in range(reps):
-        for (m, w), (e0, e1) in zip(shapes, evs):
-            off = n - m
-            e0.record(st)
-            ff.update_syrk(C[off:, off:], P[off:, :w], dtype="f64", stream=st)
-            e1.record(st)
-        torch.cuda.synchronize()
-        for (m, w), (e0, e1) in zip(shapes, evs):
-            tot_ms += e0.elapsed_time(e1)
-            tot_flops += float(m) * (m + 1) * w
-            launches += 1
-    del P, C
-    return tot_ms / launches, tot_flops / launches, launches
 
 
 def main():
@@ -110,6 +79,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 x 1 GiB read + 1 GiB written")
+        return
     ff.load()
     n = args.n
     svals = [int(x) for x in args.s.split(",")]
@@ -149,11 +126,23 @@ def main():
     for i in range(W):
         ff.chol_factor(copies[i].t(), s, dtype="f64", info=info)
     torch.cuda.synchronize()
+    # The library brackets each trailing-update launch with HIP events on its own
+    # stream while profiling is on; event records cost microseconds of host time
+    # each, so the K steps are timed once without and once with them.
     t0 = time.perf_counter()
     for i in range(W, W + K):
         ff.chol_factor(copies[i].t(), s, dtype="f64", info=info)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / K
+    for i in range(W, W + K):
+        copies[i].copy_(A0)
+    torch.cuda.synchronize()
+    ff.update_profile_enable(True)
+    for i in range(W, W + K):
+        ff.chol_factor(copies[i].t(), s, dtype="f64", info=info)
+    torch.cuda.synchronize()
+    ff.update_profile_enable(False)
+    prof = ff.update_profile_read()
     if int(info.item()) != 0:
         print(f"factorisation failed: info={int(info.item())}", file=sys.stderr)
         sys.exit(1)
@@ -167,25 +156,31 @@ def main():
     del L, copies
     torch.cuda.empty_cache()
 
-    # roofline of the dominant kernel (binary64 trailing update)
-    avg_ms, avg_flops, nl = time_update_kernel(ff, torch, n, s, dev)
+    # roofline of the dominant kernel: the trailing-update shape with the most time
+    shape, pk = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_ms = pk["total_ms"] / max(1, pk["launches"])
+    avg_flops = pk["total_flops"] / max(1, pk["launches"])
     achieved = avg_flops / (avg_ms * 1e-3) / 1e12
     peak = MI355X_PEAK_TFLOPS["f64"]
+    kname = KERNEL_OF_SHAPE[shape]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("source_sha256_16") == source_hash(UPDATE_SRC) and int(tr.get("s", -1)) == s:
+            if (tr.get("source_sha256_16") == source_hash(UPDATE_SRC) and int(tr.get("s", -1)) == s
+                    and tr.get("kernel") == kname):
                 traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "update_kernel<double> (A22 -= L21 L21^T, lower)",
-                "avg_launch_ms": round(avg_ms, 4), "launches": nl,
-                "flops_per_launch": avg_flops}
-    log(f"[bench] update kernel: avg {avg_ms:.3f} ms/launch over {nl} launches, {achieved:.2f} TFLOP/s "
-        f"({achieved/peak*100:.1f}% of FP64 MFMA peak)")
+                "frac": round(achieved / peak, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
+                "kernel": kname, "avg_launch_ms": round(avg_ms, 4), "launches": pk["launches"],
+                "flops_per_launch": avg_flops,
+                "time_share_of_step": round(pk["total_ms"] / (K * dt * 1e3), 4),
+                "other_update_shapes": {k: v for k, v in prof.items() if k != shape and v["launches"]}}
+    log(f"[bench] dominant kernel {kname}: avg {avg_ms:.3f} ms/launch over {pk['launches']} launches, "
+        f"{achieved:.2f} TFLOP/s ({achieved/peak*100:.1f}% of FP64 MFMA peak), "
+        f"{pk['total_ms'] / (K * dt * 1e3) * 100:.1f}% of step time")
 
     extras = {}
     if not args.quick and not args.no_extras:

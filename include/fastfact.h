@@ -169,6 +169,29 @@ int ff_update_syrk(int64_t m, int64_t w, void *C, int64_t ldc, const void *P, in
 int ff_update_gemm(int64_t m, int64_t w, void *C, int64_t ldc, const void *X, int64_t ldx,
                    const void *Y, int64_t ldy, int dtype, unsigned flags, void *stream);
 
+/*
+ * Measurement aid (not part of the method): while enabled, every trailing
+ * update launched by chol_factor is bracketed by a pair of HIP events recorded
+ * on the stream it runs on, and tallied by the kernel shape the launch used.
+ * Events are created per launch, so leave it off outside timing runs.
+ *   ff_update_profile_enable(1) clears the tallies and starts recording;
+ *   ff_update_profile_enable(0) stops recording (tallies are kept).
+ *   ff_update_profile_read waits for the recorded events and fills out[shape]
+ *   for shape FF_UPD_SHAPE_64 (64 x 64 tiles), FF_UPD_SHAPE_128 (128 x 128
+ *   tiles, two workgroups per CU) and FF_UPD_SHAPE_256x128 (256 x 128 tiles, one
+ *   workgroup per CU: the lookahead update); flops are the algorithmic
+ *   2 K x (entries written) of each launch.  Host-synchronous; the tallies are
+ *   process-wide.  Returns 0 or FF_ERR_HIP.
+ */
+enum { FF_UPD_SHAPE_64 = 0, FF_UPD_SHAPE_128 = 1, FF_UPD_SHAPE_256x128 = 2, FF_UPD_NSHAPES = 3 };
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double total_flops;
+} ff_kernel_profile;
+int ff_update_profile_enable(int enable);
+int ff_update_profile_read(ff_kernel_profile out[FF_UPD_NSHAPES]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,7 +33,14 @@ EXPORTED = (
     "ff_status_string", "ff_version", "ff_chol_workspace_size", "chol_factor",
     "ff_lu_workspace_size", "lu_nopiv_factor", "ff_solve_workspace_size", "chol_solve",
     "ff_trisolve_workspace_size", "chol_trisolve", "ff_update_syrk", "ff_update_gemm",
+    "ff_update_profile_enable", "ff_update_profile_read",
 )
+
+UPD_SHAPES = ("64x64", "128x128", "256x128")   # FF_UPD_SHAPE_* order
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("total_flops", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -88,6 +95,10 @@ def load():
     lib.ff_update_syrk.restype = i32
     lib.ff_update_gemm.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, i32, u32, vp]
     lib.ff_update_gemm.restype = i32
+    lib.ff_update_profile_enable.argtypes = [i32]
+    lib.ff_update_profile_enable.restype = i32
+    lib.ff_update_profile_read.argtypes = [ctypes.POINTER(KernelProfile)]
+    lib.ff_update_profile_read.restype = i32
     _lib = lib
     return lib
 
@@ -263,3 +274,16 @@ def update_gemm(C: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, dtype="f64", 
                                _stream(stream))
     _check(rc, "ff_update_gemm")
     return C
+
+
+def update_profile_enable(enable: bool = True):
+    """Start (clearing the tallies) or stop event timing of chol_factor's trailing updates."""
+    _check(load().ff_update_profile_enable(1 if enable else 0), "ff_update_profile_enable")
+
+
+def update_profile_read() -> dict:
+    """Per kernel shape: launches, total_ms, total_flops since the last enable (synchronises)."""
+    out = (KernelProfile * 3)()
+    _check(load().ff_update_profile_read(out), "ff_update_profile_read")
+    return {UPD_SHAPES[i]: {"launches": int(out[i].launches), "total_ms": float(out[i].total_ms),
+                            "total_flops": float(out[i].total_flops)} for i in range(3)}

@@ -95,6 +95,65 @@ struct Events {
     }
 };
 
+// ---------------------------------------------------------------- update profile
+// Measurement aid behind ff_update_profile_*: event pairs around the trailing
+// updates of chol_factor, tallied per kernel shape.
+struct UpdProfile {
+    std::mutex mu;
+    bool on = false;
+    struct Rec {
+        hipEvent_t e0, e1;
+        double flops;
+        int shape;
+    };
+    std::vector<Rec> recs;
+    ff_kernel_profile tally[FF_UPD_NSHAPES];
+};
+UpdProfile& upd_profile() {
+    static UpdProfile p;
+    return p;
+}
+
+// Entries (i, j), i < M, j < N, with i - j >= shift.
+double region_entries(int M, int N, int shift) {
+    double c = 0;
+    for (int j = 0; j < N; ++j) {
+        const int lo = std::max(0, j + shift);
+        if (lo < M) c += (double)(M - lo);
+    }
+    return c;
+}
+
+struct UpdTimer {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double flops = 0;
+    int shape = 0;
+    hipStream_t st = nullptr;
+    UpdTimer(int M, int N, int K, int shift, int reserve, hipStream_t s) : st(s) {
+        UpdProfile& p = upd_profile();
+        {
+            std::lock_guard<std::mutex> lk(p.mu);
+            if (!p.on) return;
+        }
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            e0 = e1 = nullptr;
+            return;
+        }
+        flops = 2.0 * (double)K * region_entries(M, N, shift);
+        shape = update_shape(M, N, reserve);
+        (void)hipEventRecord(e0, st);
+    }
+    void stop() {
+        if (!e0) return;
+        (void)hipEventRecord(e1, st);
+        UpdProfile& p = upd_profile();
+        std::lock_guard<std::mutex> lk(p.mu);
+        p.recs.push_back({e0, e1, flops, shape});
+        e0 = e1 = nullptr;
+    }
+};
+
 // ---------------------------------------------------------------- panel solves
 // X T = B for the m x w panel, T upper triangular (see launch_trsm), solved in
 // column chunks of TRSM_MAX when w is wider: chunk [c0, c1) first subtracts the
@@ -169,10 +228,12 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
                                                    reinterpret_cast<const double*>(P + r0), lda, info, st));
             return 0;
         }
+        UpdTimer tm(M, N, w, shift, reserve, st);
         FF_TRY(launch_update<double>(M, N, w, reinterpret_cast<double*>(C), lda,
                                      reinterpret_cast<const double*>(P + r0), lda,
                                      reinterpret_cast<const double*>(P + q0), lda, true, true, shift, info, st,
                                      reserve));
+        tm.stop();
     } else {
         if (dtype == FF_BF16)
             FF_TRY(launch_update_bf16(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, shift, info, st, reserve));
@@ -641,6 +702,41 @@ int ff_update_gemm(int64_t m, int64_t w, void* C, int64_t ldc, const void* X, in
                                  static_cast<const float*>(Y), ldy, false, false, 0, nullptr, st);
     }
     return e == hipSuccess ? 0 : FF_ERR_HIP;
+}
+
+int ff_update_profile_enable(int enable) {
+    UpdProfile& p = upd_profile();
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (enable) {
+        for (auto& r : p.recs) {
+            (void)hipEventDestroy(r.e0);
+            (void)hipEventDestroy(r.e1);
+        }
+        p.recs.clear();
+        for (auto& t : p.tally) t = ff_kernel_profile{0, 0.0, 0.0};
+    }
+    p.on = enable != 0;
+    return 0;
+}
+
+int ff_update_profile_read(ff_kernel_profile out[FF_UPD_NSHAPES]) {
+    UpdProfile& p = upd_profile();
+    std::lock_guard<std::mutex> lk(p.mu);
+    int rc = 0;
+    for (auto& r : p.recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) rc = FF_ERR_HIP;
+        ff_kernel_profile& t = p.tally[r.shape];
+        t.launches += 1;
+        t.total_ms += ms;
+        t.total_flops += r.flops;
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    p.recs.clear();
+    if (out)
+        for (int i = 0; i < FF_UPD_NSHAPES; ++i) out[i] = p.tally[i];
+    return rc;
 }
 
 }  // extern "C"

@@ -32,6 +32,8 @@ hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const 
                               int reserve_cus = 0);
 // Persistent workgroups an update launch uses when reserve_cus CUs are kept free.
 int update_workers(int reserve_cus);
+// Kernel shape launch_update picks for an M x N region (FF_UPD_SHAPE_*).
+int update_shape(int M, int N, int reserve_cus);
 // One Strassen level over 2x2 super-tiles of output tiles (strassen.hip).
 hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc, const double* P, int64_t ldp,
                                            const int* info, hipStream_t st);

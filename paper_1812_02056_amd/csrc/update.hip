@@ -28,6 +28,7 @@
 // and bf16 operands (binary32 storage, operands rounded to bfloat16 while staged
 // into LDS, binary32 accumulation, v_mfma_f32_16x16x32_bf16; YROWS only).
 #include "common.hpp"
+#include "fastfact.h"
 #include "internal.hpp"
 
 namespace ff {
@@ -476,6 +477,14 @@ int update_workers(int reserve_cus) {
     return w < N_XCD ? N_XCD : w;
 }
 
+int update_shape(int M, int N, int reserve_cus) {
+    // narrow regions (fewer 128-wide tiles than half the CUs) use 64 tiles
+    const bool narrow = (M < 2 * 128 || N < 2 * 128) ||
+                        ((int64_t)((M + 127) / 128) * ((N + 127) / 128) < (int64_t)cu_count() / 2);
+    if (narrow) return FF_UPD_SHAPE_64;
+    return reserve_cus > 0 ? FF_UPD_SHAPE_256x128 : FF_UPD_SHAPE_128;
+}
+
 template <typename T>
 hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
                          bool yrows, bool lower, int shift, const int* info, hipStream_t st, int reserve_cus,
@@ -484,9 +493,8 @@ hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int
     if (!ld_fits(ldc, sizeof(T)) || (!yrows && !ld_fits(ldy, sizeof(T)))) return hipErrorInvalidValue;
     const int kc = max_k_chunk(ldx, ldy, yrows, sizeof(T));
     if (kc < 1) return hipErrorInvalidValue;
-    // narrow regions (fewer 128-wide tiles than half the CUs) use 64 tiles
-    const bool narrow = (M < 2 * 128 || N < 2 * 128) ||
-                        ((int64_t)((M + 127) / 128) * ((N + 127) / 128) < (int64_t)cu_count() / 2);
+    const int shape = update_shape(M, N, reserve_cus);
+    const bool narrow = shape == FF_UPD_SHAPE_64;
     for (int k0 = 0; k0 < K; k0 += kc) {
         const int Kc = (K - k0 < kc) ? K - k0 : kc;
         const T* Xk = X + (int64_t)k0 * ldx;
@@ -498,7 +506,7 @@ hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int
             int nwg = g.nslots;
             if (max_cus > 0 && nwg > 4 * max_cus) nwg = 4 * max_cus;     // four 64-tile workgroups fit a CU
             e = launch_wide<T, 32, 2>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
-        } else if (reserve_cus > 0) {
+        } else if (shape == FF_UPD_SHAPE_256x128) {
             // one workgroup per CU on all but reserve_cus CUs
             const Grid g = make_grid(256, 128, 4, 8, M, N, lower, shift);
             int nwg = update_workers(reserve_cus);
