@@ -34,9 +34,21 @@ EXPORTED = (
     "ff_lu_workspace_size", "lu_nopiv_factor", "ff_solve_workspace_size", "chol_solve",
     "ff_trisolve_workspace_size", "chol_trisolve", "ff_update_syrk", "ff_update_gemm",
     "ff_update_profile_enable", "ff_update_profile_read",
+    "ff_server_create", "ff_server_destroy", "ff_server_submit", "ff_server_step", "ff_server_poll",
+    "ff_server_get_stats",
 )
 
 UPD_SHAPES = ("64x64", "128x128", "256x128")   # FF_UPD_SHAPE_* order
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("info", ctypes.c_int32), ("cache_hit", ctypes.c_int32),
+                ("latency_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "steps", "grouped_launches", "cache_hits",
+                                              "evictions", "arena_free", "resident_factors", "queued", "active")]
 
 
 class KernelProfile(ctypes.Structure):
@@ -99,6 +111,19 @@ def load():
     lib.ff_update_profile_enable.restype = i32
     lib.ff_update_profile_read.argtypes = [ctypes.POINTER(KernelProfile)]
     lib.ff_update_profile_read.restype = i32
+    lib.ff_server_create.argtypes = [vp, sz, vp, ctypes.POINTER(i32)]
+    lib.ff_server_create.restype = vp
+    lib.ff_server_destroy.argtypes = [vp]
+    lib.ff_server_destroy.restype = i32
+    lib.ff_server_submit.argtypes = [vp, ctypes.c_uint64, i64, vp, i64, vp, i64, i64, vp, i64,
+                                     ctypes.POINTER(i64)]
+    lib.ff_server_submit.restype = i32
+    lib.ff_server_step.argtypes = [vp]
+    lib.ff_server_step.restype = i32
+    lib.ff_server_poll.argtypes = [vp, ctypes.POINTER(ServerResult), i32, ctypes.POINTER(i32)]
+    lib.ff_server_poll.restype = i32
+    lib.ff_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.ff_server_get_stats.restype = i32
     _lib = lib
     return lib
 
@@ -287,3 +312,73 @@ def update_profile_read() -> dict:
     _check(load().ff_update_profile_read(out), "ff_update_profile_read")
     return {UPD_SHAPES[i]: {"launches": int(out[i].launches), "total_ms": float(out[i].total_ms),
                             "total_flops": float(out[i].total_flops)} for i in range(3)}
+
+
+class Server:
+    """Continuous-batching solver (ff_server_*): many independent binary64 SPD
+    systems, every admitted factorisation advanced one block per step() with
+    grouped launches; finished factors stay resident under their key.
+
+    arena: a device tensor whose storage is the HBM budget (kept alive here).
+    Tensors passed to submit() are kept alive until their request is polled."""
+
+    def __init__(self, arena: torch.Tensor, stream=None):
+        self._lib = load()
+        self.arena = arena
+        self.stream = stream if stream is not None else torch.cuda.current_stream(arena.device)
+        st = ctypes.c_int(0)
+        h = self._lib.ff_server_create(_ptr(arena), arena.numel() * arena.element_size(), _stream(self.stream),
+                                       ctypes.byref(st))
+        if not h:
+            raise FastFactError(f"ff_server_create failed: {st.value} ({status_string(st.value)})")
+        self._h = ctypes.c_void_p(h)
+        self._keep = {}
+
+    def submit(self, A: torch.Tensor, B: torch.Tensor, X: torch.Tensor, key: int = 0) -> int:
+        """A: n x n column-major float64 (lower triangle read); B, X: n x nrhs column-major."""
+        n = int(A.shape[0])
+        for name, T in (("A", A), ("B", B), ("X", X)):
+            if T.dtype != torch.float64 or not T.is_cuda:
+                raise ValueError(f"{name} must be a float64 device tensor")
+        if A.shape[1] != n or B.shape[0] != n or tuple(X.shape) != tuple(B.shape):
+            raise ValueError("A must be n x n and B, X n x nrhs")
+        rid = ctypes.c_int64(0)
+        rc = self._lib.ff_server_submit(self._h, int(key), n, _ptr(A), _ld(A, "A"), _ptr(B), int(B.shape[1]),
+                                        _ld(B, "B"), _ptr(X), _ld(X, "X"), ctypes.byref(rid))
+        _check(rc, "ff_server_submit")
+        self._keep[rid.value] = (A, B, X)
+        return rid.value
+
+    def step(self) -> int:
+        rc = self._lib.ff_server_step(self._h)
+        if rc < 0:
+            _check(rc, "ff_server_step")
+        return rc
+
+    def poll(self, max_out: int = 256) -> list:
+        out = (ServerResult * max_out)()
+        k = ctypes.c_int(0)
+        _check(self._lib.ff_server_poll(self._h, out, max_out, ctypes.byref(k)), "ff_server_poll")
+        res = []
+        for i in range(k.value):
+            r = out[i]
+            self._keep.pop(r.id, None)
+            res.append({"id": r.id, "info": r.info, "cache_hit": bool(r.cache_hit), "latency_ms": r.latency_ms})
+        return res
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.ff_server_get_stats(self._h, ctypes.byref(st)), "ff_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ff_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

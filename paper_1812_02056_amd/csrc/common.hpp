@@ -104,6 +104,15 @@ template <typename T> __device__ __forceinline__ void buf_store(rsrc_t r, int of
 }
 constexpr int AUX_NT = 2;
 
+// Row i of the packed triangle index t = i(i+1)/2 + j (0 <= j <= i): a float
+// estimate corrected by one step either way (exact for t < 2^20).
+__device__ __forceinline__ int tri_row(int t) {
+    int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    if ((i + 1) * (i + 2) / 2 <= t) ++i;
+    if (i * (i + 1) / 2 > t) --i;
+    return i;
+}
+
 // Grid geometry of the update kernels: output tiles grouped into square
 // super-tiles (8 x 8 tiles for square tiles); every XCD of the chip (workgroups
 // are dealt to the 8 XCDs round-robin) works through whole super-tiles so the

@@ -40,6 +40,41 @@ hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc,
 hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc, const double* X, int64_t ldx,
                                            const double* Y, int64_t ldy, const int* info, hipStream_t st);
 
+// Job tables of the grouped (many-matrix) kernels, device resident.
+//   GroupDiag: factor the w x w block at a (binary64, w <= LDS_DIAG_MAX).
+//   GroupTrsm: solve the m x w panel x against the factored block t (both with
+//              leading dimension ld); workgroups [wg_begin, wg_begin + nwg).
+//   GroupUpd:  c -= p p^T on the lower triangle of the m x m square c, p m x w;
+//              lower-triangle 128 x 128 tiles [tiles_begin, tiles_begin + tiles).
+struct GroupDiag {
+    double* a;
+    int64_t ld;
+    int w;
+    int col_base;
+    int* info;
+};
+struct GroupTrsm {
+    double* x;
+    const double* t;
+    int64_t ld;
+    int m, w;
+    int wg_begin, nwg;
+    const int* info;
+};
+struct GroupUpd {
+    double* c;
+    const double* p;
+    int64_t ld;
+    int m, w;
+    int tiles_begin;
+    const int* info;
+};
+hipError_t launch_potrf_grouped(int njobs, const GroupDiag* d_jobs, hipStream_t st);
+hipError_t launch_trsm_grouped(int njobs, int total_wg, const GroupTrsm* d_jobs, hipStream_t st);
+int trsm_rows_per_wg();
+hipError_t launch_update_grouped(int njobs, int total_tiles, const GroupUpd* d_jobs, hipStream_t st);
+int grouped_update_tile();
+
 // Diagonal factorisations and panel solves (panel.hip).
 template <typename S>
 hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, int* info, int col_base, hipStream_t st);

@@ -245,22 +245,12 @@ constexpr int PT = 1024;
 
 __device__ __forceinline__ int ltile(int i, int j) { return (i * (i + 1) / 2 + j) * 256; }
 
-// Row i of the packed triangle index t = i(i+1)/2 + j (0 <= j <= i): a float
-// estimate corrected by one step either way (exact for t < 2^20).
-__device__ __forceinline__ int tri_row(int t) {
-    int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-    if ((i + 1) * (i + 2) / 2 <= t) ++i;
-    if (i * (i + 1) / 2 > t) --i;
-    return i;
-}
-
 // Tiles staged per thread per batch: that many global loads are in flight at
 // once, where a loop of one element per iteration would wait on each in turn.
 constexpr int STG = 8;
 
 template <typename S>
-__global__ __launch_bounds__(PT)
-void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int col_base)
+__device__ __forceinline__ void potrf_block(int w, S* __restrict__ blk, int64_t ldb, int* info, int col_base)
 {
     if (*info != 0) return;
     __shared__ double tl[LDS_NTILE * 256];
@@ -356,6 +346,13 @@ void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int co
     }
 }
 
+template <typename S>
+__global__ __launch_bounds__(PT)
+void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int col_base)
+{
+    potrf_block<S>(w, blk, ldb, info, col_base);
+}
+
 // ---------------------------------------------------------------------------
 // Triangular solve X T = B in place (X overwrites B), T upper triangular w x w
 // (w <= TRSM_MAX): row by row, x_j = (b_j - sum_{k<j} x_k T(k, j)) / T(j, j)
@@ -373,10 +370,10 @@ void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int co
 constexpr int TRSM_TMAX = TRSM_MAX / DT;
 constexpr int TRSM_NT = 512;
 
+// Workgroup wg of nwg solving one panel (the row-block loop strides by nwg).
 template <typename T, bool XCOL>
-__global__ __launch_bounds__(TRSM_NT)
-void trsm_reg_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* __restrict__ t, int64_t tk,
-                     int64_t tj, int unit, const int* info)
+__device__ __forceinline__ void trsm_block(int m, int w, T* x, int64_t xi, int64_t xj, const T* __restrict__ t,
+                                           int64_t tk, int64_t tj, int unit, const int* info, int wg, int nwg)
 {
     if (info && *info != 0) return;
     typedef acc_traits<T> AT;
@@ -435,7 +432,7 @@ void trsm_reg_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* __rest
     // Each wave walks 16-row blocks grid-stride; T stays staged for all of them.
     const int b = lane & 15;
     constexpr int SZ = sizeof(T);
-    for (int r0 = (blockIdx.x * (TRSM_NT / 64) + wave) * DT; r0 < m; r0 += gridDim.x * (TRSM_NT / 64) * DT) {
+    for (int r0 = (wg * (TRSM_NT / 64) + wave) * DT; r0 < m; r0 += nwg * (TRSM_NT / 64) * DT) {
         const int row = r0 + b;
         const bool rok = row < m;
         V xr[TRSM_TMAX];
@@ -495,6 +492,38 @@ void trsm_reg_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* __rest
     }
 }
 
+template <typename T, bool XCOL>
+__global__ __launch_bounds__(TRSM_NT)
+void trsm_reg_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* __restrict__ t, int64_t tk,
+                     int64_t tj, int unit, const int* info)
+{
+    trsm_block<T, XCOL>(m, w, x, xi, xj, t, tk, tj, unit, info, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped forms for many independent factorisations at once (serving): one
+// launch covers the diagonal blocks, or the panel solves, of every job.
+__global__ __launch_bounds__(PT)
+void potrf_grouped_kernel(const GroupDiag* __restrict__ jobs)
+{
+    const GroupDiag jb = jobs[blockIdx.x];
+    potrf_block<double>(jb.w, jb.a, jb.ld, jb.info, jb.col_base);
+}
+
+__global__ __launch_bounds__(TRSM_NT)
+void trsm_grouped_kernel(const GroupTrsm* __restrict__ jobs, int njobs)
+{
+    // the job whose workgroup range holds this workgroup
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg_begin <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const GroupTrsm jb = jobs[lo];
+    trsm_block<double, true>(jb.m, jb.w, jb.x, 1, jb.ld, jb.t, jb.ld, 1, 0, jb.info, blockIdx.x - jb.wg_begin, jb.nwg);
+}
+
 }  // namespace
 
 hipError_t launch_set_int(int* p, int v, hipStream_t st) {
@@ -535,6 +564,20 @@ hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, i
                            tj, unit, info);
     return hipGetLastError();
 }
+
+hipError_t launch_potrf_grouped(int njobs, const GroupDiag* d_jobs, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(potrf_grouped_kernel, dim3(njobs), dim3(PT), 0, st, d_jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_grouped(int njobs, int total_wg, const GroupTrsm* d_jobs, hipStream_t st) {
+    if (njobs <= 0 || total_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(trsm_grouped_kernel, dim3(total_wg), dim3(TRSM_NT), 0, st, d_jobs, njobs);
+    return hipGetLastError();
+}
+
+int trsm_rows_per_wg() { return TRSM_NT / 4; }
 
 template hipError_t launch_potrf_diag<double>(int, double*, int64_t, int*, int, hipStream_t);
 template hipError_t launch_potrf_diag<float>(int, float*, int64_t, int*, int, hipStream_t);

@@ -1,0 +1,440 @@
+// serve.hip -- continuous batching of many independent SPD solves.
+//
+// Each request is Algorithm 1 of arXiv 1812.02056 (Sec. 2) on its own matrix,
+// followed by the two triangular solves.  The server keeps every admitted
+// factorisation in flight at once: one scheduler iteration (ff_server_step)
+// advances each of them by one block of s columns with three grouped launches
+// (diagonal factorisations, panel solves, trailing updates of all active
+// matrices), and starts the solves of the factorisations that finished.
+// Factors live in a caller-provided device arena (the HBM budget); a finished
+// factor stays resident under its key, so a later request for the same matrix
+// skips the factorisation.  Admission is first come, first served, by arena
+// space, evicting least recently used resident factors that no request holds.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <list>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "fastfact.h"
+#include "internal.hpp"
+
+namespace ff {
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_ACTIVE = 512;      // admitted requests (job-table capacity)
+constexpr int RING = 4;              // job-table slots in flight
+
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// First-fit allocator over [0, size) with coalescing on free.
+struct Arena {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    void init(size_t n) {
+        size = n;
+        free_.clear();
+        if (n) free_[0] = n;
+    }
+    bool alloc(size_t n, size_t& off) {
+        n = align_up(n ? n : 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                off = it->first;
+                const size_t rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = align_up(n ? n : 1);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Factor {            // a factor buffer in the arena
+    uint64_t key;
+    int n;
+    size_t off, bytes;
+    int users = 0;         // requests that read or write it
+    bool ready = false;    // factorisation finished (enqueued)
+    bool dead = false;     // failed or unkeyed: freed when the last user is done
+    int info_slot = -1;
+};
+
+enum State { QUEUED, FACTOR, WAIT_FACTOR, SOLVE, DONE };
+
+struct Request {
+    int64_t id;
+    uint64_t key;
+    int n, nrhs;
+    const double* A;
+    int64_t lda;
+    const double* B;
+    int64_t ldb;
+    double* X;
+    int64_t ldx;
+    State st = QUEUED;
+    Factor* f = nullptr;
+    bool owner = false;    // this request computes f
+    int s = 0, c0 = 0;
+    size_t ws_off = 0, ws_bytes = 0;
+    hipEvent_t t_arrive = nullptr, t_done = nullptr;
+    bool hit = false;
+};
+
+int default_step(int n) {
+    const int s = (int)std::lround(std::pow((double)n, 0.5286));
+    return std::max(1, std::min(s, LDS_DIAG_MAX));
+}
+
+}  // namespace
+}  // namespace ff
+
+using namespace ff;
+
+struct ff_server {
+    hipStream_t st = nullptr;      // all server work
+    hipStream_t clock = nullptr;   // idle stream: arrival stamps
+    char* base = nullptr;
+    Arena arena;
+    std::list<Request*> queue;     // not yet admitted
+    std::vector<Request*> active;
+    std::list<Factor*> resident;   // ready keyed factors, front = most recently used
+    std::map<uint64_t, Factor*> by_key;
+    std::vector<Factor*> factors;  // every live factor
+    int64_t next_id = 1;
+    // info words: device and a pinned host mirror
+    int* d_info = nullptr;
+    int* h_info = nullptr;
+    std::vector<int> free_info;
+    // job tables: pinned host + device, RING slots
+    void* h_tab[RING] = {};
+    void* d_tab[RING] = {};
+    hipEvent_t tab_ev[RING] = {};
+    int tab_used[RING] = {};
+    int64_t steps = 0;
+    ff_server_stats stats{};
+};
+
+namespace {
+
+constexpr size_t TAB_BYTES = MAX_ACTIVE * (sizeof(GroupDiag) + sizeof(GroupTrsm) + sizeof(GroupUpd)) + 3 * ALIGN;
+
+void drop_factor(ff_server* s, Factor* f) {
+    s->arena.release(f->off, f->bytes);
+    if (f->info_slot >= 0) s->free_info.push_back(f->info_slot);
+    if (f->key) {
+        auto it = s->by_key.find(f->key);
+        if (it != s->by_key.end() && it->second == f) s->by_key.erase(it);
+    }
+    s->resident.remove(f);
+    s->factors.erase(std::remove(s->factors.begin(), s->factors.end(), f), s->factors.end());
+    delete f;
+}
+
+// Space for n bytes, evicting unused resident factors, oldest first.
+bool make_room(ff_server* s, size_t bytes, size_t& off) {
+    while (!s->arena.alloc(bytes, off)) {
+        Factor* victim = nullptr;
+        for (auto it = s->resident.rbegin(); it != s->resident.rend(); ++it)
+            if ((*it)->users == 0) { victim = *it; break; }
+        if (!victim) return false;
+        drop_factor(s, victim);
+        s->stats.evictions++;
+    }
+    return true;
+}
+
+// Admit queued requests in arrival order while space allows.
+int admit(ff_server* s) {
+    while (!s->queue.empty() && (int)s->active.size() < MAX_ACTIVE) {
+        Request* r = s->queue.front();
+        const size_t ws = ff_trisolve_workspace_size(r->n, FF_F64);
+        Factor* f = nullptr;
+        bool owner = false;
+        auto it = r->key ? s->by_key.find(r->key) : s->by_key.end();
+        if (it != s->by_key.end() && it->second->n == r->n) {
+            f = it->second;
+        } else {
+            if (s->free_info.empty()) break;
+            f = new (std::nothrow) Factor{r->key, r->n, 0, (size_t)r->n * r->n * sizeof(double)};
+            if (!f) return FF_ERR_HIP;
+            owner = true;
+        }
+        size_t ws_off = 0, f_off = 0;
+        f->users++;                       // keep it from being evicted below
+        if (owner && !make_room(s, f->bytes, f_off)) { f->users--; delete f; break; }
+        if (owner) {
+            f->off = f_off;
+            s->factors.push_back(f);
+        }
+        if (!make_room(s, ws, ws_off)) {
+            f->users--;
+            if (owner) {
+                s->arena.release(f->off, f->bytes);
+                s->factors.pop_back();
+                delete f;
+            }
+            break;
+        }
+        s->queue.pop_front();
+        r->f = f;
+        r->owner = owner;
+        r->ws_off = ws_off;
+        r->ws_bytes = ws;
+        if (owner) {
+            f->info_slot = s->free_info.back();
+            s->free_info.pop_back();
+            if (f->key) s->by_key[f->key] = f;
+            // the factor starts as a copy of A (lower triangle read), info = 0
+            double* L = reinterpret_cast<double*>(s->base + f->off);
+            if (hipMemcpy2DAsync(L, (size_t)r->n * sizeof(double), r->A, (size_t)r->lda * sizeof(double),
+                                 (size_t)r->n * sizeof(double), r->n, hipMemcpyDeviceToDevice, s->st) != hipSuccess ||
+                launch_set_int(s->d_info + f->info_slot, 0, s->st) != hipSuccess)
+                return FF_ERR_HIP;
+            r->st = FACTOR;
+            r->s = default_step(r->n);
+            r->c0 = 0;
+        } else {
+            r->hit = true;
+            r->st = f->ready ? SOLVE : WAIT_FACTOR;
+            if (f->ready) {
+                s->resident.remove(f);
+                s->resident.push_front(f);
+            }
+            s->stats.cache_hits++;
+        }
+        s->active.push_back(r);
+    }
+    return 0;
+}
+
+int launch_solve(ff_server* s, Request* r) {
+    const double* L = reinterpret_cast<const double*>(s->base + r->f->off);
+    if (hipMemcpy2DAsync(r->X, (size_t)r->ldx * sizeof(double), r->B, (size_t)r->ldb * sizeof(double),
+                         (size_t)r->n * sizeof(double), r->nrhs, hipMemcpyDeviceToDevice, s->st) != hipSuccess)
+        return FF_ERR_HIP;
+    const int rc = chol_trisolve(r->n, r->nrhs, L, r->n, FF_F64, r->X, r->ldx, s->base + r->ws_off, r->ws_bytes, s->st);
+    if (rc) return rc;
+    if (hipEventRecord(r->t_done, s->st) != hipSuccess) return FF_ERR_HIP;
+    r->st = DONE;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+ff_server* ff_server_create(void* arena, size_t arena_bytes, void* stream, int* status) {
+    int rc = 0;
+    ff_server* s = new (std::nothrow) ff_server();
+    if (!s) rc = FF_ERR_HIP;
+    if (!rc && arena_bytes > 0 && arena == nullptr) rc = -1;
+    if (!rc) {
+        s->st = static_cast<hipStream_t>(stream);
+        s->base = static_cast<char*>(arena);
+        s->arena.init(arena_bytes);
+        if (hipStreamCreateWithFlags(&s->clock, hipStreamNonBlocking) != hipSuccess ||
+            hipMalloc(&s->d_info, MAX_ACTIVE * sizeof(int)) != hipSuccess ||
+            hipHostMalloc(&s->h_info, MAX_ACTIVE * sizeof(int)) != hipSuccess)
+            rc = FF_ERR_HIP;
+        for (int i = 0; !rc && i < RING; ++i)
+            if (hipHostMalloc(&s->h_tab[i], TAB_BYTES) != hipSuccess || hipMalloc(&s->d_tab[i], TAB_BYTES) != hipSuccess ||
+                hipEventCreateWithFlags(&s->tab_ev[i], hipEventDisableTiming) != hipSuccess)
+                rc = FF_ERR_HIP;
+        for (int i = MAX_ACTIVE - 1; i >= 0; --i) s->free_info.push_back(i);
+    }
+    if (status) *status = rc;
+    if (rc && s) {
+        ff_server_destroy(s);
+        return nullptr;
+    }
+    return s;
+}
+
+int ff_server_destroy(ff_server* s) {
+    if (!s) return 0;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    for (Request* r : s->active) { (void)hipEventDestroy(r->t_arrive); (void)hipEventDestroy(r->t_done); delete r; }
+    for (Request* r : s->queue) { (void)hipEventDestroy(r->t_arrive); (void)hipEventDestroy(r->t_done); delete r; }
+    for (Factor* f : s->factors) delete f;
+    for (int i = 0; i < RING; ++i) {
+        if (s->h_tab[i]) (void)hipHostFree(s->h_tab[i]);
+        if (s->d_tab[i]) (void)hipFree(s->d_tab[i]);
+        if (s->tab_ev[i]) (void)hipEventDestroy(s->tab_ev[i]);
+    }
+    if (s->d_info) (void)hipFree(s->d_info);
+    if (s->h_info) (void)hipHostFree(s->h_info);
+    if (s->clock) (void)hipStreamDestroy(s->clock);
+    delete s;
+    return 0;
+}
+
+int ff_server_submit(ff_server* s, uint64_t key, int64_t n, const double* A, int64_t lda, const double* B,
+                     int64_t nrhs, int64_t ldb, double* X, int64_t ldx, int64_t* req_id) {
+    if (!s) return -1;
+    if (n < 1 || n > 65536) return -3;
+    if (!A) return -4;
+    if (lda < n) return -5;
+    if (!B) return -6;
+    if (nrhs < 1) return -7;
+    if (ldb < n) return -8;
+    if (!X) return -9;
+    if (ldx < n) return -10;
+    const size_t need = align_up((size_t)n * n * sizeof(double)) + align_up(ff_trisolve_workspace_size(n, FF_F64));
+    if (need > s->arena.size) return FF_ERR_WORKSPACE;
+    Request* r = new (std::nothrow) Request();
+    if (!r) return FF_ERR_HIP;
+    *r = Request{s->next_id++, key, (int)n, (int)nrhs, A, lda, B, ldb, X, ldx};
+    if (hipEventCreate(&r->t_arrive) != hipSuccess || hipEventCreate(&r->t_done) != hipSuccess ||
+        hipEventRecord(r->t_arrive, s->clock) != hipSuccess) {
+        delete r;
+        return FF_ERR_HIP;
+    }
+    s->queue.push_back(r);
+    s->stats.submitted++;
+    if (req_id) *req_id = r->id;
+    return 0;
+}
+
+int ff_server_step(ff_server* s) {
+    if (!s) return -1;
+    // a job-table slot is reused only after the step that last used it has run
+    const int slot = (int)(s->steps % RING);
+    if (s->tab_used[slot] && hipEventSynchronize(s->tab_ev[slot]) != hipSuccess) return FF_ERR_HIP;
+    int rc = admit(s);
+    if (rc) return rc;
+
+    // requests waiting on a factor another request computes
+    for (Request* r : s->active)
+        if (r->st == WAIT_FACTOR && r->f->ready) r->st = SOLVE;
+
+    // one block step of every active factorisation, three grouped launches
+    char* h = static_cast<char*>(s->h_tab[slot]);
+    char* d = static_cast<char*>(s->d_tab[slot]);
+    GroupDiag* hd = reinterpret_cast<GroupDiag*>(h);
+    GroupTrsm* ht = reinterpret_cast<GroupTrsm*>(h + align_up(MAX_ACTIVE * sizeof(GroupDiag)));
+    GroupUpd* hu = reinterpret_cast<GroupUpd*>(h + align_up(MAX_ACTIVE * sizeof(GroupDiag)) +
+                                               align_up(MAX_ACTIVE * sizeof(GroupTrsm)));
+    int nd = 0, nt = 0, nu = 0, wg = 0, tiles = 0;
+    const int rows_wg = trsm_rows_per_wg(), ut = grouped_update_tile();
+    std::vector<Request*> stepped;
+    for (Request* r : s->active) {
+        if (r->st != FACTOR) continue;
+        const int n = r->n, c0 = r->c0, w = std::min(r->s, n - c0), m = n - c0 - w;
+        double* L = reinterpret_cast<double*>(s->base + r->f->off);
+        int* info = s->d_info + r->f->info_slot;
+        double* A11 = L + c0 + (int64_t)c0 * n;
+        hd[nd++] = GroupDiag{A11, n, w, c0, info};
+        if (m > 0) {
+            double* A21 = L + (c0 + w) + (int64_t)c0 * n;
+            const int nwg = std::min((m + rows_wg - 1) / rows_wg, 64);
+            ht[nt++] = GroupTrsm{A21, A11, n, m, w, wg, nwg, info};
+            wg += nwg;
+            const int nb = (m + ut - 1) / ut;
+            hu[nu++] = GroupUpd{L + (c0 + w) + (int64_t)(c0 + w) * n, A21, n, m, w, tiles, info};
+            tiles += nb * (nb + 1) / 2;
+        }
+        stepped.push_back(r);
+    }
+    if (nd > 0) {
+        if (hipMemcpyAsync(d, h, TAB_BYTES, hipMemcpyHostToDevice, s->st) != hipSuccess) return FF_ERR_HIP;
+        const GroupDiag* dd = reinterpret_cast<const GroupDiag*>(d);
+        const GroupTrsm* dt = reinterpret_cast<const GroupTrsm*>(d + align_up(MAX_ACTIVE * sizeof(GroupDiag)));
+        const GroupUpd* du = reinterpret_cast<const GroupUpd*>(d + align_up(MAX_ACTIVE * sizeof(GroupDiag)) +
+                                                               align_up(MAX_ACTIVE * sizeof(GroupTrsm)));
+        if (launch_potrf_grouped(nd, dd, s->st) != hipSuccess || launch_trsm_grouped(nt, wg, dt, s->st) != hipSuccess ||
+            launch_update_grouped(nu, tiles, du, s->st) != hipSuccess)
+            return FF_ERR_HIP;
+        s->stats.grouped_launches += 3;
+    }
+    for (Request* r : stepped) {
+        r->c0 += std::min(r->s, r->n - r->c0);
+        if (r->c0 >= r->n) {
+            // factor finished: its info word goes to the host mirror, then the solve
+            if (hipMemcpyAsync(s->h_info + r->f->info_slot, s->d_info + r->f->info_slot, sizeof(int),
+                               hipMemcpyDeviceToHost, s->st) != hipSuccess)
+                return FF_ERR_HIP;
+            r->f->ready = true;
+            if (r->f->key) s->resident.push_front(r->f);
+            else r->f->dead = true;
+            r->st = SOLVE;
+        }
+    }
+    for (Request* r : s->active)
+        if (r->st == SOLVE && (rc = launch_solve(s, r)) != 0) return rc;
+    if (hipEventRecord(s->tab_ev[slot], s->st) != hipSuccess) return FF_ERR_HIP;
+    s->tab_used[slot] = 1;
+    s->steps++;
+    s->stats.steps = s->steps;
+    int inflight = 0;
+    for (Request* r : s->active) inflight += r->st != DONE;
+    return inflight + (int)s->queue.size();
+}
+
+int ff_server_poll(ff_server* s, ff_server_result* out, int max_out, int* n_out) {
+    if (!s) return -1;
+    if (max_out < 0 || (max_out > 0 && !out)) return -2;
+    int k = 0;
+    for (size_t i = 0; i < s->active.size() && k < max_out;) {
+        Request* r = s->active[i];
+        if (r->st != DONE || hipEventQuery(r->t_done) != hipSuccess) { ++i; continue; }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, r->t_arrive, r->t_done);
+        Factor* f = r->f;
+        const int info = s->h_info[f->info_slot];
+        out[k++] = ff_server_result{r->id, info, r->hit ? 1 : 0, (double)ms};
+        s->arena.release(r->ws_off, r->ws_bytes);
+        f->users--;
+        if (info != 0 && !f->dead) {
+            // a failed factor is never served again
+            f->dead = true;
+            s->resident.remove(f);
+            auto it = s->by_key.find(f->key);
+            if (it != s->by_key.end() && it->second == f) s->by_key.erase(it);
+        }
+        if (f->dead && f->users == 0) drop_factor(s, f);
+        (void)hipEventDestroy(r->t_arrive);
+        (void)hipEventDestroy(r->t_done);
+        delete r;
+        s->active.erase(s->active.begin() + i);
+        s->stats.completed++;
+    }
+    if (n_out) *n_out = k;
+    return 0;
+}
+
+int ff_server_get_stats(ff_server* s, ff_server_stats* out) {
+    if (!s || !out) return -1;
+    *out = s->stats;
+    size_t fr = 0;
+    for (auto& kv : s->arena.free_) fr += kv.second;
+    out->arena_free = (int64_t)fr;
+    out->resident_factors = (int64_t)s->resident.size();
+    out->queued = (int64_t)s->queue.size();
+    out->active = (int64_t)s->active.size();
+    return 0;
+}
+
+}  // extern "C"

@@ -101,12 +101,22 @@ __device__ __forceinline__ bool tile_of_slot(const Grid& g, int slot, bool lower
 template <typename T> struct wide_depth { static constexpr int BK = 16; };
 template <> struct wide_depth<float> { static constexpr int BK = 32; };
 
+template <typename T, int WW, int WMW>
+struct wide_cfg {
+    static constexpr int TM = WW * WMW, TN = 2 * WW;
+    static constexpr int BK = wide_depth<T>::BK;
+};
+
+// One output tile (bi, bj) of C -= X Y^T: the whole K loop and the fused
+// write-back.  Shared by the single-region and the grouped kernels; ends with a
+// barrier so the caller may start another tile on the same LDS buffers.
 template <typename T, int WW, int WMW, bool YROWS, bool LOWER>
-__global__ __launch_bounds__(128 * WMW, 4 / WMW)
-void update_wide_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, const T* __restrict__ X, int64_t ldx,
-                        const T* __restrict__ Y, int64_t ldy, Grid g, const int* __restrict__ info)
+__device__ __forceinline__ void wide_tile(int M, int N, int K, T* __restrict__ C, int64_t ldc,
+                                          const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y,
+                                          int64_t ldy, int shift, int bi, int bj,
+                                          T (&As)[2][wide_cfg<T, WW, WMW>::BK][wide_cfg<T, WW, WMW>::TM],
+                                          T (&Bs)[2][wide_cfg<T, WW, WMW>::BK][wide_cfg<T, WW, WMW>::TN])
 {
-    if (info && *info != 0) return;
     constexpr int TM = WW * WMW, TN = 2 * WW;
     constexpr int NTH = 128 * WMW;
     constexpr int BK = wide_depth<T>::BK;
@@ -118,9 +128,6 @@ void update_wide_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, con
     constexpr int NB = WW / 16;                   // MFMA blocks per wave edge
     typedef acc_traits<T> AT;
     typedef typename AT::vec V;
-
-    __shared__ T As[2][BK][TM];   // row operand X(row0 + r, k)    stored [k][r]
-    __shared__ T Bs[2][BK][TN];   // column operand Y(col0 + c, k) stored [k][c]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -135,160 +142,195 @@ void update_wide_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, con
     const int nk = (K + BK - 1) / BK;
     const int xs = (int)ldx * SZ, ys = (int)ldy * SZ;
 
+    const int row0 = bi * TM, col0 = bj * TN;
+    const int mrem = M - row0, nrem = N - col0;
+    const bool active = !LOWER || (row0 + WW * wr + WW - 1) - (col0 + WW * wc) >= shift;
+    const int vx = sxr < mrem ? sxr * SZ : BUF_OOB;
+    const int vy = YROWS ? (syr < nrem ? syr * SZ : BUF_OOB) : (yc < nrem ? yc * ys : BUF_OOB);
+    const T* Xt = X + row0;
+    const T* Yt = YROWS ? Y + col0 : Y + (int64_t)col0 * ldy;
+
+    // Stage kt: a resource starting at K column kt*BK whose record count ends
+    // at column K, so K columns past the end read zero; rows past M read zero
+    // through vx / vy.
+    T xa[NLX], ya[NLY];
+    auto load = [&](int kt) {
+        const int k0 = kt * BK;
+        const int kv = K - k0 > 0 ? K - k0 : 0;
+        const rsrc_t rx = make_rsrc_n(Xt + (int64_t)k0 * ldx, kv * xs);
+#pragma unroll
+        for (int q = 0; q < NLX; ++q) xa[q] = buf_load<T>(rx, vx, (sxk + XSTEP * q) * xs);
+        if (YROWS) {
+            const rsrc_t ry = make_rsrc_n(Yt + (int64_t)k0 * ldy, kv * ys);
+#pragma unroll
+            for (int q = 0; q < NLY; ++q) ya[q] = buf_load<T>(ry, vy, (syk + YSTEP * q) * ys);
+        } else {
+            const rsrc_t ry = make_rsrc(Yt + k0);
+#pragma unroll
+            for (int e = 0; e < NLY; ++e) ya[e] = buf_load<T>(ry, yk0 + e < kv ? vy + (yk0 + e) * SZ : BUF_OOB, 0);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NLX; ++q) As[buf][sxk + XSTEP * q][sxr] = xa[q];
+        if (YROWS) {
+#pragma unroll
+            for (int q = 0; q < NLY; ++q) Bs[buf][syk + YSTEP * q][syr] = ya[q];
+        } else {
+#pragma unroll
+            for (int e = 0; e < NLY; ++e) Bs[buf][yk0 + e][yc] = ya[e];
+        }
+    };
+
+    V acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = zero_vec<V>();
+
+    // fa: column-operand fragments (the MFMA A input), fb: row-operand
+    // fragments; the product tile is the transposed one (lanes along rows).
+    auto frags = [&](int buf, int k4, T (&fa)[NB], T (&fb)[NB]) {
+        const int kk = 4 * k4 + (lane >> 4);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) fa[b] = Bs[buf][kk][WW * wc + 16 * b + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) fb[b] = As[buf][kk][WW * wr + 16 * b + (lane & 15)];
+    };
+    auto mma = [&](const T (&fa)[NB], const T (&fb)[NB]) {
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+            for (int r4 = 0; r4 < NB; ++r4) acc[cb][r4] = AT::mfma(fa[cb], fb[r4], acc[cb][r4]);
+    };
+    auto compute_full = [&](int buf) {
+        T fa0[NB], fb0[NB], fa1[NB], fb1[NB];
+        frags(buf, 0, fa0, fb0);
+#pragma unroll
+        for (int k4 = 0; k4 < BK / 4; k4 += 2) {
+            frags(buf, k4 + 1, fa1, fb1);
+            mma(fa0, fb0);
+            if (k4 + 2 < BK / 4) frags(buf, k4 + 2, fa0, fb0);
+            mma(fa1, fb1);
+        }
+    };
+    auto compute_tail = [&](int buf, int nk4) {
+#pragma unroll
+        for (int k4 = 0; k4 < BK / 4; ++k4) {
+            if (k4 < nk4) {
+                T fa[NB], fb[NB];
+                frags(buf, k4, fa, fb);
+                mma(fa, fb);
+            }
+        }
+    };
+
+    load(0);
+    store(0);
+    __syncthreads();
+    // No branch around the MFMAs: a conditional compute lets the compiler sink
+    // the next stage's loads below it, next to their LDS stores, which exposes
+    // the full load latency every stage.  Waves wholly outside the written
+    // region (diagonal tiles only) compute and discard.
+    for (int kt = 0; kt + 1 < nk; ++kt) {
+        load(kt + 1);
+        compute_full(kt & 1);
+        store((kt + 1) & 1);
+        __syncthreads();
+    }
+    compute_tail((nk - 1) & 1, (K - (nk - 1) * BK + 3) / 4);
+
+    if (active) {
+        // Write-back C - S.  Lane part of the offset in a register, the block
+        // column in the scalar offset, the block row in the immediate.  Tiles
+        // on an edge or crossing the written region's boundary mask each entry.
+        const rsrc_t rc = make_rsrc(C + row0 + (int64_t)col0 * ldc);
+        const int li0 = WW * wr + (lane & 15);
+        const int lj0 = WW * wc + AT::col_lane(lane);
+        const int cs = (int)ldc * SZ;
+        const int cbase = (li0 + lj0 * (int)ldc) * SZ;
+        const bool full = mrem >= TM && nrem >= TN && (!LOWER || row0 - (col0 + TN - 1) >= shift);
+        if (full) {
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                T cv[NB][4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int r4 = 0; r4 < NB; ++r4)
+                        cv[r4][r] = bufop<T, AUX_NT>::load(rc, cbase + 16 * r4 * SZ, (16 * cb + AT::col_reg(r)) * cs);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int r4 = 0; r4 < NB; ++r4)
+                        bufop<T, AUX_NT>::store(rc, cbase + 16 * r4 * SZ, cv[r4][r] - acc[cb][r4][r],
+                                                (16 * cb + AT::col_reg(r)) * cs);
+            }
+        } else {
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                T cv[NB][4];
+                int off[NB][4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int r4 = 0; r4 < NB; ++r4) {
+                        const int li = li0 + 16 * r4;
+                        const int lj = lj0 + 16 * cb + AT::col_reg(r);
+                        const bool ok = li < mrem && lj < nrem && (!LOWER || (row0 + li) - (col0 + lj) >= shift);
+                        off[r4][r] = ok ? cbase + (16 * r4 + (16 * cb + AT::col_reg(r)) * (int)ldc) * SZ : BUF_OOB;
+                        cv[r4][r] = bufop<T, AUX_NT>::load(rc, off[r4][r], 0);
+                    }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int r4 = 0; r4 < NB; ++r4)
+                        bufop<T, AUX_NT>::store(rc, off[r4][r], cv[r4][r] - acc[cb][r4][r], 0);
+            }
+        }
+    }
+    __syncthreads();   // the next tile's first stage reuses buffer 0
+}
+
+template <typename T, int WW, int WMW, bool YROWS, bool LOWER>
+__global__ __launch_bounds__(128 * WMW, 4 / WMW)
+void update_wide_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, const T* __restrict__ X, int64_t ldx,
+                        const T* __restrict__ Y, int64_t ldy, Grid g, const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    typedef wide_cfg<T, WW, WMW> CF;
+    __shared__ T As[2][CF::BK][CF::TM];   // row operand X(row0 + r, k)    stored [k][r]
+    __shared__ T Bs[2][CF::BK][CF::TN];   // column operand Y(col0 + c, k) stored [k][c]
     for (int slot = blockIdx.x; slot < g.nslots; slot += gridDim.x) {
         int bi, bj;
         if (!tile_of_slot(g, slot, LOWER, bi, bj)) continue;
-        const int row0 = bi * TM, col0 = bj * TN;
-        const int mrem = M - row0, nrem = N - col0;
-        const bool active = !LOWER || (row0 + WW * wr + WW - 1) - (col0 + WW * wc) >= g.shift;
-        const int vx = sxr < mrem ? sxr * SZ : BUF_OOB;
-        const int vy = YROWS ? (syr < nrem ? syr * SZ : BUF_OOB) : (yc < nrem ? yc * ys : BUF_OOB);
-        const T* Xt = X + row0;
-        const T* Yt = YROWS ? Y + col0 : Y + (int64_t)col0 * ldy;
-
-        // Stage kt: a resource starting at K column kt*BK whose record count ends
-        // at column K, so K columns past the end read zero; rows past M read zero
-        // through vx / vy.
-        T xa[NLX], ya[NLY];
-        auto load = [&](int kt) {
-            const int k0 = kt * BK;
-            const int kv = K - k0 > 0 ? K - k0 : 0;
-            const rsrc_t rx = make_rsrc_n(Xt + (int64_t)k0 * ldx, kv * xs);
-#pragma unroll
-            for (int q = 0; q < NLX; ++q) xa[q] = buf_load<T>(rx, vx, (sxk + XSTEP * q) * xs);
-            if (YROWS) {
-                const rsrc_t ry = make_rsrc_n(Yt + (int64_t)k0 * ldy, kv * ys);
-#pragma unroll
-                for (int q = 0; q < NLY; ++q) ya[q] = buf_load<T>(ry, vy, (syk + YSTEP * q) * ys);
-            } else {
-                const rsrc_t ry = make_rsrc(Yt + k0);
-#pragma unroll
-                for (int e = 0; e < NLY; ++e) ya[e] = buf_load<T>(ry, yk0 + e < kv ? vy + (yk0 + e) * SZ : BUF_OOB, 0);
-            }
-        };
-        auto store = [&](int buf) {
-#pragma unroll
-            for (int q = 0; q < NLX; ++q) As[buf][sxk + XSTEP * q][sxr] = xa[q];
-            if (YROWS) {
-#pragma unroll
-                for (int q = 0; q < NLY; ++q) Bs[buf][syk + YSTEP * q][syr] = ya[q];
-            } else {
-#pragma unroll
-                for (int e = 0; e < NLY; ++e) Bs[buf][yk0 + e][yc] = ya[e];
-            }
-        };
-
-        V acc[NB][NB];
-#pragma unroll
-        for (int a = 0; a < NB; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) acc[a][b] = zero_vec<V>();
-
-        // fa: column-operand fragments (the MFMA A input), fb: row-operand
-        // fragments; the product tile is the transposed one (lanes along rows).
-        auto frags = [&](int buf, int k4, T (&fa)[NB], T (&fb)[NB]) {
-            const int kk = 4 * k4 + (lane >> 4);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) fa[b] = Bs[buf][kk][WW * wc + 16 * b + (lane & 15)];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) fb[b] = As[buf][kk][WW * wr + 16 * b + (lane & 15)];
-        };
-        auto mma = [&](const T (&fa)[NB], const T (&fb)[NB]) {
-#pragma unroll
-            for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-                for (int r4 = 0; r4 < NB; ++r4) acc[cb][r4] = AT::mfma(fa[cb], fb[r4], acc[cb][r4]);
-        };
-        auto compute_full = [&](int buf) {
-            T fa0[NB], fb0[NB], fa1[NB], fb1[NB];
-            frags(buf, 0, fa0, fb0);
-#pragma unroll
-            for (int k4 = 0; k4 < BK / 4; k4 += 2) {
-                frags(buf, k4 + 1, fa1, fb1);
-                mma(fa0, fb0);
-                if (k4 + 2 < BK / 4) frags(buf, k4 + 2, fa0, fb0);
-                mma(fa1, fb1);
-            }
-        };
-        auto compute_tail = [&](int buf, int nk4) {
-#pragma unroll
-            for (int k4 = 0; k4 < BK / 4; ++k4) {
-                if (k4 < nk4) {
-                    T fa[NB], fb[NB];
-                    frags(buf, k4, fa, fb);
-                    mma(fa, fb);
-                }
-            }
-        };
-
-        load(0);
-        store(0);
-        __syncthreads();
-        // No branch around the MFMAs: a conditional compute lets the compiler sink
-        // the next stage's loads below it, next to their LDS stores, which exposes
-        // the full load latency every stage.  Waves wholly outside the written
-        // region (diagonal tiles only) compute and discard.
-        for (int kt = 0; kt + 1 < nk; ++kt) {
-            load(kt + 1);
-            compute_full(kt & 1);
-            store((kt + 1) & 1);
-            __syncthreads();
-        }
-        compute_tail((nk - 1) & 1, (K - (nk - 1) * BK + 3) / 4);
-
-        if (active) {
-            // Write-back C - S.  Lane part of the offset in a register, the block
-            // column in the scalar offset, the block row in the immediate.  Tiles
-            // on an edge or crossing the written region's boundary mask each entry.
-            const rsrc_t rc = make_rsrc(C + row0 + (int64_t)col0 * ldc);
-            const int li0 = WW * wr + (lane & 15);
-            const int lj0 = WW * wc + AT::col_lane(lane);
-            const int cs = (int)ldc * SZ;
-            const int cbase = (li0 + lj0 * (int)ldc) * SZ;
-            const bool full = mrem >= TM && nrem >= TN && (!LOWER || row0 - (col0 + TN - 1) >= g.shift);
-            if (full) {
-#pragma unroll
-                for (int cb = 0; cb < NB; ++cb) {
-                    T cv[NB][4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int r4 = 0; r4 < NB; ++r4)
-                            cv[r4][r] = bufop<T, AUX_NT>::load(rc, cbase + 16 * r4 * SZ, (16 * cb + AT::col_reg(r)) * cs);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int r4 = 0; r4 < NB; ++r4)
-                            bufop<T, AUX_NT>::store(rc, cbase + 16 * r4 * SZ, cv[r4][r] - acc[cb][r4][r],
-                                                    (16 * cb + AT::col_reg(r)) * cs);
-                }
-            } else {
-#pragma unroll
-                for (int cb = 0; cb < NB; ++cb) {
-                    T cv[NB][4];
-                    int off[NB][4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int r4 = 0; r4 < NB; ++r4) {
-                            const int li = li0 + 16 * r4;
-                            const int lj = lj0 + 16 * cb + AT::col_reg(r);
-                            const bool ok = li < mrem && lj < nrem && (!LOWER || (row0 + li) - (col0 + lj) >= g.shift);
-                            off[r4][r] = ok ? cbase + (16 * r4 + (16 * cb + AT::col_reg(r)) * (int)ldc) * SZ : BUF_OOB;
-                            cv[r4][r] = bufop<T, AUX_NT>::load(rc, off[r4][r], 0);
-                        }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int r4 = 0; r4 < NB; ++r4)
-                            bufop<T, AUX_NT>::store(rc, off[r4][r], cv[r4][r] - acc[cb][r4][r], 0);
-                }
-            }
-        }
-        __syncthreads();   // the next tile's first stage reuses buffer 0
+        wide_tile<T, WW, WMW, YROWS, LOWER>(M, N, K, C, ldc, X, ldx, Y, ldy, g.shift, bi, bj, As, Bs);
     }
 }
 
+// Grouped trailing updates (many independent matrices, serving): the lower
+// 128 x 128 tiles of every job form one flat queue; a workgroup finds its job by
+// binary search over the tile offsets and runs the same tile body.
+__global__ __launch_bounds__(256, 2)
+void update_grouped_kernel(const GroupUpd* __restrict__ jobs, int njobs, int ntiles)
+{
+    typedef wide_cfg<double, 64, 2> CF;
+    __shared__ double As[2][CF::BK][CF::TM];
+    __shared__ double Bs[2][CF::BK][CF::TN];
+    for (int slot = blockIdx.x; slot < ntiles; slot += gridDim.x) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tiles_begin <= slot) lo = mid;
+            else hi = mid - 1;
+        }
+        const GroupUpd jb = jobs[lo];
+        if (jb.info && *jb.info != 0) continue;
+        const int t = slot - jb.tiles_begin;
+        const int bi = tri_row(t), bj = t - bi * (bi + 1) / 2;
+        wide_tile<double, 64, 2, true, true>(jb.m, jb.m, jb.w, jb.c, jb.ld, jb.p, jb.ld, jb.p, jb.ld, 0, bi, bj, As, Bs);
+    }
+}
 
 // bfloat16-operand variant (YROWS form, optional LOWER, persistent 128 tiles);
 // binary32 storage and accumulation.  Operand tiles are stored row-major
@@ -523,6 +565,16 @@ hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+int grouped_update_tile() { return 128; }
+
+hipError_t launch_update_grouped(int njobs, int total_tiles, const GroupUpd* d_jobs, hipStream_t st) {
+    if (njobs <= 0 || total_tiles <= 0) return hipSuccess;
+    int nwg = 2 * update_workers(0);
+    if (nwg > total_tiles) nwg = total_tiles;
+    hipLaunchKernelGGL(update_grouped_kernel, dim3(nwg), dim3(256), 0, st, d_jobs, njobs, total_tiles);
+    return hipGetLastError();
 }
 
 hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const float* X, int64_t ldx,
