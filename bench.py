@@ -55,6 +55,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--cpu-n", type=int, default=12288)
+    p.add_argument("--serving-only", action="store_true", help="only the serving leg (many independent solves)")
+    p.add_argument("--serving-requests", type=int, default=2000)
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy 3 times (reference kernel for HBM counter scaling)")
     return p.parse_args()
@@ -88,6 +90,12 @@ def main():
         log("[bench] copy calibration: 3 x 1 GiB read + 1 GiB written")
         return
     ff.load()
+    if args.serving_only:
+        from paper_1812_02056_amd import workloads as wl
+        res = run_serving(ff, torch, wl, dev, nreq=args.serving_requests)
+        log(f"[bench] serving: {res}")
+        print(json.dumps({"serving_f64": res}), flush=True)
+        return
     n = args.n
     svals = [int(x) for x in args.s.split(",")]
     K, W = args.steps, args.warmup
@@ -295,7 +303,132 @@ def run_extras(ff, torch, wl, dev, n, A0):
     except Exception as e:
         out["mixed_solve_n16384_lambda1"] = {"error": str(e)}
     torch.cuda.empty_cache()
+
+    # --- serving: continuous batching of many independent solves
+    try:
+        out["serving_f64"] = run_serving(ff, torch, wl, dev)
+        log(f"[bench] serving: {out['serving_f64']}")
+    except Exception as e:
+        out["serving_f64"] = {"error": str(e)}
+    torch.cuda.empty_cache()
     return out
+
+
+def run_serving(ff, torch, wl, dev, nreq=2000, seed=0, pool=48, window=128, rho=0.8):
+    """Continuous batching of many independent binary64 SPD solves (the serving
+    workload): sizes n = round(exp(U(ln 256, ln 8192))), nrhs ~ U{1..8}; with
+    probability 0.3 a request repeats the matrix of one of the last 64 distinct
+    ones (same key: the resident factor serves it).  Matrices come from a pool of
+    pre-generated A = G G^T/n + I (a new request gets a new key, so it is factored
+    even when its pool matrix was used before).  Closed loop (a window of
+    outstanding requests) gives the saturation rate X_max; an open loop with
+    exponential arrivals at rho * X_max gives the latency percentiles (device time
+    from the submit stamp to the end of the solve, plus any lateness of the host
+    loop behind the nominal arrival)."""
+    import math
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sizes = [int(round(math.exp(rng.uniform(math.log(256), math.log(8192))))) for _ in range(pool)]
+    mats = [wl.spd_scaled_device(n, seed=10**6 + i, device=dev) for i, n in enumerate(sizes)]
+    torch.cuda.synchronize()
+
+    def workload():
+        reqs, distinct = [], []
+        for i in range(nreq):
+            if distinct and rng.uniform() < 0.3:
+                key, j = distinct[int(rng.integers(0, min(64, len(distinct)))) - min(64, len(distinct))]
+            else:
+                key, j = i + 1, int(rng.integers(0, pool))
+                distinct.append((key, j))
+            reqs.append((key, j, int(rng.integers(1, 9))))
+        return reqs
+
+    def run(reqs, arrivals=None):
+        arena = torch.empty(64 << 27, dtype=torch.float64, device=dev)     # 64 GiB budget
+        srv = ff.Server(arena)
+        flops = 0.0
+        lat, hits, out = [], 0, {}
+        nominal = {}
+        t0 = time.perf_counter()
+        nxt, done = 0, 0
+        last_done, last_t, last_log = 0, 0.0, 0.0
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            if done != last_done:
+                last_done, last_t = done, now
+            elif now - last_t > 60.0 and nxt > done:
+                raise RuntimeError(f"serving made no progress for 60 s ({done}/{len(reqs)} done)")
+            if now - last_log > 10.0:
+                log(f"[bench] serving: {done}/{len(reqs)} done after {now:.1f} s")
+                last_log = now
+            while nxt < len(reqs) and (nxt - done) < window and (arrivals is None or arrivals[nxt] <= now):
+                key, j, nrhs = reqs[nxt]
+                A = mats[j].t()
+                n = A.shape[0]
+                B = torch.randn(nrhs, n, dtype=torch.float64, device=dev).t()
+                X = torch.empty_like(B)
+                rid = srv.submit(A, B, X, key=key)
+                nominal[rid] = (now - arrivals[nxt]) * 1e3 if arrivals is not None else 0.0
+                out[rid] = n
+                nxt += 1
+            srv.step()
+            for r in srv.poll():
+                done += 1
+                hits += r["cache_hit"]
+                if r["info"] != 0:
+                    raise RuntimeError(f"serving request failed: info={r['info']}")
+                if not r["cache_hit"]:
+                    flops += out[r["id"]] ** 3 / 3.0
+                lat.append(r["latency_ms"] + nominal[r["id"]])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        del arena
+        torch.cuda.empty_cache()
+        lat = np.array(lat)
+        return {"requests": len(reqs), "wall_s": round(wall, 3), "solves_per_s": round(len(reqs) / wall, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "cache_hit_rate": round(hits / len(reqs), 3), "factor_tflops": round(flops / wall / 1e12, 3),
+                "steps": st["steps"], "grouped_launches": st["grouped_launches"], "evictions": st["evictions"]}
+
+    def sequential(reqs):
+        # the same requests one at a time through chol_factor + chol_trisolve
+        # (resident factors reused for repeats, as the server does)
+        cache = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for key, j, nrhs in reqs:
+            A = mats[j].t()
+            n = A.shape[0]
+            if key not in cache:
+                L = A.clone(memory_format=torch.preserve_format)
+                ff.chol_factor(L, min(wl.default_s(n), 192))
+                cache[key] = L
+            X = torch.randn(nrhs, n, dtype=torch.float64, device=dev).t()
+            ff.chol_trisolve(cache[key], X)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        del cache
+        torch.cuda.empty_cache()
+        return {"requests": len(reqs), "wall_s": round(wall, 3), "solves_per_s": round(len(reqs) / wall, 1)}
+
+    reqs = workload()
+    log(f"[bench] serving: pool of {pool} matrices ready, {nreq} requests")
+    run(reqs[:100])                                  # warm-up (kernels, allocator)
+    closed = run(reqs)
+    log(f"[bench] serving closed loop: {closed}")
+    seq = sequential(reqs)
+    log(f"[bench] one request at a time: {seq}")
+    xmax = closed["solves_per_s"]
+    gaps = rng.exponential(1.0 / (rho * xmax), size=len(reqs))
+    arrivals = np.cumsum(gaps)
+    opened = run(reqs, arrivals)
+    del mats
+    torch.cuda.empty_cache()
+    return {"workload": f"{nreq} requests, n log-uniform [256, 8192], nrhs U{{1..8}}, 30% repeats, "
+                        f"pool of {pool} matrices, binary64, arena 64 GiB",
+            "closed_loop": closed, f"open_loop_rho{rho}": opened, "one_at_a_time": seq}
 
 
 def cpu_baseline(n_cpu):

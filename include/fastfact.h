@@ -218,8 +218,9 @@ int ff_update_profile_read(ff_kernel_profile out[FF_UPD_NSHAPES]);
  *     -(argument index) or FF_ERR_WORKSPACE if the request can never fit.
  *   ff_server_step: one scheduler iteration (admission, one block step of
  *     every active factorisation, solves).  Enqueues only, except that it waits
- *     for the step RING (4) iterations back before reusing its job table.
- *     Returns the number of requests not yet finished (>= 0) or an error.
+ *     for the step 4 iterations back before reusing its job table.  Returns the
+ *     number of requests not yet finished (>= 0), or an error (FF_ERR_WORKSPACE
+ *     if the oldest queued request cannot be admitted although nothing runs).
  *   ff_server_poll: up to max_out finished requests (their solve has completed
  *     on the device): id, info, cache_hit, latency_ms (device time from the
  *     submit stamp to the end of the solve).  Non-blocking.

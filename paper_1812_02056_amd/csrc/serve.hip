@@ -28,6 +28,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int MAX_ACTIVE = 512;      // admitted requests (job-table capacity)
+constexpr int MAX_FACTORS = 8192;    // live factors (info words)
 constexpr int RING = 4;              // job-table slots in flight
 
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -153,16 +154,21 @@ void drop_factor(ff_server* s, Factor* f) {
     delete f;
 }
 
+// Drop the least recently used resident factor no request is using.
+bool evict_one(ff_server* s) {
+    Factor* victim = nullptr;
+    for (auto it = s->resident.rbegin(); it != s->resident.rend(); ++it)
+        if ((*it)->users == 0) { victim = *it; break; }
+    if (!victim) return false;
+    drop_factor(s, victim);
+    s->stats.evictions++;
+    return true;
+}
+
 // Space for n bytes, evicting unused resident factors, oldest first.
 bool make_room(ff_server* s, size_t bytes, size_t& off) {
-    while (!s->arena.alloc(bytes, off)) {
-        Factor* victim = nullptr;
-        for (auto it = s->resident.rbegin(); it != s->resident.rend(); ++it)
-            if ((*it)->users == 0) { victim = *it; break; }
-        if (!victim) return false;
-        drop_factor(s, victim);
-        s->stats.evictions++;
-    }
+    while (!s->arena.alloc(bytes, off))
+        if (!evict_one(s)) return false;
     return true;
 }
 
@@ -177,7 +183,7 @@ int admit(ff_server* s) {
         if (it != s->by_key.end() && it->second->n == r->n) {
             f = it->second;
         } else {
-            if (s->free_info.empty()) break;
+            if (s->free_info.empty() && !evict_one(s)) break;
             f = new (std::nothrow) Factor{r->key, r->n, 0, (size_t)r->n * r->n * sizeof(double)};
             if (!f) return FF_ERR_HIP;
             owner = true;
@@ -256,14 +262,14 @@ ff_server* ff_server_create(void* arena, size_t arena_bytes, void* stream, int* 
         s->base = static_cast<char*>(arena);
         s->arena.init(arena_bytes);
         if (hipStreamCreateWithFlags(&s->clock, hipStreamNonBlocking) != hipSuccess ||
-            hipMalloc(&s->d_info, MAX_ACTIVE * sizeof(int)) != hipSuccess ||
-            hipHostMalloc(&s->h_info, MAX_ACTIVE * sizeof(int)) != hipSuccess)
+            hipMalloc(&s->d_info, MAX_FACTORS * sizeof(int)) != hipSuccess ||
+            hipHostMalloc(&s->h_info, MAX_FACTORS * sizeof(int)) != hipSuccess)
             rc = FF_ERR_HIP;
         for (int i = 0; !rc && i < RING; ++i)
             if (hipHostMalloc(&s->h_tab[i], TAB_BYTES) != hipSuccess || hipMalloc(&s->d_tab[i], TAB_BYTES) != hipSuccess ||
                 hipEventCreateWithFlags(&s->tab_ev[i], hipEventDisableTiming) != hipSuccess)
                 rc = FF_ERR_HIP;
-        for (int i = MAX_ACTIVE - 1; i >= 0; --i) s->free_info.push_back(i);
+        for (int i = MAX_FACTORS - 1; i >= 0; --i) s->free_info.push_back(i);
     }
     if (status) *status = rc;
     if (rc && s) {
@@ -325,6 +331,10 @@ int ff_server_step(ff_server* s) {
     if (s->tab_used[slot] && hipEventSynchronize(s->tab_ev[slot]) != hipSuccess) return FF_ERR_HIP;
     int rc = admit(s);
     if (rc) return rc;
+    // nothing running and the oldest request still not admitted: it cannot be
+    // (fragmented arena with every factor in use cannot happen when nothing is
+    // active, so this is a broken invariant, reported instead of spinning)
+    if (s->active.empty() && !s->queue.empty()) return FF_ERR_WORKSPACE;
 
     // requests waiting on a factor another request computes
     for (Request* r : s->active)

@@ -183,3 +183,20 @@ def test_server_rejects_requests_that_can_never_fit():
     with pytest.raises(ff.FastFactError):
         srv.submit(A, B, torch.zeros_like(B))
     srv.close()
+
+
+def test_server_many_small_keyed_requests_all_complete():
+    # more distinct resident factors than requests in flight: admission must never stall
+    srv = ff.Server(arena(1 << 28))
+    A = wl.spd_scaled(40, seed=3)
+    Ad = dev(A)
+    B = dev(wl.rhs(40, 1, 4))
+    outs = []
+    for i in range(700):
+        X = torch.zeros_like(B)
+        outs.append((srv.submit(Ad, B, X, key=10_000 + i), X))
+    done = drain(srv)
+    assert len(done) == 700 and all(r["info"] == 0 for r in done.values())
+    Xa, _ = alone(A, wl.rhs(40, 1, 4))
+    assert all(np.array_equal(host(X), Xa) for _, X in outs[::97])
+    srv.close()
