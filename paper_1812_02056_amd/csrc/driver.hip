@@ -401,6 +401,8 @@ struct SolveWs {
     int* d_info;
     S* linv;
     int* flags;
+    S* parts;
+    double* rpart;
     double* R;
     S* D;
     double* rowsum;
@@ -416,6 +418,8 @@ SolveWs<S> carve_solve(void* base, int64_t n, int64_t s, int64_t nrhs, int dtype
     w.d_info = cv.take<int>(1);
     w.linv = cv.take<S>(trisolve_linv_elems((int)n));
     w.flags = cv.take<int>(trisolve_flag_ints((int)n));
+    w.parts = cv.take<S>(trisolve_part_elems((int)n));
+    w.rpart = cv.take<double>(residual_part_doubles((int)n));
     w.R = cv.take<double>((size_t)n * (size_t)nrhs);
     w.D = cv.take<S>((size_t)n * (size_t)nrhs);
     w.rowsum = cv.take<double>((size_t)n);
@@ -449,18 +453,17 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
             return 0;
         }
     }
-    const int nblk = trisolve_nblk(n);
     // iteration 0: X = W^-T W^-1 B in the factor's precision
     FF_TRY(launch_convert_from_f64<S>(n, nrhs, B, ldb, w.D, n, st));
-    FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.linv, w.flags, true, st));
+    FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.linv, w.flags, w.parts, true, st));
     FF_TRY(launch_widen<S>(n, nrhs, w.D, n, X, ldx, st));
     double prev = -1.0;
     double host[2];
     int bad_wait = 0;
     for (int it = 1; it <= max_iter; ++it) {
-        FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, nullptr, st));
+        FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, nullptr, w.rpart, st));
         FF_TRY(launch_convert_from_f64<S>(n, nrhs, w.R, n, w.D, n, st));
-        FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.linv, w.flags, false, st));
+        FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.linv, w.flags, w.parts, false, st));
         FF_TRY(launch_axpy_max<S>(n, nrhs, w.D, n, X, ldx, w.norms, st));
         FF_TRY(hipMemcpyAsync(host, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         FF_TRY(hipStreamSynchronize(st));
@@ -475,13 +478,15 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
         prev = corr;
     }
     // backward error of the returned X
-    FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, w.rowsum, st));
+    FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, w.rowsum, w.rpart, st));
     FF_TRY(launch_norms(n, nrhs, w.rowsum, X, ldx, nullptr, 0, w.R, n, B, ldb, w.norms, st));
     std::vector<double> nh(3 + 3 * (size_t)nrhs);
     int wait_err[2] = {0, 0};
     FF_TRY(hipMemcpyAsync(nh.data(), w.norms, nh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    FF_TRY(hipMemcpyAsync(&wait_err[0], w.flags + nblk + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-    FF_TRY(hipMemcpyAsync(&wait_err[1], w.flags + 2 * nblk + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+    FF_TRY(hipMemcpyAsync(&wait_err[0], w.flags + trisolve_error_index((int)n, 0), sizeof(int), hipMemcpyDeviceToHost,
+                          st));
+    FF_TRY(hipMemcpyAsync(&wait_err[1], w.flags + trisolve_error_index((int)n, 1), sizeof(int), hipMemcpyDeviceToHost,
+                          st));
     FF_TRY(hipStreamSynchronize(st));
     bad_wait = wait_err[0] | wait_err[1];
     if (bad_wait) return FF_ERR_HIP;
@@ -606,7 +611,8 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t ld
 size_t ff_trisolve_workspace_size(int64_t n, int dtype) {
     if (n <= 0) return 0;
     const size_t es = (dtype == FF_F64) ? sizeof(double) : sizeof(float);
-    return align_up(trisolve_linv_elems((int)n) * es) + align_up(trisolve_flag_ints((int)n) * sizeof(int));
+    return align_up(trisolve_linv_elems((int)n) * es) + align_up(trisolve_flag_ints((int)n) * sizeof(int)) +
+           align_up(trisolve_part_elems((int)n) * es);
 }
 
 int chol_trisolve(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtype, void* X, int64_t ldx, void* ws,
@@ -625,14 +631,16 @@ int chol_trisolve(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtype
     if (dtype == FF_F64) {
         double* linv = cv.take<double>(trisolve_linv_elems((int)n));
         int* flags = cv.take<int>(trisolve_flag_ints((int)n));
+        double* parts = cv.take<double>(trisolve_part_elems((int)n));
         if (trisolve_impl<double>((int)n, (int)nrhs, static_cast<const double*>(L), ldl, static_cast<double*>(X), ldx,
-                                  linv, flags, true, st) != hipSuccess)
+                                  linv, flags, parts, true, st) != hipSuccess)
             return FF_ERR_HIP;
     } else {
         float* linv = cv.take<float>(trisolve_linv_elems((int)n));
         int* flags = cv.take<int>(trisolve_flag_ints((int)n));
+        float* parts = cv.take<float>(trisolve_part_elems((int)n));
         if (trisolve_impl<float>((int)n, (int)nrhs, static_cast<const float*>(L), ldl, static_cast<float*>(X), ldx,
-                                 linv, flags, true, st) != hipSuccess)
+                                 linv, flags, parts, true, st) != hipSuccess)
             return FF_ERR_HIP;
     }
     return 0;

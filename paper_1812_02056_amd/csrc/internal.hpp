@@ -90,16 +90,28 @@ template <typename S>
 hipError_t launch_convert_from_f64(int n, int nrhs, const double* B, int64_t ldb, S* X, int64_t ldx, hipStream_t st);
 // Solve L L^T X = X in place with 64-row blocks; Linv holds (or, when
 // make_inverses, receives) the inverses of the 64 x 64 diagonal blocks
-// (trisolve_linv_elems(n) elements); flags needs trisolve_flag_ints(n) ints.
-// flags[nblk + 1] / flags[2*nblk + 3] become nonzero if a bounded wait expired.
+// (trisolve_linv_elems(n) elements); flags needs trisolve_flag_ints(n) ints and
+// parts trisolve_part_elems(n) elements.  The word at trisolve_error_index(n, k)
+// of flags becomes nonzero if a bounded wait of sweep k (0 forward, 1 backward)
+// expired.
+constexpr int TRISOLVE_TP = 8;      // workgroups per 64-row block
+constexpr int RESIDUAL_CB = 16;     // 64-column blocks per residual workgroup
 inline int trisolve_nblk(int n) { return (n + 63) / 64; }
 inline size_t trisolve_linv_elems(int n) { return (size_t)trisolve_nblk(n) * 64 * 64; }
-inline size_t trisolve_flag_ints(int n) { return 2 * ((size_t)trisolve_nblk(n) + 2); }
+inline size_t trisolve_sweep_ints(int n) { return 2 + (size_t)trisolve_nblk(n) * (1 + TRISOLVE_TP); }
+inline size_t trisolve_flag_ints(int n) { return 2 * trisolve_sweep_ints(n); }
+inline size_t trisolve_error_index(int n, int sweep) { return sweep * trisolve_sweep_ints(n) + 1; }
+inline size_t trisolve_part_elems(int n) { return (size_t)trisolve_nblk(n) * (TRISOLVE_TP - 1) * 64 * 16; }
 template <typename S>
-hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, S* Linv, int* flags,
+hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, S* Linv, int* flags, S* parts,
                          bool make_inverses, hipStream_t st);
+// part: residual_part_doubles(n) doubles of scratch.
+inline size_t residual_part_doubles(int n) {
+    const size_t nch = ((size_t)trisolve_nblk(n) + RESIDUAL_CB - 1) / RESIDUAL_CB;
+    return nch * (size_t)n * 16 + nch * (size_t)n;
+}
 hipError_t launch_residual_f64(int n, int nrhs, const double* A, int64_t lda, const double* X, int64_t ldx,
-                               const double* B, int64_t ldb, double* R, int64_t ldr, double* rowsum,
+                               const double* B, int64_t ldb, double* R, int64_t ldr, double* rowsum, double* part,
                                hipStream_t st);
 template <typename S>
 hipError_t launch_axpy_update(int n, int nrhs, const S* D, int64_t ldd, double* X, int64_t ldx, hipStream_t st);

@@ -5,12 +5,19 @@
 // from the low-precision factor, x += d) is how the mixed-precision factor wins
 // back binary64 accuracy.
 //
-// Triangular solves: the n rows are cut into 64-row blocks.  One workgroup per
-// block takes a ticket from an atomic counter, so a workgroup only ever waits for
-// blocks whose workgroups already started; it streams its row of L against the
-// solved blocks as their flags appear, then applies the precomputed inverse of
-// its 64 x 64 diagonal block and publishes its result.  Every wait is bounded:
-// past the spin limit the workgroup records an error and exits.
+// Triangular solves: the n rows are cut into 64-row blocks, and each block gets
+// TP workgroups that take tickets from an atomic counter in block order.  The
+// first TP - 1 fold disjoint sets of already-solved blocks into partial sums as
+// those blocks' flags appear (streaming their tiles of L, the next tile loaded
+// while the current one is applied); the last one folds the newest solved block,
+// adds the partial sums in a fixed order, applies the precomputed inverse of the
+// 64 x 64 diagonal block and publishes the block.  Every wait is on a workgroup
+// with a smaller ticket, so every wait ends; each is also bounded: past the spin
+// limit the workgroup records an error and exits.
+//
+// The binary64 residual R = B - A X reads tril(A) once per use of symmetry:
+// workgroups own (row block, chunk of column blocks) pairs and write partial
+// products, which a second kernel adds in a fixed order.
 #include <algorithm>
 
 #include "common.hpp"
@@ -22,6 +29,8 @@ namespace {
 
 constexpr int TB = 64;          // row block of the triangular solves
 constexpr int RHS_CHUNK = 16;   // right-hand sides per launch
+constexpr int TP = TRISOLVE_TP; // workgroups per row block of a triangular solve
+constexpr int RCB = RESIDUAL_CB;// column blocks per residual workgroup
 constexpr int SPIN_LIMIT = 1 << 24;
 
 template <typename S>
@@ -66,9 +75,11 @@ void inv_diag_kernel(int n, const S* __restrict__ L, int64_t ldl, S* __restrict_
     for (int i = 0; i < TB; ++i) Linv[(int64_t)b * TB * TB + i + (int64_t)c * TB] = (S)x[i][c];
 }
 
+// Spin on a relaxed load (an acquire load would invalidate the caches on every
+// iteration); callers issue one acquire fence after the flag is seen.
 __device__ __forceinline__ bool wait_flag(const int* f) {
     int spins = 0;
-    while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
         if (++spins > SPIN_LIMIT) return false;
         __builtin_amdgcn_s_sleep(2);
     }
@@ -76,151 +87,242 @@ __device__ __forceinline__ bool wait_flag(const int* f) {
 }
 
 // Forward (TRANS = false: L y = b) or backward (TRANS = true: L^T x = y)
-// substitution on nrhs <= 16 columns of X in place.  flags[0..nblk-1] are the
-// per-block "published" flags, flags[nblk] the ticket counter, flags[nblk+1]
-// the error word; all start at zero.
+// substitution on nr <= 16 columns of X in place.  fl: [0] ticket, [1] error
+// word, [2, 2 + nblk) block flags, then nblk * TP partial flags; all start at
+// zero.  parts: (TP - 1) partial sums of 64 x 16 per block.
 template <typename S, bool TRANS>
 __global__ __launch_bounds__(256)
-void trisolve_kernel(int n, int nrhs, const S* __restrict__ L, int64_t ldl, const S* __restrict__ Linv,
-                     S* X, int64_t ldx, int* flags)
+void trisolve_kernel(int n, int nr, const S* __restrict__ L, int64_t ldl, const S* __restrict__ Linv,
+                     S* X, int64_t ldx, int* fl, S* __restrict__ parts)
 {
     __shared__ S tile[TB][TB + 1];
-    __shared__ S yv[TB][RHS_CHUNK];
-    __shared__ S acc[TB][RHS_CHUNK];
-    __shared__ int ticket, bad;
+    __shared__ S xv[TB][RHS_CHUNK];
+    __shared__ int sh_ticket, bad;
     const int nblk = (n + TB - 1) / TB;
+    int* const err = fl + 1;
+    int* const bflag = fl + 2;
+    int* const pflag = fl + 2 + nblk;
     const int tid = threadIdx.x;
     if (tid == 0) {
-        ticket = atomicAdd(&flags[nblk], 1);
+        sh_ticket = atomicAdd(&fl[0], 1);
         bad = 0;
     }
     __syncthreads();
-    const int j = TRANS ? (nblk - 1 - ticket) : ticket;
+    const int jj = sh_ticket / TP, p = sh_ticket % TP;   // jj blocks are solved before this one
+    const int j = TRANS ? (nblk - 1 - jj) : jj;
     const int r0 = j * TB;
     const int nbr = min(TB, n - r0);
     const int r = tid % TB, g = tid / TB;
-
-    for (int c = g; c < RHS_CHUNK; c += 4)
-        acc[r][c] = (r < nbr && c < nrhs) ? X[(int64_t)(r0 + r) + (int64_t)c * ldx] : S(0);
-
-    for (int t = 0; t < nblk - 1; ++t) {
-        const int i = TRANS ? (nblk - 1 - t) : t;     // solved block to fold in
-        if (TRANS ? (i <= j) : (i >= j)) break;
-        const int i0 = i * TB;
-        const int nbi = min(TB, n - i0);
-        // tile = L[j-block, i-block] (forward) or L[i-block, j-block] (backward), both below the diagonal
-        for (int e = tid; e < TB * TB; e += 256) {
-            const int a = e % TB, b = e / TB;      // a: row within tile (contiguous), b: column
-            S v = S(0);
-            if (!TRANS) { if (a < nbr && b < nbi) v = L[(int64_t)(r0 + a) + (int64_t)(i0 + b) * ldl]; }
-            else        { if (a < nbi && b < nbr) v = L[(int64_t)(i0 + a) + (int64_t)(r0 + b) * ldl]; }
-            tile[a][b] = v;
+    const bool fin = p == TP - 1;
+    S acc[RHS_CHUNK / 4];
+#pragma unroll
+    for (int q = 0; q < RHS_CHUNK / 4; ++q) {
+        const int c = g + 4 * q;
+        acc[q] = (fin && r < nbr && c < nr) ? X[(int64_t)(r0 + r) + (int64_t)c * ldx] : S(0);
+    }
+    // Blocks folded here, by distance d from block j: the finisher takes d = 1,
+    // workgroup p < TP - 1 takes d = p + 2, p + 2 + (TP - 1), ... and walks them
+    // oldest first, so it works through the blocks already solved while the newer
+    // ones are still being solved.
+    const int dlo = fin ? 1 : p + 2;
+    const int d0 = fin ? 1 : (jj >= dlo ? dlo + (jj - dlo) / (TP - 1) * (TP - 1) : 0);
+    const int dstep = fin ? -(jj + 1) : -(TP - 1);
+    constexpr int NE = TB * TB / 256;
+    S tv[NE];
+    auto load_tile = [&](int d) {
+        const int i = TRANS ? j + d : j - d;
+        const int i0 = i * TB, nbi = min(TB, n - i0);
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = tid + 256 * u;
+            const int a = e % TB, b = e / TB;    // a: row within the tile (contiguous), b: column
+            const bool in = !TRANS ? (a < nbr && b < nbi) : (a < nbi && b < nbr);
+            const int64_t off = !TRANS ? (int64_t)(r0 + a) + (int64_t)(i0 + b) * ldl
+                                       : (int64_t)(i0 + a) + (int64_t)(r0 + b) * ldl;
+            const S v = L[in ? off : 0];
+            tv[u] = in ? v : S(0);
         }
-        if (tid == 0 && !wait_flag(&flags[i])) bad = 1;
+    };
+    S* const mine = parts + ((int64_t)j * (TP - 1)) * TB * RHS_CHUNK;
+    S lv[NE];                                    // the finisher's inverse diagonal block, loaded early
+    if (fin) {
+        // partial sums first (their blocks were solved earlier), all flags at once
+        if (tid < TP - 1 && !wait_flag(&pflag[j * TP + tid])) bad = 1;
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         if (bad) {
-            if (tid == 0) atomicExch(&flags[nblk + 1], 1);
+            if (tid == 0) atomicExch(err, 1);
             return;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+        for (int pp = 0; pp < TP - 1; ++pp)
+#pragma unroll
+            for (int q = 0; q < RHS_CHUNK / 4; ++q) acc[q] += mine[(int64_t)pp * TB * RHS_CHUNK + r * RHS_CHUNK + g + 4 * q];
+#pragma unroll
+        for (int u = 0; u < NE; ++u) lv[u] = Linv[(int64_t)j * TB * TB + tid + 256 * u];
+    }
+    if (d0 >= dlo && d0 <= jj) load_tile(d0);
+    for (int d = d0; d >= dlo && d <= jj; d += dstep) {
+        const int i = TRANS ? j + d : j - d;
+        const int i0 = i * TB, nbi = min(TB, n - i0);
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = tid + 256 * u;
+            tile[e % TB][e / TB] = tv[u];
+        }
+        if (d + dstep >= dlo) load_tile(d + dstep);      // next tile in flight during this one
+        // one wave takes the acquire (the invalidation acts for the whole CU)
+        if (tid == 0 && !wait_flag(&bflag[i])) bad = 1;
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        if (bad) {
+            if (tid == 0) atomicExch(err, 1);
+            return;
+        }
         for (int e = tid; e < TB * RHS_CHUNK; e += 256) {
             const int a = e % TB, c = e / TB;
-            yv[a][c] = (a < nbi && c < nrhs) ? X[(int64_t)(i0 + a) + (int64_t)c * ldx] : S(0);
+            xv[a][c] = (a < nbi && c < nr) ? X[(int64_t)(i0 + a) + (int64_t)c * ldx] : S(0);
         }
         __syncthreads();
-        for (int c = g; c < nrhs; c += 4) {
-            S s = S(0);
-            if (!TRANS) { for (int k = 0; k < TB; ++k) s += tile[r][k] * yv[k][c]; }
-            else        { for (int k = 0; k < TB; ++k) s += tile[k][r] * yv[k][c]; }
-            acc[r][c] -= s;
+#pragma unroll
+        for (int q = 0; q < RHS_CHUNK / 4; ++q) {
+            const int c = g + 4 * q;
+            S sum = S(0);
+            if (!TRANS) { for (int k = 0; k < TB; ++k) sum += tile[r][k] * xv[k][c]; }
+            else        { for (int k = 0; k < TB; ++k) sum += tile[k][r] * xv[k][c]; }
+            acc[q] -= sum;
         }
         __syncthreads();
     }
-    // apply the inverse diagonal block
-    for (int e = tid; e < TB * TB; e += 256) {
-        const int a = e % TB, b = e / TB;
-        tile[a][b] = Linv[(int64_t)j * TB * TB + a + (int64_t)b * TB];
+    if (!fin) {
+#pragma unroll
+        for (int q = 0; q < RHS_CHUNK / 4; ++q) mine[(int64_t)p * TB * RHS_CHUNK + r * RHS_CHUNK + g + 4 * q] = acc[q];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(&pflag[j * TP + p], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
     }
+    // apply the inverse diagonal block (column-major, ld 64)
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+        const int e = tid + 256 * u;
+        tile[e % TB][e / TB] = lv[u];
+    }
+#pragma unroll
+    for (int q = 0; q < RHS_CHUNK / 4; ++q) xv[r][g + 4 * q] = acc[q];
     __syncthreads();
-    for (int c = g; c < nrhs; c += 4) {
-        S s = S(0);
-        if (!TRANS) { for (int k = 0; k < TB; ++k) s += tile[r][k] * acc[k][c]; }
-        else        { for (int k = 0; k < TB; ++k) s += tile[k][r] * acc[k][c]; }
-        if (r < nbr) X[(int64_t)(r0 + r) + (int64_t)c * ldx] = s;
+    for (int c = g; c < nr; c += 4) {
+        S sum = S(0);
+        if (!TRANS) { for (int k = 0; k < TB; ++k) sum += tile[r][k] * xv[k][c]; }
+        else        { for (int k = 0; k < TB; ++k) sum += tile[k][r] * xv[k][c]; }
+        if (r < nbr) X[(int64_t)(r0 + r) + (int64_t)c * ldx] = sum;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(&flags[j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_store(&bflag[j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void fill_int_kernel(int* p, int count, int v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
-// R = B - A X in binary64 with A symmetric, only tril(A) read: the 64-row block j
-// takes A[j-block, i-block] for i <= j and A[i-block, j-block]^T for i > j.  Also
-// writes the absolute row sums of A (for ||A||_inf) into rowsum when non-null.
+// Partial products of R = B - A X in binary64 with A symmetric, only tril(A)
+// read: workgroup (j, c) takes the 64-row block j against column blocks
+// i in [c*RCB, (c+1)*RCB): A[j-block, i-block] for i < j, A[i-block, j-block]^T
+// for i > j, the symmetric diagonal block for i = j.  part[c] receives A X of
+// those columns (n x nr, ld n) and, when rsum is non-null, the absolute row sums.
 __global__ __launch_bounds__(256)
-void residual_kernel(int n, int nrhs, const double* __restrict__ A, int64_t lda, const double* __restrict__ X,
-                     int64_t ldx, const double* __restrict__ B, int64_t ldb, double* __restrict__ R, int64_t ldr,
-                     double* __restrict__ rowsum)
+void residual_part_kernel(int n, int nr, const double* __restrict__ A, int64_t lda, const double* __restrict__ X,
+                          int64_t ldx, double* __restrict__ part, int64_t pstride, double* __restrict__ rsum)
 {
     __shared__ double tile[TB][TB + 1];
     __shared__ double xv[TB][RHS_CHUNK];
-    const int j = blockIdx.x;
-    const int chunk0 = blockIdx.y * RHS_CHUNK;
-    const int nr = min(RHS_CHUNK, nrhs - chunk0);
+    const int j = blockIdx.x, c = blockIdx.y;
     const int r0 = j * TB;
     const int nbr = min(TB, n - r0);
     const int nblk = (n + TB - 1) / TB;
     const int tid = threadIdx.x, r = tid % TB, g = tid / TB;
+    const int ib = c * RCB, ie = min(nblk, ib + RCB);
     double acc[RHS_CHUNK / 4];
     double asum = 0.0;
 #pragma unroll
     for (int q = 0; q < RHS_CHUNK / 4; ++q) acc[q] = 0.0;
-    for (int i = 0; i < nblk; ++i) {
-        const int i0 = i * TB;
-        const int nbi = min(TB, n - i0);
-        for (int e = tid; e < TB * TB; e += 256) {
+    constexpr int NE = TB * TB / 256;
+    double tv[NE];
+    auto load_tile = [&](int i) {
+        const int i0 = i * TB, nbi = min(TB, n - i0);
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = tid + 256 * u;
             const int a = e % TB, b = e / TB;
-            double v = 0.0;
-            if (i < j) { if (a < nbr && b < nbi) v = A[(int64_t)(r0 + a) + (int64_t)(i0 + b) * lda]; }
-            else if (i > j) { if (a < nbi && b < nbr) v = A[(int64_t)(i0 + a) + (int64_t)(r0 + b) * lda]; }
-            else { if (a < nbr && b < nbr && a >= b) v = A[(int64_t)(r0 + a) + (int64_t)(r0 + b) * lda]; }
-            tile[a][b] = v;
+            bool in;
+            int64_t off;
+            if (i < j) { in = a < nbr && b < nbi; off = (int64_t)(r0 + a) + (int64_t)(i0 + b) * lda; }
+            else if (i > j) { in = a < nbi && b < nbr; off = (int64_t)(i0 + a) + (int64_t)(r0 + b) * lda; }
+            else { in = a < nbr && b < nbr && a >= b; off = (int64_t)(r0 + a) + (int64_t)(r0 + b) * lda; }
+            const double v = A[in ? off : 0];
+            tv[u] = in ? v : 0.0;
+        }
+    };
+    if (ib < ie) load_tile(ib);
+    for (int i = ib; i < ie; ++i) {
+        const int i0 = i * TB, nbi = min(TB, n - i0);
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = tid + 256 * u;
+            tile[e % TB][e / TB] = tv[u];
         }
         for (int e = tid; e < TB * RHS_CHUNK; e += 256) {
-            const int a = e % TB, c = e / TB;
-            xv[a][c] = (a < nbi && c < nr) ? X[(int64_t)(i0 + a) + (int64_t)(chunk0 + c) * ldx] : 0.0;
+            const int a = e % TB, cc = e / TB;
+            xv[a][cc] = (a < nbi && cc < nr) ? X[(int64_t)(i0 + a) + (int64_t)cc * ldx] : 0.0;
         }
+        if (i + 1 < ie) load_tile(i + 1);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < RHS_CHUNK / 4; ++q) {
-            const int c = g + 4 * q;
-            if (c < nr) {
-                double s = 0.0;
-                if (i < j) { for (int k = 0; k < TB; ++k) s += tile[r][k] * xv[k][c]; }
-                else if (i > j) { for (int k = 0; k < TB; ++k) s += tile[k][r] * xv[k][c]; }
-                else { for (int k = 0; k < TB; ++k) s += (r >= k ? tile[r][k] : tile[k][r]) * xv[k][c]; }
-                acc[q] += s;
+            const int cc = g + 4 * q;
+            if (cc < nr) {
+                double sum = 0.0;
+                if (i < j) { for (int k = 0; k < TB; ++k) sum += tile[r][k] * xv[k][cc]; }
+                else if (i > j) { for (int k = 0; k < TB; ++k) sum += tile[k][r] * xv[k][cc]; }
+                else { for (int k = 0; k < TB; ++k) sum += (r >= k ? tile[r][k] : tile[k][r]) * xv[k][cc]; }
+                acc[q] += sum;
             }
         }
-        if (rowsum && g == 0 && blockIdx.y == 0) {
-            double s = 0.0;
-            if (i < j) { for (int k = 0; k < TB; ++k) s += fabs(tile[r][k]); }
-            else if (i > j) { for (int k = 0; k < TB; ++k) s += fabs(tile[k][r]); }
-            else { for (int k = 0; k < TB; ++k) s += fabs(r >= k ? tile[r][k] : tile[k][r]); }
-            asum += s;
+        if (rsum && g == 0) {
+            double sum = 0.0;
+            if (i < j) { for (int k = 0; k < TB; ++k) sum += fabs(tile[r][k]); }
+            else if (i > j) { for (int k = 0; k < TB; ++k) sum += fabs(tile[k][r]); }
+            else { for (int k = 0; k < TB; ++k) sum += fabs(r >= k ? tile[r][k] : tile[k][r]); }
+            asum += sum;
         }
         __syncthreads();
     }
+    double* pc = part + (int64_t)c * pstride;
 #pragma unroll
     for (int q = 0; q < RHS_CHUNK / 4; ++q) {
-        const int c = g + 4 * q;
-        if (c < nr && r < nbr)
-            R[(int64_t)(r0 + r) + (int64_t)(chunk0 + c) * ldr] = B[(int64_t)(r0 + r) + (int64_t)(chunk0 + c) * ldb] - acc[q];
+        const int cc = g + 4 * q;
+        if (cc < nr && r < nbr) pc[(int64_t)(r0 + r) + (int64_t)cc * n] = acc[q];
     }
-    if (rowsum && g == 0 && blockIdx.y == 0 && r < nbr) rowsum[r0 + r] = asum;
+    if (rsum && g == 0 && r < nbr) rsum[(int64_t)c * n + r0 + r] = asum;
+}
+
+// R = B - sum_c part[c] (c ascending), rowsum = sum_c rsum[c].
+__global__ void residual_reduce_kernel(int n, int nr, int nch, const double* __restrict__ part, int64_t pstride,
+                                       const double* __restrict__ B, int64_t ldb, double* __restrict__ R, int64_t ldr,
+                                       const double* __restrict__ rsum, double* __restrict__ rowsum)
+{
+    const int cc = blockIdx.y;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < nch; ++c) s += part[(int64_t)c * pstride + i + (int64_t)cc * n];
+        R[i + (int64_t)cc * ldr] = B[i + (int64_t)cc * ldb] - s;
+        if (rowsum && cc == 0) {
+            double t = 0.0;
+            for (int c = 0; c < nch; ++c) t += rsum[(int64_t)c * n + i];
+            rowsum[i] = t;
+        }
+    }
 }
 
 template <typename S>
@@ -350,7 +452,7 @@ hipError_t launch_convert_from_f64(int n, int nrhs, const double* B, int64_t ldb
 
 template <typename S>
 hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, S* Linv, int* flags,
-                         bool make_inverses, hipStream_t st) {
+                         S* parts, bool make_inverses, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
     const int nblk = (n + TB - 1) / TB;
     if (make_inverses) {
@@ -358,31 +460,47 @@ hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    const int per = (int)trisolve_sweep_ints(n);
     for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
         const int nr = (nrhs - c0 < RHS_CHUNK) ? nrhs - c0 : RHS_CHUNK;
         S* Xc = X + (int64_t)c0 * ldx;
-        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(256), 0, st, flags, 2 * (nblk + 2), 0);
-        hipLaunchKernelGGL((trisolve_kernel<S, false>), dim3(nblk), dim3(256), 0, st, n, nr, L, ldl, Linv, Xc, ldx,
-                           flags);
-        hipLaunchKernelGGL((trisolve_kernel<S, true>), dim3(nblk), dim3(256), 0, st, n, nr, L, ldl, Linv, Xc, ldx,
-                           flags + (nblk + 2));
+        hipLaunchKernelGGL(fill_int_kernel, dim3(std::min(64, (2 * per + 255) / 256)), dim3(256), 0, st, flags,
+                           2 * per, 0);
+        hipLaunchKernelGGL((trisolve_kernel<S, false>), dim3(nblk * TP), dim3(256), 0, st, n, nr, L, ldl, Linv, Xc,
+                           ldx, flags, parts);
+        hipLaunchKernelGGL((trisolve_kernel<S, true>), dim3(nblk * TP), dim3(256), 0, st, n, nr, L, ldl, Linv, Xc,
+                           ldx, flags + per, parts);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-template hipError_t trisolve_impl<double>(int, int, const double*, int64_t, double*, int64_t, double*, int*, bool, hipStream_t);
-template hipError_t trisolve_impl<float>(int, int, const float*, int64_t, float*, int64_t, float*, int*, bool, hipStream_t);
+template hipError_t trisolve_impl<double>(int, int, const double*, int64_t, double*, int64_t, double*, int*, double*, bool,
+                                          hipStream_t);
+template hipError_t trisolve_impl<float>(int, int, const float*, int64_t, float*, int64_t, float*, int*, float*, bool,
+                                         hipStream_t);
 
 hipError_t launch_residual_f64(int n, int nrhs, const double* A, int64_t lda, const double* X, int64_t ldx,
-                               const double* B, int64_t ldb, double* R, int64_t ldr, double* rowsum, hipStream_t st) {
+                               const double* B, int64_t ldb, double* R, int64_t ldr, double* rowsum, double* part,
+                               hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
     const int nblk = (n + TB - 1) / TB;
-    const int nchunk = (nrhs + RHS_CHUNK - 1) / RHS_CHUNK;
-    hipLaunchKernelGGL(residual_kernel, dim3(nblk, nchunk), dim3(256), 0, st, n, nrhs, A, lda, X, ldx, B, ldb, R, ldr,
-                       rowsum);
-    return hipGetLastError();
+    const int nch = (nblk + RCB - 1) / RCB;
+    const int64_t pstride = (int64_t)n * RHS_CHUNK;
+    double* rsum = part + (int64_t)nch * pstride;
+    for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
+        const int nr = std::min(RHS_CHUNK, nrhs - c0);
+        double* rs = (c0 == 0 && rowsum) ? rsum : nullptr;
+        hipLaunchKernelGGL(residual_part_kernel, dim3(nblk, nch), dim3(256), 0, st, n, nr, A, lda,
+                           X + (int64_t)c0 * ldx, ldx, part, pstride, rs);
+        hipLaunchKernelGGL(residual_reduce_kernel, dim3(std::min(1024, (n + 255) / 256), nr), dim3(256), 0, st, n, nr,
+                           nch, part, pstride, B + (int64_t)c0 * ldb, ldb, R + (int64_t)c0 * ldr, ldr, rs,
+                           c0 == 0 ? rowsum : nullptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename S>
