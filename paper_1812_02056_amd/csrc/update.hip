@@ -37,6 +37,8 @@ namespace {
 
 constexpr int NT = 256;    // threads of the bfloat16 shape (2 x 2 waves)
 
+constexpr int GRID_MAXSUP = 640;   // super-tiles the balanced order can describe
+
 struct Grid {
     int tm, tn;        // output tile rows, columns
     int gm, gn;        // tiles per super-tile along M and N
@@ -46,7 +48,56 @@ struct Grid {
     int tri;           // 1: square lower region enumerated as a triangle of super-tiles
     int shift;         // LOWER: write only i - j >= shift
     int nslots;        // flat slots covering every super-tile
+    // Balanced order: the region's tiles listed super-tile by super-tile; XCD x
+    // (workgroups b with b % 8 == x) takes the x-th eighth of the list and its
+    // workgroups stride through it, so shares differ by at most one tile.
+    int balanced;
+    int nsup;
+    int ntiles;
+    int pre[GRID_MAXSUP + 1];   // tiles in super-tiles [0, u)
 };
+
+// Super-tile u of the slot order.
+__host__ __device__ __forceinline__ void super_of(const Grid& g, int u, int& SI, int& SJ) {
+    if (g.tri) {
+        SJ = 0;
+        while (u >= g.nsm - SJ) { u -= g.nsm - SJ; ++SJ; }
+        SI = SJ + u;
+    } else {
+        SI = u % g.nsm;
+        SJ = u / g.nsm;
+    }
+}
+
+__host__ __device__ __forceinline__ bool tile_in_region(const Grid& g, bool lower, int bi, int bj) {
+    return bi < g.nbm && bj < g.nbn && !(lower && (bi * g.tm + g.tm - 1) - bj * g.tn < g.shift);
+}
+
+// The t-th tile of the balanced order (column-major inside a super-tile).
+__device__ __forceinline__ void tile_of_index(const Grid& g, bool lower, int t, int& bi, int& bj) {
+    int lo = 0, hi = g.nsup - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.pre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    int local = t - g.pre[lo];
+    int SI, SJ;
+    super_of(g, lo, SI, SJ);
+    bi = SI * g.gm;
+    bj = SJ * g.gn;
+    if (g.pre[lo + 1] - g.pre[lo] == g.gm * g.gn) {     // a whole super-tile
+        bi += local % g.gm;
+        bj += local / g.gm;
+        return;
+    }
+    for (int c = 0; c < g.gn; ++c)
+        for (int r = 0; r < g.gm; ++r)
+            if (tile_in_region(g, lower, SI * g.gm + r, SJ * g.gn + c)) {
+                if (local == 0) { bi = SI * g.gm + r; bj = SJ * g.gn + c; return; }
+                --local;
+            }
+}
 
 // Map a flat slot to an output tile (bi, bj).  Returns false when the slot is
 // empty.  Workgroups are dealt to the 8 XCDs round-robin, so slot % 8 is the XCD;
@@ -62,20 +113,11 @@ __device__ __forceinline__ bool tile_of_slot(const Grid& g, int slot, bool lower
     const int per = g.gm * g.gn;
     const int xcd = slot % N_XCD;
     const int k = slot / N_XCD;
-    int u = (k / per) * N_XCD + xcd;
+    const int u = (k / per) * N_XCD + xcd;
     const int within = k % per;
+    if (u >= (g.tri ? g.nsm * (g.nsm + 1) / 2 : g.nsm * g.nsn)) return false;
     int SI, SJ;
-    if (g.tri) {
-        const int nsup = g.nsm * (g.nsm + 1) / 2;
-        if (u >= nsup) return false;
-        SJ = 0;
-        while (u >= g.nsm - SJ) { u -= g.nsm - SJ; ++SJ; }
-        SI = SJ + u;
-    } else {
-        if (u >= g.nsm * g.nsn) return false;
-        SI = u % g.nsm;
-        SJ = u / g.nsm;
-    }
+    super_of(g, u, SI, SJ);
     bi = SI * g.gm + (within % g.gm);
     bj = SJ * g.gn + (within / g.gm);
     if (bi >= g.nbm || bj >= g.nbn) return false;
@@ -98,13 +140,17 @@ __device__ __forceinline__ bool tile_of_slot(const Grid& g, int slot, bool lower
 //     stream (the lookahead panel work).
 // The grid may be smaller than the tile count; each workgroup then walks the
 // slots grid-stride.
-template <typename T> struct wide_depth { static constexpr int BK = 16; };
-template <> struct wide_depth<float> { static constexpr int BK = 32; };
+// K depth of one LDS stage (double-buffered).  The one-workgroup-per-CU shape
+// has the LDS for 24-deep binary64 stages (144 KB), which cuts its stage
+// barriers, where both waves of a SIMD stall together, by a third.
+template <typename T, int WMW> struct wide_depth { static constexpr int BK = 16; };
+template <> struct wide_depth<double, 4> { static constexpr int BK = 24; };
+template <int WMW> struct wide_depth<float, WMW> { static constexpr int BK = 32; };
 
 template <typename T, int WW, int WMW>
 struct wide_cfg {
     static constexpr int TM = WW * WMW, TN = 2 * WW;
-    static constexpr int BK = wide_depth<T>::BK;
+    static constexpr int BK = wide_depth<T, WMW>::BK;
 };
 
 // One output tile (bi, bj) of C -= X Y^T: the whole K loop and the fused
@@ -119,7 +165,7 @@ __device__ __forceinline__ void wide_tile(int M, int N, int K, T* __restrict__ C
 {
     constexpr int TM = WW * WMW, TN = 2 * WW;
     constexpr int NTH = 128 * WMW;
-    constexpr int BK = wide_depth<T>::BK;
+    constexpr int BK = wide_depth<T, WMW>::BK;
     constexpr int SZ = sizeof(T);
     constexpr int NLX = BK * TM / NTH;            // staged X elements per thread per stage
     constexpr int NLY = BK * TN / NTH;            // staged Y elements per thread per stage
@@ -301,9 +347,15 @@ void update_wide_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, con
     typedef wide_cfg<T, WW, WMW> CF;
     __shared__ T As[2][CF::BK][CF::TM];   // row operand X(row0 + r, k)    stored [k][r]
     __shared__ T Bs[2][CF::BK][CF::TN];   // column operand Y(col0 + c, k) stored [k][c]
-    for (int slot = blockIdx.x; slot < g.nslots; slot += gridDim.x) {
+    // balanced order: this XCD's eighth of the tile list, strided; else the slots
+    const int xg = blockIdx.x % N_XCD;
+    const int it0 = g.balanced ? (int)((int64_t)g.ntiles * xg / N_XCD) + (int)blockIdx.x / N_XCD : (int)blockIdx.x;
+    const int it1 = g.balanced ? (int)((int64_t)g.ntiles * (xg + 1) / N_XCD) : g.nslots;
+    const int itd = g.balanced ? (int)gridDim.x / N_XCD : (int)gridDim.x;
+    for (int it = it0; it < it1; it += itd) {
         int bi, bj;
-        if (!tile_of_slot(g, slot, LOWER, bi, bj)) continue;
+        if (g.balanced) tile_of_index(g, LOWER, it, bi, bj);
+        else if (!tile_of_slot(g, it, LOWER, bi, bj)) continue;
         wide_tile<T, WW, WMW, YROWS, LOWER>(M, N, K, C, ldc, X, ldx, Y, ldy, g.shift, bi, bj, As, Bs);
     }
 }
@@ -356,9 +408,15 @@ void update_bf16_kernel(int M, int N, int K, float* __restrict__ C, int64_t ldc,
     const int sr = tid % BF_TILE, sh = tid / BF_TILE;   // staging: row, k-half
     const int nk = (K + BF_BK - 1) / BF_BK;
 
-    for (int slot = blockIdx.x; slot < g.nslots; slot += gridDim.x) {
+    // balanced order: this XCD's eighth of the tile list, strided; else the slots
+    const int xg = blockIdx.x % N_XCD;
+    const int it0 = g.balanced ? (int)((int64_t)g.ntiles * xg / N_XCD) + (int)blockIdx.x / N_XCD : (int)blockIdx.x;
+    const int it1 = g.balanced ? (int)((int64_t)g.ntiles * (xg + 1) / N_XCD) : g.nslots;
+    const int itd = g.balanced ? (int)gridDim.x / N_XCD : (int)gridDim.x;
+    for (int it = it0; it < it1; it += itd) {
         int bi, bj;
-        if (!tile_of_slot(g, slot, LOWER, bi, bj)) continue;
+        if (g.balanced) tile_of_index(g, LOWER, it, bi, bj);
+        else if (!tile_of_slot(g, it, LOWER, bi, bj)) continue;
         const int row0 = bi * BF_TILE, col0 = bj * BF_TILE;
         const int mrem = M - row0, nrem = N - col0;
         const bool active = !LOWER || (row0 + 64 * wr + 63) - (col0 + 64 * wc) >= g.shift;
@@ -464,7 +522,30 @@ Grid make_grid(int tm, int tn, int gm, int gn, int M, int N, bool lower, int shi
     // mostly empty workgroups.
     g.flat = (int64_t)g.nbm * g.nbn < 256 ? 1 : 0;
     if (g.flat) g.nslots = g.nbm * g.nbn;
+    g.balanced = 0;
+    g.nsup = nsup;
+    g.ntiles = 0;
+    if (!g.flat && nsup <= GRID_MAXSUP) {
+        g.pre[0] = 0;
+        for (int u = 0; u < nsup; ++u) {
+            int SI, SJ, c = 0;
+            super_of(g, u, SI, SJ);
+            for (int jj = 0; jj < gn; ++jj)
+                for (int ii = 0; ii < gm; ++ii) c += tile_in_region(g, lower, SI * gm + ii, SJ * gn + jj);
+            g.pre[u + 1] = g.pre[u] + c;
+        }
+        g.ntiles = g.pre[nsup];
+        g.balanced = 1;
+    }
     return g;
+}
+// Grid size of a persistent launch: at most max_wg, a multiple of the XCD count,
+// and no more than the tiles (the balanced order needs whole XCD groups).
+int persistent_grid(Grid& g, int max_wg) {
+    if (!g.balanced) return max_wg < g.nslots ? max_wg : g.nslots;
+    int nwg = max_wg < g.ntiles ? max_wg : g.ntiles;
+    nwg = (nwg + N_XCD - 1) / N_XCD * N_XCD;
+    return nwg > N_XCD ? nwg : N_XCD;
 }
 Grid make_grid(int tile, int M, int N, bool lower, int shift) {
     return make_grid(tile, tile, UPD_GROUP, UPD_GROUP, M, N, lower, shift);
@@ -544,22 +625,20 @@ hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int
         hipError_t e;
         if (narrow) {
             // 64 x 64 tiles of 32 x 32 wave parts, one tile per workgroup
-            const Grid g = make_grid(64, M, N, lower, shift);
+            Grid g = make_grid(64, M, N, lower, shift);
             int nwg = g.nslots;
-            if (max_cus > 0 && nwg > 4 * max_cus) nwg = 4 * max_cus;     // four 64-tile workgroups fit a CU
+            if (g.balanced) nwg = persistent_grid(g, g.ntiles);         // one tile per workgroup
+            if (max_cus > 0 && nwg > 4 * max_cus) nwg = persistent_grid(g, 4 * max_cus);   // four fit a CU
             e = launch_wide<T, 32, 2>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
         } else if (shape == FF_UPD_SHAPE_256x128) {
             // one workgroup per CU on all but reserve_cus CUs
-            const Grid g = make_grid(256, 128, 4, 8, M, N, lower, shift);
-            int nwg = update_workers(reserve_cus);
-            if (nwg > g.nslots) nwg = g.nslots;
+            Grid g = make_grid(256, 128, 4, 8, M, N, lower, shift);
+            const int nwg = persistent_grid(g, update_workers(reserve_cus));
             e = launch_wide<T, 64, 4>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
         } else {
             // two workgroups per CU
-            const Grid g = make_grid(128, M, N, lower, shift);
-            int nwg = 2 * update_workers(0);
-            if (max_cus > 0 && nwg > 2 * max_cus) nwg = 2 * max_cus;
-            if (nwg > g.nslots) nwg = g.nslots;
+            Grid g = make_grid(128, M, N, lower, shift);
+            const int nwg = persistent_grid(g, max_cus > 0 ? 2 * max_cus : 2 * update_workers(0));
             e = launch_wide<T, 64, 2>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
         }
         if (e != hipSuccess) return e;
@@ -584,9 +663,8 @@ hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const 
     if (!ld_fits(ldc, sizeof(float))) return hipErrorInvalidValue;
     const int kc = max_k_chunk(ldx, ldy, true, sizeof(float));
     if (kc < 1) return hipErrorInvalidValue;
-    const Grid g = make_grid(BF_TILE, M, N, lower, shift);
-    int nwg = update_workers(reserve_cus);
-    if (nwg > g.nslots) nwg = g.nslots;
+    Grid g = make_grid(BF_TILE, M, N, lower, shift);
+    const int nwg = persistent_grid(g, update_workers(reserve_cus));
     for (int k0 = 0; k0 < K; k0 += kc) {
         const int Kc = (K - k0 < kc) ? K - k0 : kc;
         const float* Xk = X + (int64_t)k0 * ldx;
