@@ -249,13 +249,14 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
 // estimate fits under the update's estimate, else the one that minimises the
 // longer of the two.  Model: the diagonal block costs about diag_us; the panel
 // solve takes 128 rows per free CU per round, a round being two 16-row blocks
-// per SIMD of 4 T(T+1)/2 MFMAs of 64 cycles each (T = 16-column tiles), issued
-// at about half the peak rate.
+// per SIMD of 4 T(T+1)/2 MFMAs of 64 cycles each (T = 16-column tiles), at the
+// measured fraction of the peak issue rate.
 int lookahead_reserve(int mr, int w, int wn, size_t sz) {
     const double rate = (sz == sizeof(double) ? 45e12 : 90e12);
     const int tiles = (std::min(wn, TRSM_MAX) + 15) / 16;
-    // measured rounds run at about half the MFMA issue rate (dependent MFMA chains)
-    const double round_us = 2.0 * (double)tiles * (tiles + 1) * 4.0 * 64.0 / 2400.0 * (sz == sizeof(double) ? 1.0 : 0.5);
+    // measured rounds take about 4.5x their MFMA issue time (dependent MFMA
+    // chains, operand loads): ~75 us for 192 columns
+    const double round_us = 4.5 * (double)tiles * (tiles + 1) * 4.0 * 64.0 / 2400.0 * (sz == sizeof(double) ? 1.0 : 0.5);
     const double diag_us = wn <= 64 ? 20.0 : wn <= 128 ? 50.0 : wn <= 192 ? 110.0 : 220.0;
     const int cus = update_workers(0);
     int best = 8;

@@ -464,17 +464,15 @@ __device__ __forceinline__ void trsm_block(int m, int w, T* x, int64_t xi, int64
                     y = AT::mfma(vt[b + 16 * k], xr[jq][i], y);
                 }
                 xr[jq] = y;
+                // one 4-deep K step at a time across all later tile columns: the
+                // MFMAs of a step are independent, so they issue back to back
 #pragma unroll
-                for (int q = jq + 1; q < TRSM_TMAX; ++q) {
-                    if (q < Tn) {
-                        const T* ut = tu + (q * (q + 1) / 2 + jq) * 256;
+                for (int i = 0; i < 4; ++i) {
+                    const int k = tcol<T>(lane, i);
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int k = tcol<T>(lane, i);
-                            xr[q] = AT::mfma(-ut[b + 16 * k], xr[jq][i], xr[q]);
-                        }
-                    }
-                    // keep the scheduler from hoisting every tile's LDS reads at once
+                    for (int q = jq + 1; q < TRSM_TMAX; ++q)
+                        if (q < Tn) xr[q] = AT::mfma(-tu[(q * (q + 1) / 2 + jq) * 256 + b + 16 * k], xr[jq][i], xr[q]);
+                    // keep the scheduler from hoisting every step's LDS reads at once
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
