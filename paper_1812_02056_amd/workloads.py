@@ -144,3 +144,38 @@ def rhs_device(n: int, nrhs: int = 1, seed: int = 0, device="cuda"):
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
     return torch.randn(nrhs, n, dtype=torch.float64, device=device, generator=gen)
+
+
+def chol_int_family_device(n: int, seed: int = 0, device="cuda"):
+    """(L0, A) on the device, for sizes where the host product is too slow: L0 lower
+    with off-diagonal entries uniform on {-1, 0, 1} and diagonal in {1, 2} (drawn on
+    the host), A = L0 L0^T formed by a binary64 GEMM, exact because every partial sum
+    is an integer of magnitude at most 4n.  Both returned row-major; A is symmetric,
+    and L0 read column-major is L0^T."""
+    import torch
+    rng = np.random.default_rng(seed)
+    off = torch.from_numpy(rng.integers(-1, 2, size=(n, n), dtype=np.int8))
+    diag = torch.from_numpy(rng.integers(1, 3, size=n, dtype=np.int8))
+    L0 = torch.tril(off.to(device=device, dtype=torch.float64), -1)
+    del off
+    L0.diagonal().copy_(diag.to(device=device, dtype=torch.float64))
+    A = torch.mm(L0, L0.t().contiguous())
+    return L0, A
+
+
+def lu_int_family_device(n: int, seed: int = 0, device="cuda"):
+    """(L0, U0, A) on the device: L0 unit lower, U0 upper with diagonal in {1, 2},
+    off-diagonal entries uniform on {-1, 0, 1}; A = L0 U0 by a binary64 GEMM (exact:
+    integer partial sums of magnitude at most 2n).  Row-major tensors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    lo = torch.from_numpy(rng.integers(-1, 2, size=(n, n), dtype=np.int8))
+    up = torch.from_numpy(rng.integers(-1, 2, size=(n, n), dtype=np.int8))
+    diag = torch.from_numpy(rng.integers(1, 3, size=n, dtype=np.int8))
+    L0 = torch.tril(lo.to(device=device, dtype=torch.float64), -1)
+    L0.diagonal().fill_(1.0)
+    U0 = torch.triu(up.to(device=device, dtype=torch.float64), 1)
+    U0.diagonal().copy_(diag.to(device=device, dtype=torch.float64))
+    del lo, up
+    A = torch.mm(L0, U0)
+    return L0, U0, A

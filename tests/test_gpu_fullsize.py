@@ -1,0 +1,97 @@
+"""Full-size GPU checks at n = 16384, in the configuration bench.py times (binary64,
+lookahead schedule, the benchmark's step sizes).  The oracle cannot run at this
+size inside a test, so the checks are ones whose expected values do not come from
+the library:
+
+* integer families: A = L0 L0^T (or L0 U0) formed by torch's binary64 GEMM, exact
+  for these entries; the factor must equal L0 (U0) bit for bit, as at small sizes;
+* the benchmark matrix A = G G^T / n + I: backward error by torch's GEMM, and
+  sampled entries of L L^T recomputed on the host in binary64 from the factor's
+  rows against A;
+* refined solves: an integer solution x0 recovered from b = A x0 (A the benchmark
+  family).
+"""
+import numpy as np
+import pytest
+
+from paper_1812_02056_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1812_02056_amd as ff  # noqa: E402
+
+DEV = torch.device("cuda:0")
+N = 16384
+
+
+def colmajor(A_rowmajor):
+    out = torch.empty_strided(A_rowmajor.shape, (1, A_rowmajor.shape[0]), dtype=A_rowmajor.dtype, device=DEV)
+    out.copy_(A_rowmajor)
+    return out
+
+
+@pytest.mark.parametrize("s", [256, 168])
+def test_fullsize_chol_integer_family_bitwise(s):
+    L0, A = wl.chol_int_family_device(N, seed=5, device=DEV)
+    Acm = A.t()                                  # symmetric: the same storage read column-major
+    assert ff.chol_factor(Acm, s, dtype="f64", sync=True) == 0
+    assert torch.equal(torch.tril(Acm), L0)
+    del L0, A, Acm
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_chol_benchmark_matrix():
+    s = 256
+    A0 = wl.spd_scaled_device(N, seed=0, device=DEV)
+    Acm = A0.clone().t()
+    assert ff.chol_factor(Acm, s, dtype="f64", sync=True) == 0
+    L = torch.tril(Acm)
+    bwd = float(torch.linalg.norm(A0.t() - L @ L.t().contiguous()) / torch.linalg.norm(A0))
+    assert bwd <= 1e-13
+    # sampled entries of L L^T against A, summed on the host in binary64
+    rng = np.random.default_rng(11)
+    idx = np.unique(np.concatenate([rng.integers(0, N, 40), [0, 1, N - 1, N - 2]]))
+    rows = L[idx].cpu().numpy()                  # the factor's rows i (L(i, :))
+    Ah = A0[idx][:, idx].cpu().numpy()
+    for a, i in enumerate(idx):
+        for b, j in enumerate(idx):
+            if j > i:
+                continue
+            k = min(i, j) + 1
+            v = float(np.dot(rows[a, :k], rows[b, :k]))
+            assert abs(v - Ah[a, b]) <= 1e-13 * max(1.0, abs(Ah[a, b])) * 4, (i, j)
+    del A0, Acm, L
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_lu_integer_family_bitwise():
+    L0, U0, A = wl.lu_int_family_device(N, seed=6, device=DEV)
+    Acm = colmajor(A)
+    del A
+    assert ff.lu_nopiv_factor(Acm, 168, sync=True) == 0
+    assert torch.equal(torch.tril(Acm, -1), torch.tril(L0, -1))
+    assert torch.equal(torch.triu(Acm), U0)
+    del L0, U0, Acm
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype,s", [("f64", 256), ("f32", 256), ("bf16", 512)])
+def test_fullsize_refined_solve_integer_solution(dtype, s):
+    # the benchmark family (kappa ~ 5); b = A x0 by torch's GEMM, so x0 is recovered
+    # to about kappa * 1e-16 (the integer family's triangular factors are too
+    # ill-conditioned to solve with at this size, though they factor exactly)
+    A = wl.spd_scaled_device(N, seed=3, device=DEV)
+    x0 = torch.randint(-1, 2, (2, N), generator=torch.Generator().manual_seed(8)).to(DEV, torch.float64)
+    B = (A @ x0.t().contiguous()).t().contiguous().t()        # column-major n x 2
+    X, W, info = ff.chol_solve(A.t(), B, s, dtype=dtype, tol=1e-13, max_iter=50)
+    assert info["info"] == 0
+    if dtype != "f64":
+        assert info["converged"] == 1
+    assert float((X - x0.t()).abs().max()) <= 1e-12
+    assert info["backward_err"] <= 1e-15
+    del A, B, X, W
+    torch.cuda.empty_cache()
