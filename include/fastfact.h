@@ -55,7 +55,16 @@ typedef enum {
 /* Flags for the factorisations. */
 enum {
     FF_FLAG_STRASSEN1 = 1u << 0,  /* one Strassen level in the trailing update
-                                      (Sec. 2, Strassen on rectangles) */
+                                      (Sec. 2, Strassen on rectangles): every
+                                      128 x 128 output super-tile takes the 7
+                                      half-K products of its 64 x 64 quadrants
+                                      instead of 8; under Cholesky, super-tiles
+                                      on the diagonal keep the 6 classical ones.
+                                      Binary64 only (FF_ERR_UNSUPPORTED for
+                                      other dtypes).  Results differ from the
+                                      classical update by rounding only; the
+                                      bound grows as K^2 u max|X| max|Y|
+                                      instead of K u sum|X||Y|. */
     FF_FLAG_NO_LOOKAHEAD = 1u << 1 /* keep every step on `stream` in strict order */
 };
 

@@ -225,7 +225,7 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
     if constexpr (sizeof(S) == sizeof(double)) {
         if ((flags & FF_FLAG_STRASSEN1) && M == N && shift == 0) {
             FF_TRY(launch_update_syrk_strassen_f64(M, w, reinterpret_cast<double*>(C), lda,
-                                                   reinterpret_cast<const double*>(P + r0), lda, info, st));
+                                                   reinterpret_cast<const double*>(P + r0), lda, info, st, reserve));
             return 0;
         }
         UpdTimer tm(M, N, w, shift, reserve, st);

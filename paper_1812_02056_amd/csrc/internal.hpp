@@ -34,9 +34,12 @@ hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const 
 int update_workers(int reserve_cus);
 // Kernel shape launch_update picks for an M x N region (FF_UPD_SHAPE_*).
 int update_shape(int M, int N, int reserve_cus);
-// One Strassen level over 2x2 super-tiles of output tiles (strassen.hip).
+// One Strassen level over 128 x 128 super-tiles of 64 x 64 quadrants
+// (strassen.hip): C -= P P^T on the lower triangle of the m x m C (P m x w), or
+// C -= X Y on all of it (X m x w, Y w x m column-major).  One workgroup per CU on
+// all but reserve_cus CUs.
 hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc, const double* P, int64_t ldp,
-                                           const int* info, hipStream_t st);
+                                           const int* info, hipStream_t st, int reserve_cus = 0);
 hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc, const double* X, int64_t ldx,
                                            const double* Y, int64_t ldy, const int* info, hipStream_t st);
 
