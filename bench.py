@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 
 MI355X_HBM_GBS = 8000.0
 MI355X_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-UPDATE_SRC = os.path.join(ROOT, "paper_1812_02056_amd", "csrc", "update.hip")
+# sources the update kernel is built from (the traffic record names their hash)
+UPDATE_SRCS = [os.path.join(ROOT, "paper_1812_02056_amd", "csrc", f) for f in ("update.hip", "grid.hpp", "common.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_wide_f64_n16384_traffic.json")
 KERNEL_OF_SHAPE = {"64x64": "update_wide_kernel<double, 32, 2, ...>",
                    "128x128": "update_wide_kernel<double, 64, 2, ...>",
@@ -62,9 +63,12 @@ def parse():
     return p.parse_args()
 
 
-def source_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -175,7 +179,7 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            if (tr.get("source_sha256_16") == source_hash(UPDATE_SRC) and int(tr.get("s", -1)) == s
+            if (tr.get("source_sha256_16") == source_hash(UPDATE_SRCS) and int(tr.get("s", -1)) == s
                     and tr.get("kernel") == kname):
                 traffic = tr.get("bytes_per_launch")
         except Exception:

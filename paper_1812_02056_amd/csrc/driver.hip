@@ -129,7 +129,10 @@ struct UpdTimer {
     double flops = 0;
     int shape = 0;
     hipStream_t st = nullptr;
-    UpdTimer(int M, int N, int K, int shift, int reserve, hipStream_t s) : st(s) {
+    UpdTimer(int M, int N, int K, int shift, int reserve, hipStream_t s, double f0 = 0.0, double f1 = 1.0) : st(s) {
+        // the tail part of a split update runs concurrently on another stream and
+        // is not recorded (the profile covers the launches on the caller's stream)
+        if (f0 > 0.0) return;
         UpdProfile& p = upd_profile();
         {
             std::lock_guard<std::mutex> lk(p.mu);
@@ -140,7 +143,8 @@ struct UpdTimer {
             e0 = e1 = nullptr;
             return;
         }
-        flops = 2.0 * (double)K * region_entries(M, N, shift);
+        const double part = f1 < 1.0 ? update_range_entries(M, N, true, shift, reserve, f0, f1) : -1.0;
+        flops = 2.0 * (double)K * (part >= 0.0 ? part : region_entries(M, N, shift));
         shape = update_shape(M, N, reserve);
         (void)hipEventRecord(e0, st);
     }
@@ -215,9 +219,12 @@ int chol_panel(int n, int c0, int w, S* A, int64_t lda, int dtype, double* ws64,
 
 // A22 region update: C(i, j) -= sum_k P(i, k) P(j, k) over rows [r0, m) and
 // columns [q0, q1) of the m x m trailing matrix, lower part only.
+// [f0, f1): the part of the region's tile order to apply (see launch_update);
+// max_cus > 0 sizes the launch for a stream that owns only that many CUs.
 template <typename S>
 int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, int q1, int dtype, unsigned flags,
-                const int* info, hipStream_t st, int reserve = 0) {
+                const int* info, hipStream_t st, int reserve = 0, double f0 = 0.0, double f1 = 1.0,
+                int max_cus = 0) {
     const int M = m - r0, N = q1 - q0;
     if (M <= 0 || N <= 0) return 0;
     S* C = A22 + (int64_t)r0 + (int64_t)q0 * lda;
@@ -228,45 +235,58 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
                                                    reinterpret_cast<const double*>(P + r0), lda, info, st, reserve));
             return 0;
         }
-        UpdTimer tm(M, N, w, shift, reserve, st);
+        UpdTimer tm(M, N, w, shift, reserve, st, f0, f1);
         FF_TRY(launch_update<double>(M, N, w, reinterpret_cast<double*>(C), lda,
                                      reinterpret_cast<const double*>(P + r0), lda,
                                      reinterpret_cast<const double*>(P + q0), lda, true, true, shift, info, st,
-                                     reserve));
+                                     reserve, max_cus, f0, f1));
         tm.stop();
     } else {
         if (dtype == FF_BF16)
             FF_TRY(launch_update_bf16(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, shift, info, st, reserve));
         else
             FF_TRY(launch_update<float>(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, true, shift, info, st,
-                                        reserve));
+                                        reserve, max_cus, f0, f1));
     }
     return 0;
 }
 
 // CUs to keep free for the next block's diagonal factorisation and panel solve
-// while the rest of the update runs: the smallest of 8/16/32/64 whose panel
-// estimate fits under the update's estimate, else the one that minimises the
-// longer of the two.  Model: the diagonal block costs about diag_us; the panel
-// solve takes 128 rows per free CU per round, a round being two 16-row blocks
-// per SIMD of 4 T(T+1)/2 MFMAs of 64 cycles each (T = 16-column tiles), at the
+// while the rest of the update runs: 32 if the panel estimate fits under the
+// update's estimate there, else the one of 32/64 that minimises the longer of
+// the two.  Model: the diagonal block costs about diag_us; the panel solve
+// takes 128 rows per free CU per round, a round being two 16-row blocks per
+// SIMD of 4 T(T+1)/2 MFMAs of 64 cycles each (T = 16-column tiles), at the
 // measured fraction of the peak issue rate.
-int lookahead_reserve(int mr, int w, int wn, size_t sz) {
-    const double rate = (sz == sizeof(double) ? 45e12 : 90e12);
+// *tail: the fraction of the update's tiles (its last ones) that the reserved
+// CUs can take after the panel work and still finish with the rest, which runs
+// on the other CUs: (U - P) / (U (1 + (C - R) / R)) for update and panel
+// estimates U and P, less a margin (0 when the panel is the longer).
+int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail) {
+    const double rate = (sz == sizeof(double) ? 50e12 : 90e12);
     const int tiles = (std::min(wn, TRSM_MAX) + 15) / 16;
-    // measured rounds take about 4.5x their MFMA issue time (dependent MFMA
-    // chains, operand loads): ~75 us for 192 columns
-    const double round_us = 4.5 * (double)tiles * (tiles + 1) * 4.0 * 64.0 / 2400.0 * (sz == sizeof(double) ? 1.0 : 0.5);
-    const double diag_us = wn <= 64 ? 20.0 : wn <= 128 ? 50.0 : wn <= 192 ? 110.0 : 220.0;
+    // measured rounds take about twice their MFMA issue time (dependent MFMA
+    // chains, operand loads): ~33 us for 192 columns
+    const double round_us = 2.0 * (double)tiles * (tiles + 1) * 4.0 * 64.0 / 2400.0 * (sz == sizeof(double) ? 1.0 : 0.5);
+    // diagonal block, plus for wn > 192 the second panel-solve chunk and the
+    // update between the chunks (fitted to traces at wn = 256)
+    const double diag_us = wn <= 64 ? 30.0 : wn <= 128 ? 60.0 : wn <= 192 ? 110.0 : 290.0 + (wn - 256);
     const int cus = update_workers(0);
-    int best = 8;
-    double best_t = 1e30;
-    for (int r : {8, 16, 32, 64}) {
+    // At least 4 free CUs per XCD: with fewer, the side stream's workgroups are
+    // often placed behind the update's (the free CUs of an XCD are not all
+    // reachable) and the panel solve waits for the whole update to drain.
+    int best = 32;
+    double best_t = 1e30, best_u = 0, best_p = 0;
+    for (int r : {32, 64}) {
         const double upd_us = (double)mr * (double)mr * (double)w / (rate * (double)(cus - r) / cus) * 1e6;
-        const double pan_us = diag_us + std::ceil((double)mr / (128.0 * r)) * round_us * (wn > TRSM_MAX ? 1.3 : 1.0);
+        const double pan_us = diag_us + std::ceil((double)mr / (128.0 * r)) * round_us * (wn > TRSM_MAX ? 1.1 : 1.0);
         const double t = std::max(upd_us, pan_us);
-        if (pan_us <= upd_us) return r;
-        if (t < best_t) { best_t = t; best = r; }
+        if (t < best_t) { best_t = t; best = r; best_u = upd_us; best_p = pan_us; }
+        if (pan_us <= upd_us) break;
+    }
+    if (tail) {
+        const double f = best_u > best_p ? (best_u - best_p) / (best_u * (1.0 + (double)(cus - best) / best)) : 0.0;
+        *tail = 0.9 * f;
     }
     return best;
 }
@@ -320,13 +340,23 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         if (!en || hipEventRecord(en, st) != hipSuccess || hipStreamWaitEvent(side, en, 0) != hipSuccess)
             return fail(FF_ERR_HIP);
         // 2) the rest of the update, concurrently with the next panel, on all but
-        //    `reserve` CUs; the panel solve's grid is sized to those free CUs
-        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S));
+        //    `reserve` CUs; the panel solve's grid is sized to those free CUs,
+        //    which then take the last `tail` of the update's tile order
+        double tail = 0.0;
+        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S), &tail);
+        if ((flags & FF_FLAG_STRASSEN1) || dtype == FF_BF16 || tail < 0.01 ||
+            !update_splittable(m - wn, m - wn, true, 0, reserve))
+            tail = 0.0;
         rc = chol_panel<S>(n, c0 + w, wn, A, lda, dtype, ws64, info, col_base, side, reserve);
         if (rc) return fail(rc);
+        if (tail > 0.0) {
+            rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, side, reserve, 1.0 - tail, 1.0,
+                                reserve);
+            if (rc) return fail(rc);
+        }
         hipEvent_t ep2 = evs.make();
         if (!ep2 || hipEventRecord(ep2, side) != hipSuccess) return fail(FF_ERR_HIP);
-        rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, st, reserve);
+        rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, st, reserve, 0.0, 1.0 - tail);
         if (rc) return fail(rc);
         if (hipStreamWaitEvent(st, ep2, 0) != hipSuccess) return fail(FF_ERR_HIP);
     }

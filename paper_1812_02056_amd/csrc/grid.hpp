@@ -27,6 +27,7 @@ struct Grid {
     int balanced;
     int nsup;
     int ntiles;
+    int tfirst, tlast;          // the launch covers tiles [tfirst, tlast) of the balanced order
     int pre[GRID_MAXSUP + 1];   // tiles in super-tiles [0, u)
 };
 
@@ -47,7 +48,7 @@ __host__ __device__ __forceinline__ bool tile_in_region(const Grid& g, bool lowe
 }
 
 // The t-th tile of the balanced order (column-major inside a super-tile).
-__device__ __forceinline__ void tile_of_index(const Grid& g, bool lower, int t, int& bi, int& bj) {
+__host__ __device__ __forceinline__ void tile_of_index(const Grid& g, bool lower, int t, int& bi, int& bj) {
     int lo = 0, hi = g.nsup - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -70,6 +71,23 @@ __device__ __forceinline__ void tile_of_index(const Grid& g, bool lower, int t, 
                 if (local == 0) { bi = SI * g.gm + r; bj = SJ * g.gn + c; return; }
                 --local;
             }
+}
+
+// This workgroup's walk over the tile order: a balanced grid's range [tfirst,
+// tlast) is cut into 8 contiguous XCD shares (workgroup b runs on XCD b % 8),
+// each walked grid-stride by that XCD's workgroups; a flat grid walks its slots.
+__device__ __forceinline__ void tile_walk(const Grid& g, int& it0, int& it1, int& itd) {
+    if (g.balanced) {
+        const int xg = blockIdx.x % N_XCD;
+        const int64_t nt = g.tlast - g.tfirst;
+        it0 = g.tfirst + (int)(nt * xg / N_XCD) + (int)blockIdx.x / N_XCD;
+        it1 = g.tfirst + (int)(nt * (xg + 1) / N_XCD);
+        itd = (int)gridDim.x / N_XCD;
+    } else {
+        it0 = (int)blockIdx.x;
+        it1 = g.nslots;
+        itd = (int)gridDim.x;
+    }
 }
 
 // Map a flat slot to an output tile (bi, bj).  Returns false when the slot is
@@ -121,6 +139,7 @@ inline Grid make_grid(int tm, int tn, int gm, int gn, int M, int N, bool lower, 
     g.balanced = 0;
     g.nsup = nsup;
     g.ntiles = 0;
+    g.tfirst = g.tlast = 0;
     if (!g.flat && nsup <= GRID_MAXSUP) {
         g.pre[0] = 0;
         for (int u = 0; u < nsup; ++u) {
@@ -132,6 +151,7 @@ inline Grid make_grid(int tm, int tn, int gm, int gn, int M, int N, bool lower, 
         }
         g.ntiles = g.pre[nsup];
         g.balanced = 1;
+        g.tlast = g.ntiles;
     }
     return g;
 }
@@ -139,9 +159,20 @@ inline Grid make_grid(int tm, int tn, int gm, int gn, int M, int N, bool lower, 
 // and no more than the tiles (the balanced order needs whole XCD groups).
 inline int persistent_grid(Grid& g, int max_wg) {
     if (!g.balanced) return max_wg < g.nslots ? max_wg : g.nslots;
-    int nwg = max_wg < g.ntiles ? max_wg : g.ntiles;
+    const int nt = g.tlast - g.tfirst;
+    int nwg = max_wg < nt ? max_wg : nt;
     nwg = (nwg + N_XCD - 1) / N_XCD * N_XCD;
     return nwg > N_XCD ? nwg : N_XCD;
+}
+// Restrict a balanced grid to the tiles [f0 * ntiles, f1 * ntiles) of its order
+// (0 <= f0 <= f1 <= 1).  Returns false for a flat grid, whose order is not split.
+inline bool grid_set_range(Grid& g, double f0, double f1) {
+    if (!g.balanced) return false;
+    g.tfirst = (int)(f0 * g.ntiles + 0.5);
+    g.tlast = (int)(f1 * g.ntiles + 0.5);
+    if (g.tlast > g.ntiles) g.tlast = g.ntiles;
+    if (g.tfirst > g.tlast) g.tfirst = g.tlast;
+    return true;
 }
 inline Grid make_grid(int tile, int M, int N, bool lower, int shift) {
     return make_grid(tile, tile, UPD_GROUP, UPD_GROUP, M, N, lower, shift);

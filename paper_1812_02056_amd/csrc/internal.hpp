@@ -22,10 +22,13 @@ hipError_t launch_set_int(int* p, int v, hipStream_t st);
 // nothing when *info != 0.  reserve_cus: number of CUs the (persistent) update
 // leaves free for work on other streams.  max_cus (> 0): the launch sizes its
 // grid for that many CUs (work on a stream that owns only the reserved CUs).
+// [f0, f1): the part of the region's tile order this launch covers (two launches
+// with the same shape arguments and adjoining ranges cover the region once);
+// hipErrorInvalidValue when the region is too small to have a split order.
 template <typename T>
 hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
                          bool yrows, bool lower, int shift, const int* info, hipStream_t st, int reserve_cus = 0,
-                         int max_cus = 0);
+                         int max_cus = 0, double f0 = 0.0, double f1 = 1.0);
 // bfloat16-operand form (yrows only), binary32 storage and accumulation.
 hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const float* X, int64_t ldx,
                               const float* Y, int64_t ldy, bool lower, int shift, const int* info, hipStream_t st,
@@ -34,6 +37,10 @@ hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const 
 int update_workers(int reserve_cus);
 // Kernel shape launch_update picks for an M x N region (FF_UPD_SHAPE_*).
 int update_shape(int M, int N, int reserve_cus);
+// Whether launch_update can split that region's tile order ([f0, f1) ranges).
+bool update_splittable(int M, int N, bool lower, int shift, int reserve_cus);
+// Entries of C that the [f0, f1) part of that split order writes (-1: no split order).
+double update_range_entries(int M, int N, bool lower, int shift, int reserve_cus, double f0, double f1);
 // One Strassen level over 128 x 128 super-tiles of 64 x 64 quadrants
 // (strassen.hip): C -= P P^T on the lower triangle of the m x m C (P m x w), or
 // C -= X Y on all of it (X m x w, Y w x m column-major).  One workgroup per CU on

@@ -260,11 +260,8 @@ void strassen_kernel(int M, int N, int K, double* __restrict__ C, int64_t ldc, c
     if (info && *info != 0) return;
     __shared__ double As[2][NPROD][SBK][lds_pitch<YROWS>::P];    // X-side sums, [k][row]
     __shared__ double Bs[2][NPROD][SBK][lds_pitch<YROWS>::P];    // Y-side sums, [k][column]
-    // balanced order: this XCD's eighth of the super-tile list, strided; else the slots
-    const int xg = blockIdx.x % N_XCD;
-    const int it0 = g.balanced ? (int)((int64_t)g.ntiles * xg / N_XCD) + (int)blockIdx.x / N_XCD : (int)blockIdx.x;
-    const int it1 = g.balanced ? (int)((int64_t)g.ntiles * (xg + 1) / N_XCD) : g.nslots;
-    const int itd = g.balanced ? (int)gridDim.x / N_XCD : (int)gridDim.x;
+    int it0, it1, itd;
+    tile_walk(g, it0, it1, itd);
     for (int it = it0; it < it1; it += itd) {
         int bi, bj;
         if (g.balanced) tile_of_index(g, LOWER, it, bi, bj);

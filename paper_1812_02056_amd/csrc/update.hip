@@ -27,6 +27,8 @@
 // Element types: double (v_mfma_f64_16x16x4f64), float (v_mfma_f32_16x16x4f32),
 // and bf16 operands (binary32 storage, operands rounded to bfloat16 while staged
 // into LDS, binary32 accumulation, v_mfma_f32_16x16x32_bf16; YROWS only).
+#include <algorithm>
+
 #include "common.hpp"
 #include "fastfact.h"
 #include "grid.hpp"
@@ -197,32 +199,41 @@ __device__ __forceinline__ void wide_tile(int M, int N, int K, T* __restrict__ C
         store((kt + 1) & 1);
         __syncthreads();
     }
+    // Write-back C - S.  Lane part of the offset in a register, the block column
+    // in the scalar offset, the block row in the immediate.  Whole tiles read C
+    // in column-block groups, each group's loads issued before the previous
+    // group's stores and the first group's before the last stage's MFMAs, so
+    // one memory latency per tile is exposed at most.  Tiles on an edge or
+    // crossing the written region's boundary mask each entry.
+    const rsrc_t rc = make_rsrc(C + row0 + (int64_t)col0 * ldc);
+    const int li0 = WW * wr + (lane & 15);
+    const int lj0 = WW * wc + AT::col_lane(lane);
+    const int cs = (int)ldc * SZ;
+    const int cbase = (li0 + lj0 * (int)ldc) * SZ;
+    const bool full = mrem >= TM && nrem >= TN && (!LOWER || row0 - (col0 + TN - 1) >= shift);
+    const int pbase = active && full ? cbase : BUF_OOB;
+    T cv[2][NB][4];
+    auto cload = [&](int cb, T (&d)[NB][4]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int r4 = 0; r4 < NB; ++r4)
+                d[r4][r] = bufop<T, AUX_NT>::load(rc, pbase == BUF_OOB ? BUF_OOB : pbase + 16 * r4 * SZ,
+                                                  (16 * cb + AT::col_reg(r)) * cs);
+    };
+    cload(0, cv[0]);
     compute_tail((nk - 1) & 1, (K - (nk - 1) * BK + 3) / 4);
 
     if (active) {
-        // Write-back C - S.  Lane part of the offset in a register, the block
-        // column in the scalar offset, the block row in the immediate.  Tiles
-        // on an edge or crossing the written region's boundary mask each entry.
-        const rsrc_t rc = make_rsrc(C + row0 + (int64_t)col0 * ldc);
-        const int li0 = WW * wr + (lane & 15);
-        const int lj0 = WW * wc + AT::col_lane(lane);
-        const int cs = (int)ldc * SZ;
-        const int cbase = (li0 + lj0 * (int)ldc) * SZ;
-        const bool full = mrem >= TM && nrem >= TN && (!LOWER || row0 - (col0 + TN - 1) >= shift);
         if (full) {
 #pragma unroll
             for (int cb = 0; cb < NB; ++cb) {
-                T cv[NB][4];
+                if (cb + 1 < NB) cload(cb + 1, cv[(cb + 1) & 1]);
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
 #pragma unroll
                     for (int r4 = 0; r4 < NB; ++r4)
-                        cv[r4][r] = bufop<T, AUX_NT>::load(rc, cbase + 16 * r4 * SZ, (16 * cb + AT::col_reg(r)) * cs);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int r4 = 0; r4 < NB; ++r4)
-                        bufop<T, AUX_NT>::store(rc, cbase + 16 * r4 * SZ, cv[r4][r] - acc[cb][r4][r],
+                        bufop<T, AUX_NT>::store(rc, cbase + 16 * r4 * SZ, cv[cb & 1][r4][r] - acc[cb][r4][r],
                                                 (16 * cb + AT::col_reg(r)) * cs);
             }
         } else {
@@ -251,26 +262,44 @@ __device__ __forceinline__ void wide_tile(int M, int N, int K, T* __restrict__ C
     __syncthreads();   // the next tile's first stage reuses buffer 0
 }
 
+// A persistent workgroup's walk over its tiles.
 template <typename T, int WW, int WMW, bool YROWS, bool LOWER>
-__global__ __launch_bounds__(128 * WMW, 4 / WMW)
-void update_wide_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, const T* __restrict__ X, int64_t ldx,
-                        const T* __restrict__ Y, int64_t ldy, Grid g, const int* __restrict__ info)
+__device__ __forceinline__ void wide_walk(int M, int N, int K, T* __restrict__ C, int64_t ldc,
+                                          const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64_t ldy,
+                                          const Grid& g)
 {
-    if (info && *info != 0) return;
     typedef wide_cfg<T, WW, WMW> CF;
     __shared__ T As[2][CF::BK][CF::TM];   // row operand X(row0 + r, k)    stored [k][r]
     __shared__ T Bs[2][CF::BK][CF::TN];   // column operand Y(col0 + c, k) stored [k][c]
-    // balanced order: this XCD's eighth of the tile list, strided; else the slots
-    const int xg = blockIdx.x % N_XCD;
-    const int it0 = g.balanced ? (int)((int64_t)g.ntiles * xg / N_XCD) + (int)blockIdx.x / N_XCD : (int)blockIdx.x;
-    const int it1 = g.balanced ? (int)((int64_t)g.ntiles * (xg + 1) / N_XCD) : g.nslots;
-    const int itd = g.balanced ? (int)gridDim.x / N_XCD : (int)gridDim.x;
+    int it0, it1, itd;
+    tile_walk(g, it0, it1, itd);
     for (int it = it0; it < it1; it += itd) {
         int bi, bj;
         if (g.balanced) tile_of_index(g, LOWER, it, bi, bj);
         else if (!tile_of_slot(g, it, LOWER, bi, bj)) continue;
         wide_tile<T, WW, WMW, YROWS, LOWER>(M, N, K, C, ldc, X, ldx, Y, ldy, g.shift, bi, bj, As, Bs);
     }
+}
+
+template <typename T, int WW, int WMW, bool YROWS, bool LOWER>
+__global__ __launch_bounds__(128 * WMW, 4 / WMW)
+void update_wide_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, const T* __restrict__ X, int64_t ldx,
+                        const T* __restrict__ Y, int64_t ldy, Grid g, const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    wide_walk<T, WW, WMW, YROWS, LOWER>(M, N, K, C, ldc, X, ldx, Y, ldy, g);
+}
+
+// The same update over the last tiles of a split tile order, launched on the
+// stream that owns the CUs kept free for panel work once that work is done (a
+// separate entry point so that traces tell it from the main part).
+template <typename T, int WW, int WMW, bool YROWS, bool LOWER>
+__global__ __launch_bounds__(128 * WMW, 4 / WMW)
+void update_wide_tail_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc, const T* __restrict__ X,
+                             int64_t ldx, const T* __restrict__ Y, int64_t ldy, Grid g, const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    wide_walk<T, WW, WMW, YROWS, LOWER>(M, N, K, C, ldc, X, ldx, Y, ldy, g);
 }
 
 // Grouped trailing updates (many independent matrices, serving): the lower
@@ -321,11 +350,8 @@ void update_bf16_kernel(int M, int N, int K, float* __restrict__ C, int64_t ldc,
     const int sr = tid % BF_TILE, sh = tid / BF_TILE;   // staging: row, k-half
     const int nk = (K + BF_BK - 1) / BF_BK;
 
-    // balanced order: this XCD's eighth of the tile list, strided; else the slots
-    const int xg = blockIdx.x % N_XCD;
-    const int it0 = g.balanced ? (int)((int64_t)g.ntiles * xg / N_XCD) + (int)blockIdx.x / N_XCD : (int)blockIdx.x;
-    const int it1 = g.balanced ? (int)((int64_t)g.ntiles * (xg + 1) / N_XCD) : g.nslots;
-    const int itd = g.balanced ? (int)gridDim.x / N_XCD : (int)gridDim.x;
+    int it0, it1, itd;
+    tile_walk(g, it0, it1, itd);
     for (int it = it0; it < it1; it += itd) {
         int bi, bj;
         if (g.balanced) tile_of_index(g, LOWER, it, bi, bj);
@@ -426,10 +452,15 @@ inline int max_k_chunk(int64_t ldx, int64_t ldy, bool yrows, size_t sz) {
 
 template <typename T, int WW, int WMW>
 hipError_t launch_wide(int M, int N, int Kc, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
-                       bool yrows, bool lower, const Grid& g, int nwg, const int* info, hipStream_t st) {
+                       bool yrows, bool lower, const Grid& g, int nwg, const int* info, hipStream_t st,
+                       bool tail = false) {
 #define FF_WIDE_LAUNCH(YR, LO)                                                                                       \
-    hipLaunchKernelGGL((update_wide_kernel<T, WW, WMW, YR, LO>), dim3(nwg), dim3(128 * WMW), 0, st, M, N, Kc, C, ldc, \
-                       X, ldx, Y, ldy, g, info)
+    if (tail)                                                                                                        \
+        hipLaunchKernelGGL((update_wide_tail_kernel<T, WW, WMW, YR, LO>), dim3(nwg), dim3(128 * WMW), 0, st, M, N,   \
+                           Kc, C, ldc, X, ldx, Y, ldy, g, info);                                                     \
+    else                                                                                                             \
+        hipLaunchKernelGGL((update_wide_kernel<T, WW, WMW, YR, LO>), dim3(nwg), dim3(128 * WMW), 0, st, M, N, Kc, C,  \
+                           ldc, X, ldx, Y, ldy, g, info)
     if (yrows) {
         if (lower) FF_WIDE_LAUNCH(true, true);
         else FF_WIDE_LAUNCH(true, false);
@@ -450,6 +481,34 @@ int update_workers(int reserve_cus) {
     return w < N_XCD ? N_XCD : w;
 }
 
+double update_range_entries(int M, int N, bool lower, int shift, int reserve_cus, double f0, double f1) {
+    const int shape = update_shape(M, N, reserve_cus);
+    Grid g = shape == FF_UPD_SHAPE_256x128 ? make_grid(256, 128, 4, 8, M, N, lower, shift)
+           : shape == FF_UPD_SHAPE_128     ? make_grid(128, M, N, lower, shift)
+                                           : make_grid(64, M, N, lower, shift);
+    if (!grid_set_range(g, f0, f1)) return -1.0;
+    double n = 0;
+    for (int t = g.tfirst; t < g.tlast; ++t) {
+        int bi, bj;
+        tile_of_index(g, lower, t, bi, bj);
+        const int64_t r0 = (int64_t)bi * g.tm, r1 = std::min<int64_t>(r0 + g.tm, M);
+        const int64_t c0 = (int64_t)bj * g.tn, c1 = std::min<int64_t>(c0 + g.tn, N);
+        for (int64_t j = c0; j < c1; ++j) {
+            const int64_t lo = lower ? std::max<int64_t>(r0, j + shift) : r0;
+            if (r1 > lo) n += (double)(r1 - lo);
+        }
+    }
+    return n;
+}
+
+bool update_splittable(int M, int N, bool lower, int shift, int reserve_cus) {
+    const int shape = update_shape(M, N, reserve_cus);
+    if (shape == FF_UPD_SHAPE_64) return false;
+    Grid g = shape == FF_UPD_SHAPE_256x128 ? make_grid(256, 128, 4, 8, M, N, lower, shift)
+                                           : make_grid(128, M, N, lower, shift);
+    return g.balanced != 0;
+}
+
 int update_shape(int M, int N, int reserve_cus) {
     // narrow regions (fewer 128-wide tiles than half the CUs) use 64 tiles
     const bool narrow = (M < 2 * 128 || N < 2 * 128) ||
@@ -461,8 +520,9 @@ int update_shape(int M, int N, int reserve_cus) {
 template <typename T>
 hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int64_t ldx, const T* Y, int64_t ldy,
                          bool yrows, bool lower, int shift, const int* info, hipStream_t st, int reserve_cus,
-                         int max_cus) {
-    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+                         int max_cus, double f0, double f1) {
+    if (M <= 0 || N <= 0 || K <= 0 || f1 <= f0) return hipSuccess;
+    const bool part = f0 > 0.0 || f1 < 1.0;
     if (!ld_fits(ldc, sizeof(T)) || (!yrows && !ld_fits(ldy, sizeof(T)))) return hipErrorInvalidValue;
     const int kc = max_k_chunk(ldx, ldy, yrows, sizeof(T));
     if (kc < 1) return hipErrorInvalidValue;
@@ -476,20 +536,25 @@ hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int
         if (narrow) {
             // 64 x 64 tiles of 32 x 32 wave parts, one tile per workgroup
             Grid g = make_grid(64, M, N, lower, shift);
+            if (part && !grid_set_range(g, f0, f1)) return hipErrorInvalidValue;
             int nwg = g.nslots;
-            if (g.balanced) nwg = persistent_grid(g, g.ntiles);         // one tile per workgroup
+            if (g.balanced) nwg = persistent_grid(g, g.tlast - g.tfirst);   // one tile per workgroup
             if (max_cus > 0 && nwg > 4 * max_cus) nwg = persistent_grid(g, 4 * max_cus);   // four fit a CU
             e = launch_wide<T, 32, 2>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
         } else if (shape == FF_UPD_SHAPE_256x128) {
             // one workgroup per CU on all but reserve_cus CUs
             Grid g = make_grid(256, 128, 4, 8, M, N, lower, shift);
-            const int nwg = persistent_grid(g, update_workers(reserve_cus));
-            e = launch_wide<T, 64, 4>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
+            if (part && !grid_set_range(g, f0, f1)) return hipErrorInvalidValue;
+            if (g.tlast == g.tfirst && g.balanced) return hipSuccess;
+            const int nwg = persistent_grid(g, max_cus > 0 ? max_cus : update_workers(reserve_cus));
+            e = launch_wide<T, 64, 4>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st, f0 > 0.0);
         } else {
             // two workgroups per CU
             Grid g = make_grid(128, M, N, lower, shift);
+            if (part && !grid_set_range(g, f0, f1)) return hipErrorInvalidValue;
+            if (g.tlast == g.tfirst && g.balanced) return hipSuccess;
             const int nwg = persistent_grid(g, max_cus > 0 ? 2 * max_cus : 2 * update_workers(0));
-            e = launch_wide<T, 64, 2>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st);
+            e = launch_wide<T, 64, 2>(M, N, Kc, C, ldc, Xk, ldx, Yk, ldy, yrows, lower, g, nwg, info, st, f0 > 0.0);
         }
         if (e != hipSuccess) return e;
     }
@@ -532,8 +597,8 @@ hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const 
 }
 
 template hipError_t launch_update<double>(int, int, int, double*, int64_t, const double*, int64_t, const double*,
-                                          int64_t, bool, bool, int, const int*, hipStream_t, int, int);
+                                          int64_t, bool, bool, int, const int*, hipStream_t, int, int, double, double);
 template hipError_t launch_update<float>(int, int, int, float*, int64_t, const float*, int64_t, const float*,
-                                         int64_t, bool, bool, int, const int*, hipStream_t, int, int);
+                                         int64_t, bool, bool, int, const int*, hipStream_t, int, int, double, double);
 
 }  // namespace ff
