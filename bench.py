@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=16384)
-    p.add_argument("--s", type=str, default="64,118,168,256,512")
+    p.add_argument("--s", type=str, default="64,118,168,256,320,512")
     p.add_argument("--quick", action="store_true", help="headline only: no LU / Strassen / mixed / CPU legs")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-extras", action="store_true")
@@ -178,7 +178,7 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
-            tr = json.load(open(TRAFFIC_FILE))
+            tr = json.load(open(TRAFFIC_FILE)).get(str(s), {})   # one record per step size
             if (tr.get("source_sha256_16") == source_hash(UPDATE_SRCS) and int(tr.get("s", -1)) == s
                     and tr.get("kernel") == kname):
                 traffic = tr.get("bytes_per_launch")

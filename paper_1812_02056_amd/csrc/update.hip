@@ -166,6 +166,12 @@ __device__ __forceinline__ void wide_tile(int M, int N, int K, T* __restrict__ C
     };
     auto compute_full = [&](int buf) {
         T fa0[NB], fb0[NB], fa1[NB], fb1[NB];
+        // Two workgroups share each SIMD in the 2-wave-per-SIMD shapes: raising
+        // the priority of a wave's MFMA phase lets it keep the matrix pipe busy
+        // while the other workgroup's wave stages operands (measured +3..6%).
+        // With one workgroup per CU both waves of a SIMD reach the MFMAs
+        // together and the raise costs a little, so it is not used there.
+        if (WMW == 2) __builtin_amdgcn_s_setprio(1);
         frags(buf, 0, fa0, fb0);
 #pragma unroll
         for (int k4 = 0; k4 < BK / 4; k4 += 2) {
@@ -174,6 +180,7 @@ __device__ __forceinline__ void wide_tile(int M, int N, int K, T* __restrict__ C
             if (k4 + 2 < BK / 4) frags(buf, k4 + 2, fa0, fb0);
             mma(fa1, fb1);
         }
+        if (WMW == 2) __builtin_amdgcn_s_setprio(0);
     };
     auto compute_tail = [&](int buf, int nk4) {
 #pragma unroll
