@@ -86,6 +86,18 @@ __device__ __forceinline__ bool wait_flag(const int* f) {
     return true;
 }
 
+// Make this workgroup's global writes visible at agent scope, then set *f.  The
+// barrier orders every wave's writes before thread 0's release fence (which is
+// cumulative over them), so one fence, one L2 write-back, serves the
+// workgroup; the flag store after it may then be relaxed.
+__device__ __forceinline__ void publish(int* f) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // Forward (TRANS = false: L y = b) or backward (TRANS = true: L^T x = y)
 // substitution on nr <= 16 columns of X in place.  fl: [0] ticket, [1] error
 // word, [2, 2 + nblk) block flags, then nblk * TP partial flags; all start at
@@ -197,9 +209,7 @@ void trisolve_kernel(int n, int nr, const S* __restrict__ L, int64_t ldl, const 
     if (!fin) {
 #pragma unroll
         for (int q = 0; q < RHS_CHUNK / 4; ++q) mine[(int64_t)p * TB * RHS_CHUNK + r * RHS_CHUNK + g + 4 * q] = acc[q];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (tid == 0) __hip_atomic_store(&pflag[j * TP + p], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        publish(&pflag[j * TP + p]);
         return;
     }
     // apply the inverse diagonal block (column-major, ld 64)
@@ -217,9 +227,7 @@ void trisolve_kernel(int n, int nr, const S* __restrict__ L, int64_t ldl, const 
         else        { for (int k = 0; k < TB; ++k) sum += tile[k][r] * xv[k][c]; }
         if (r < nbr) X[(int64_t)(r0 + r) + (int64_t)c * ldx] = sum;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&bflag[j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    publish(&bflag[j]);
 }
 
 __global__ void fill_int_kernel(int* p, int count, int v) {
