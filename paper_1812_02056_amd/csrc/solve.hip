@@ -98,6 +98,48 @@ __device__ __forceinline__ void publish(int* f) {
     }
 }
 
+// Row r of the 64 x 64 LDS tile t (column r of it for TRANS) times the columns
+// c = g + 4q of xv.  With nr <= 4 a thread has one live column (q = 0), whose
+// dependent chain is on the critical path of a block: it is summed as four
+// interleaved partial sums added in a fixed order.  With more columns each is a
+// plain sum over k, the columns giving the thread independent chains.  (So a
+// column's rounding depends on whether nr <= 4; results are deterministic for
+// a given nr.)
+template <bool TRANS, typename S>
+__device__ __forceinline__ void dots64(const S (&t)[TB][TB + 1], const S (&xv)[TB][RHS_CHUNK], int r, int g, int nr,
+                                       S (&out)[RHS_CHUNK / 4]) {
+    constexpr int NQ = RHS_CHUNK / 4;
+    if (nr <= 4) {
+        S s0 = S(0), s1 = S(0), s2 = S(0), s3 = S(0);
+#pragma unroll 4
+        for (int k = 0; k < TB; k += 4) {
+            if (!TRANS) {
+                s0 += t[r][k] * xv[k][g];
+                s1 += t[r][k + 1] * xv[k + 1][g];
+                s2 += t[r][k + 2] * xv[k + 2][g];
+                s3 += t[r][k + 3] * xv[k + 3][g];
+            } else {
+                s0 += t[k][r] * xv[k][g];
+                s1 += t[k + 1][r] * xv[k + 1][g];
+                s2 += t[k + 2][r] * xv[k + 2][g];
+                s3 += t[k + 3][r] * xv[k + 3][g];
+            }
+        }
+        out[0] = (s0 + s1) + (s2 + s3);
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) out[q] = S(0);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int c = g + 4 * q;
+        S sum = S(0);
+        if (!TRANS) { for (int k = 0; k < TB; ++k) sum += t[r][k] * xv[k][c]; }
+        else        { for (int k = 0; k < TB; ++k) sum += t[k][r] * xv[k][c]; }
+        out[q] = sum;
+    }
+}
+
 // Forward (TRANS = false: L y = b) or backward (TRANS = true: L^T x = y)
 // substitution on nr <= 16 columns of X in place.  fl: [0] ticket, [1] error
 // word, [2, 2 + nblk) block flags, then nblk * TP partial flags; all start at
@@ -196,13 +238,12 @@ void trisolve_kernel(int n, int nr, const S* __restrict__ L, int64_t ldl, const 
             xv[a][c] = (a < nbi && c < nr) ? X[(int64_t)(i0 + a) + (int64_t)c * ldx] : S(0);
         }
         __syncthreads();
+        {
+            S sum[RHS_CHUNK / 4];
+            dots64<TRANS>(tile, xv, r, g, nr, sum);
 #pragma unroll
-        for (int q = 0; q < RHS_CHUNK / 4; ++q) {
-            const int c = g + 4 * q;
-            S sum = S(0);
-            if (!TRANS) { for (int k = 0; k < TB; ++k) sum += tile[r][k] * xv[k][c]; }
-            else        { for (int k = 0; k < TB; ++k) sum += tile[k][r] * xv[k][c]; }
-            acc[q] -= sum;
+            for (int q = 0; q < RHS_CHUNK / 4; ++q)
+                if (g + 4 * q < nr) acc[q] -= sum[q];
         }
         __syncthreads();
     }
@@ -221,11 +262,14 @@ void trisolve_kernel(int n, int nr, const S* __restrict__ L, int64_t ldl, const 
 #pragma unroll
     for (int q = 0; q < RHS_CHUNK / 4; ++q) xv[r][g + 4 * q] = acc[q];
     __syncthreads();
-    for (int c = g; c < nr; c += 4) {
-        S sum = S(0);
-        if (!TRANS) { for (int k = 0; k < TB; ++k) sum += tile[r][k] * xv[k][c]; }
-        else        { for (int k = 0; k < TB; ++k) sum += tile[k][r] * xv[k][c]; }
-        if (r < nbr) X[(int64_t)(r0 + r) + (int64_t)c * ldx] = sum;
+    {
+        S sum[RHS_CHUNK / 4];
+        dots64<TRANS>(tile, xv, r, g, nr, sum);
+#pragma unroll
+        for (int q = 0; q < RHS_CHUNK / 4; ++q) {
+            const int c = g + 4 * q;
+            if (c < nr && r < nbr) X[(int64_t)(r0 + r) + (int64_t)c * ldx] = sum[q];
+        }
     }
     publish(&bflag[j]);
 }
