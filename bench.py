@@ -279,17 +279,21 @@ def run_extras(ff, torch, wl, dev, n, A0):
         out["lu_nopiv_f64_n16384_s168"] = {"error": str(e)}
     torch.cuda.empty_cache()
 
-    # --- mixed precision + refinement vs plain binary64 solve, lambda = 1, 1 and 16 rhs
+    # --- mixed precision + refinement vs plain binary64 solve, lambda = 1, 1 and 16 rhs.
+    # Each precision at its best step size (measured); refinement stops at a
+    # relative correction of 1e-12, the solution accuracy the comparison is made at
+    # (the binary64 solve is ~1e-15 here); every result's difference from the
+    # binary64 solution is reported beside its time.
     try:
         res = {}
         for nrhs in (1, 16):
             B = wl.rhs_device(n, nrhs, seed=1000, device=dev).t()     # n x nrhs column-major
             runs = {}
-            for dtype, s, iters in (("f64", 168, 0), ("f32", 256, 50), ("bf16", 512, 50)):
+            for dtype, s, iters in (("f64", 320, 0), ("f32", 320, 50), ("bf16", 512, 50)):
                 for rep in range(2):        # first call warms up
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
-                    X, W, info = ff.chol_solve(A0.t(), B, s, dtype=dtype, tol=1e-13, max_iter=iters)
+                    X, W, info = ff.chol_solve(A0.t(), B, s, dtype=dtype, tol=1e-12, max_iter=iters)
                     torch.cuda.synchronize()
                     dt = time.perf_counter() - t0
                 runs[dtype] = (X, dt, info)
@@ -301,6 +305,9 @@ def run_extras(ff, torch, wl, dev, n, A0):
                                               "converged": info["converged"], "bwd_x": info["backward_err"],
                                               "fwd_x_vs_f64_solve": fx, "info": info["info"],
                                               "tflops_effective": round(n ** 3 / 3 / dt / 1e12, 3)}
+            for dtype in ("f32", "bf16"):
+                r_, f_ = res[f"{dtype}_nrhs{nrhs}"], res[f"f64_nrhs{nrhs}"]
+                r_["faster_than_f64"] = bool(r_["ms"] < f_["ms"] and r_["fwd_x_vs_f64_solve"] <= 1e-12)
             log(f"[bench] solves nrhs={nrhs}: {res}")
             del runs, B
         out["mixed_solve_n16384_lambda1"] = res
