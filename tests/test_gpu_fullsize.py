@@ -4,7 +4,8 @@ size inside a test, so the checks are ones whose expected values do not come fro
 the library:
 
 * integer families: A = L0 L0^T (or L0 U0) formed by torch's binary64 GEMM, exact
-  for these entries; the factor must equal L0 (U0) bit for bit, as at small sizes;
+  for these entries; the factor must equal L0 (U0) bit for bit, as at small sizes,
+  with the classical and with the one-level Strassen update;
 * the benchmark matrix A = G G^T / n + I: backward error by torch's GEMM, and
   sampled entries of L L^T recomputed on the host in binary64 from the factor's
   rows against A;
@@ -76,6 +77,41 @@ def test_fullsize_lu_integer_family_bitwise():
     assert torch.equal(torch.tril(Acm, -1), torch.tril(L0, -1))
     assert torch.equal(torch.triu(Acm), U0)
     del L0, U0, Acm
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("s", [320, 512])
+def test_fullsize_chol_strassen_integer_family_bitwise(s):
+    # one Strassen level in every trailing update (lookahead schedule): operand sums
+    # and products stay small integers, so the factor is L0 bit for bit
+    L0, A = wl.chol_int_family_device(N, seed=9, device=DEV)
+    Acm = A.t()
+    assert ff.chol_factor(Acm, s, dtype="f64", strassen=True, sync=True) == 0
+    assert torch.equal(torch.tril(Acm), L0)
+    del L0, A, Acm
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_lu_strassen_integer_family_bitwise():
+    L0, U0, A = wl.lu_int_family_device(N, seed=10, device=DEV)
+    Acm = colmajor(A)
+    del A
+    assert ff.lu_nopiv_factor(Acm, 168, strassen=True, sync=True) == 0
+    assert torch.equal(torch.tril(Acm, -1), torch.tril(L0, -1))
+    assert torch.equal(torch.triu(Acm), U0)
+    del L0, U0, Acm
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_chol_benchmark_matrix_s320():
+    # the step size the benchmark picks: backward error of the timed configuration
+    A0 = wl.spd_scaled_device(N, seed=0, device=DEV)
+    Acm = A0.clone().t()
+    assert ff.chol_factor(Acm, 320, dtype="f64", sync=True) == 0
+    L = torch.tril(Acm)
+    bwd = float(torch.linalg.norm(A0.t() - L @ L.t().contiguous()) / torch.linalg.norm(A0))
+    assert bwd <= 1e-13
+    del A0, Acm, L
     torch.cuda.empty_cache()
 
 
