@@ -262,7 +262,11 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
 // CUs can take after the panel work and still finish with the rest, which runs
 // on the other CUs: (U - P) / (U (1 + (C - R) / R)) for update and panel
 // estimates U and P, less a margin (0 when the panel is the longer).
-int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail) {
+// upd_factor: update flops per mr^2 w (1 for the lower-triangle product, 2 for
+// LU's full product); n_solves: panel solves per step (1 Cholesky, 2 LU);
+// diag_extra_us: added to the diagonal-block estimate.
+int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail, double upd_factor = 1.0, int n_solves = 1,
+                      double diag_extra_us = 0.0) {
     const double rate = (sz == sizeof(double) ? 50e12 : 90e12);
     const int tiles = (std::min(wn, TRSM_MAX) + 15) / 16;
     // measured rounds take about twice their MFMA issue time (dependent MFMA
@@ -270,7 +274,7 @@ int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail) {
     const double round_us = 2.0 * (double)tiles * (tiles + 1) * 4.0 * 64.0 / 2400.0 * (sz == sizeof(double) ? 1.0 : 0.5);
     // diagonal block, plus for wn > 192 the second panel-solve chunk and the
     // update between the chunks (fitted to traces at wn = 256)
-    const double diag_us = wn <= 64 ? 30.0 : wn <= 128 ? 60.0 : wn <= 192 ? 110.0 : 290.0 + (wn - 256);
+    const double diag_us = (wn <= 64 ? 30.0 : wn <= 128 ? 60.0 : wn <= 192 ? 110.0 : 290.0 + (wn - 256)) + diag_extra_us;
     const int cus = update_workers(0);
     // At least 4 free CUs per XCD: with fewer, the side stream's workgroups are
     // often placed behind the update's (the free CUs of an XCD are not all
@@ -278,8 +282,9 @@ int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail) {
     int best = 32;
     double best_t = 1e30, best_u = 0, best_p = 0;
     for (int r : {32, 64}) {
-        const double upd_us = (double)mr * (double)mr * (double)w / (rate * (double)(cus - r) / cus) * 1e6;
-        const double pan_us = diag_us + std::ceil((double)mr / (128.0 * r)) * round_us * (wn > TRSM_MAX ? 1.1 : 1.0);
+        const double upd_us = upd_factor * (double)mr * (double)mr * (double)w / (rate * (double)(cus - r) / cus) * 1e6;
+        const double pan_us = diag_us + n_solves * std::ceil((double)mr / (128.0 * r)) * round_us *
+                                            (wn > TRSM_MAX ? 1.1 : 1.0);
         const double t = std::max(upd_us, pan_us);
         if (t < best_t) { best_t = t; best = r; best_u = upd_us; best_p = pan_us; }
         if (pan_us <= upd_us) break;
@@ -386,7 +391,100 @@ int chol_diag(int w, S* A11, int64_t lda, int dtype, double* ws64, int* info, in
 // ---------------------------------------------------------------- LU
 // Algorithm 2 as a block schedule (Doolittle packing): diagonal GETRF, then
 // L21 = A21 U11^-1 and U12 = L11^-1 A12, then A22 -= L21 U12.
+// LU panel of block [c0, c0 + w): GETRF-nopiv of the diagonal block, then
+// L21 = A21 U11^-1 and U12 = L11^-1 A12; max_wg caps the panel solves' grids.
+int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st);
+int lu_panel(int n, int c0, int w, double* A, int64_t lda, int* info, int col_base, hipStream_t st, int max_wg = 0) {
+    double* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
+    if (w <= GETRF_DIAG_MAX) {
+        FF_TRY(launch_getrf_diag(w, A11, lda, info, col_base + c0, st));
+    } else {
+        int rc = lu_blocked(w, INNER_S, A11, lda, FF_FLAG_NO_LOOKAHEAD, info, col_base + c0, st);
+        if (rc) return rc;
+    }
+    const int m = n - c0 - w;
+    if (m <= 0) return 0;
+    double* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
+    double* A12 = A + (int64_t)c0 + (int64_t)(c0 + w) * lda;
+    // L21 U11 = A21: T(k, j) = U11(k, j) = A11[k + j*lda]
+    int rc = trsm_blocked<double>(m, w, A21, lda, true, A11, lda, false, 0, info, st, max_wg);
+    if (rc) return rc;
+    // L11 U12 = A12  <=>  U12^T L11^T = A12^T: rows of X are columns of A12,
+    // T(k, j) = L11(j, k) with unit diagonal
+    return trsm_blocked<double>(m, w, A12, lda, false, A11, lda, true, 1, info, st, max_wg);
+}
+
+// Lookahead schedule of the LU (as for Cholesky): while the rest of update k
+// runs on `st` on all but `reserve` CUs, the side stream factors block k + 1
+// (whose column and row strips were updated first) and then takes the tail of
+// update k's tile order.
+int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FF_ERR_HIP;
+    hipStream_t side = acquire_side(dev);
+    if (!side) return FF_ERR_HIP;
+    Events evs;
+    auto fail = [&](int code) { release_side(dev, side); return code; };
+    hipEvent_t e0 = evs.make();
+    if (!e0 || hipEventRecord(e0, st) != hipSuccess || hipStreamWaitEvent(side, e0, 0) != hipSuccess)
+        return fail(FF_ERR_HIP);
+    int rc = lu_panel(n, 0, std::min(s, n), A, lda, info, col_base, side);
+    if (rc) return fail(rc);
+    hipEvent_t ep = evs.make();
+    if (!ep || hipEventRecord(ep, side) != hipSuccess || hipStreamWaitEvent(st, ep, 0) != hipSuccess)
+        return fail(FF_ERR_HIP);
+    for (int c0 = 0; c0 < n; c0 += s) {
+        const int w = std::min(s, n - c0);
+        const int m = n - c0 - w;
+        if (m <= 0) break;
+        double* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
+        double* A12 = A + (int64_t)c0 + (int64_t)(c0 + w) * lda;
+        double* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
+        const int wn = std::min(s, m);
+        const int mr = m - wn;
+        // 1) the next block's column strip (all rows) and row strip
+        hipError_t e = launch_update<double>(m, wn, w, A22, lda, A21, lda, A12, lda, false, false, 0, info, st);
+        if (e == hipSuccess && mr > 0)
+            e = launch_update<double>(wn, mr, w, A22 + (int64_t)wn * lda, lda, A21, lda, A12 + (int64_t)wn * lda, lda,
+                                      false, false, 0, info, st);
+        if (e != hipSuccess) return fail(FF_ERR_HIP);
+        hipEvent_t en = evs.make();
+        if (!en || hipEventRecord(en, st) != hipSuccess || hipStreamWaitEvent(side, en, 0) != hipSuccess)
+            return fail(FF_ERR_HIP);
+        // 2) the next panel on the side stream, sized to the reserved CUs; the
+        //    rest of the update on the others, its tail on the reserved CUs after
+        //    the panel
+        double tail = 0.0;
+        const int reserve = lookahead_reserve(mr, w, wn, sizeof(double), &tail, 2.0, 2, 60.0);
+        const bool strassen = (flags & FF_FLAG_STRASSEN1) != 0;
+        if (strassen || tail < 0.01 || mr <= 0 || !update_splittable(mr, mr, false, 0, reserve)) tail = 0.0;
+        rc = lu_panel(n, c0 + w, wn, A, lda, info, col_base, side, reserve);
+        if (rc) return fail(rc);
+        double* C2 = A22 + wn + (int64_t)wn * lda;
+        double* X2 = A21 + wn;
+        double* Y2 = A12 + (int64_t)wn * lda;
+        if (tail > 0.0 &&
+            launch_update<double>(mr, mr, w, C2, lda, X2, lda, Y2, lda, false, false, 0, info, side, reserve, reserve,
+                                  1.0 - tail, 1.0) != hipSuccess)
+            return fail(FF_ERR_HIP);
+        hipEvent_t ep2 = evs.make();
+        if (!ep2 || hipEventRecord(ep2, side) != hipSuccess) return fail(FF_ERR_HIP);
+        if (mr > 0) {
+            if (strassen)
+                e = launch_update_gemm_strassen_f64(mr, w, C2, lda, X2, lda, Y2, lda, info, st, reserve);
+            else
+                e = launch_update<double>(mr, mr, w, C2, lda, X2, lda, Y2, lda, false, false, 0, info, st, reserve, 0,
+                                          0.0, 1.0 - tail);
+            if (e != hipSuccess) return fail(FF_ERR_HIP);
+        }
+        if (hipStreamWaitEvent(st, ep2, 0) != hipSuccess) return fail(FF_ERR_HIP);
+    }
+    release_side(dev, side);
+    return 0;
+}
+
 int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st) {
+    if (n > s && !(flags & FF_FLAG_NO_LOOKAHEAD)) return lu_lookahead(n, s, A, lda, flags, info, col_base, st);
     for (int c0 = 0; c0 < n; c0 += s) {
         const int w = std::min(s, n - c0);
         const int m = n - c0 - w;
@@ -394,7 +492,7 @@ int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, 
         if (w <= GETRF_DIAG_MAX) {
             FF_TRY(launch_getrf_diag(w, A11, lda, info, col_base + c0, st));
         } else {
-            int rc = lu_blocked(w, INNER_S, A11, lda, 0, info, col_base + c0, st);
+            int rc = lu_blocked(w, INNER_S, A11, lda, FF_FLAG_NO_LOOKAHEAD, info, col_base + c0, st);
             if (rc) return rc;
         }
         if (m <= 0) break;

@@ -48,7 +48,8 @@ double update_range_entries(int M, int N, bool lower, int shift, int reserve_cus
 hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc, const double* P, int64_t ldp,
                                            const int* info, hipStream_t st, int reserve_cus = 0);
 hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc, const double* X, int64_t ldx,
-                                           const double* Y, int64_t ldy, const int* info, hipStream_t st);
+                                           const double* Y, int64_t ldy, const int* info, hipStream_t st,
+                                           int reserve_cus = 0);
 
 // Job tables of the grouped (many-matrix) kernels, device resident.
 //   GroupDiag: factor the w x w block at a (binary64, w <= LDS_DIAG_MAX).

@@ -41,21 +41,35 @@ __device__ __forceinline__ void tile_update_f64(double* a, int64_t ld, const dou
     d4_t acc0 = zero_vec<d4_t>(), acc1 = zero_vec<d4_t>();
     const int ra = r0 + (lane & 15), qa = q0 + (lane & 15);
     const bool rok = ra < rmax, qok = qa < qmax;
-    int k = 0;
-    for (; k + 8 <= c; k += 8) {
-        const int k1 = k + (lane >> 4), k2 = k1 + 4;
-        const double fa1 = qok ? ub[(int64_t)k1 * uk + (int64_t)qa * uj] : 0.0;
-        const double fb1 = rok ? a[(int64_t)ra + (int64_t)k1 * ld] : 0.0;
-        const double fa2 = qok ? ub[(int64_t)k2 * uk + (int64_t)qa * uj] : 0.0;
-        const double fb2 = rok ? a[(int64_t)ra + (int64_t)k2 * ld] : 0.0;
-        acc0 = mfma_f64(fa1, fb1, acc0);
-        acc1 = mfma_f64(fa2, fb2, acc1);
-    }
-    for (; k < c; k += 4) {
-        const int k1 = k + (lane >> 4);
-        const double fa1 = (qok && k1 < c) ? ub[(int64_t)k1 * uk + (int64_t)qa * uj] : 0.0;
-        const double fb1 = (rok && k1 < c) ? a[(int64_t)ra + (int64_t)k1 * ld] : 0.0;
-        acc0 = mfma_f64(fa1, fb1, acc0);
+    // K in blocks of 32, the next block's operands loaded while the current
+    // block's MFMAs run (the diagonal kernels have few waves to hide latency
+    // with).  acc0 takes the 4-deep K groups 0, 2, 4, ... of each 8 and acc1 the
+    // odd ones, in increasing K; positions past c contribute zeros.
+    double cur[4][4], nxt[4][4];
+    auto load32 = [&](int kb, double (&d)[4][4]) {
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int k1 = kb + 8 * it + (lane >> 4), k2 = k1 + 4;
+            d[it][0] = (qok && k1 < c) ? ub[(int64_t)k1 * uk + (int64_t)qa * uj] : 0.0;
+            d[it][1] = (rok && k1 < c) ? a[(int64_t)ra + (int64_t)k1 * ld] : 0.0;
+            d[it][2] = (qok && k2 < c) ? ub[(int64_t)k2 * uk + (int64_t)qa * uj] : 0.0;
+            d[it][3] = (rok && k2 < c) ? a[(int64_t)ra + (int64_t)k2 * ld] : 0.0;
+        }
+    };
+    if (c > 0) load32(0, cur);
+    for (int kb = 0; kb < c; kb += 32) {
+        if (kb + 32 < c) load32(kb + 32, nxt);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            if (kb + 8 * it < c) {
+                acc0 = mfma_f64(cur[it][0], cur[it][1], acc0);
+                if (kb + 8 * it + 4 < c) acc1 = mfma_f64(cur[it][2], cur[it][3], acc1);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cur[it][e] = nxt[it][e];
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -144,20 +158,24 @@ bool failed = false;
             }
         }
         __syncthreads();
-        // U row panel: U[c+j, q] = A[c+j, q] - sum_{k<j} L[c+j, c+k] U[c+k, q], q >= pe
+        // U row panel: U[c+j, q] = A[c+j, q] - sum_{k<j} L[c+j, c+k] U[c+k, q], q >= pe.
+        // The column's loads are all issued first and its stores come last, so
+        // the 16 rows cost one memory latency, not 16.
         for (int q = pe + tid; q < w; q += PNT) {
             double u[PB];
 #pragma unroll
-            for (int j = 0; j < PB; ++j) {
-                if (j < nbc) {
-                    double x = a[(int64_t)(c + j) + (int64_t)q * ld];
+            for (int j = 0; j < PB; ++j) u[j] = j < nbc ? a[(int64_t)(c + j) + (int64_t)q * ld] : 0.0;
 #pragma unroll
-                    for (int k = 0; k < PB; ++k)
-                        if (k < j) x -= top[j][k] * u[k];
-                    u[j] = x;
-                    a[(int64_t)(c + j) + (int64_t)q * ld] = x;
-                }
+            for (int j = 0; j < PB; ++j) {
+                double x = u[j];
+#pragma unroll
+                for (int k = 0; k < PB; ++k)
+                    if (k < j) x -= top[j][k] * u[k];
+                u[j] = x;
             }
+#pragma unroll
+            for (int j = 0; j < PB; ++j)
+                if (j < nbc) a[(int64_t)(c + j) + (int64_t)q * ld] = u[j];
         }
         __syncthreads();
     }

@@ -303,8 +303,9 @@ hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc,
 }
 
 hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc, const double* X, int64_t ldx,
-                                           const double* Y, int64_t ldy, const int* info, hipStream_t st) {
-    return launch_strassen(m, m, w, C, ldc, X, ldx, Y, ldy, false, false, info, st, 0);
+                                           const double* Y, int64_t ldy, const int* info, hipStream_t st,
+                                           int reserve_cus) {
+    return launch_strassen(m, m, w, C, ldc, X, ldx, Y, ldy, false, false, info, st, reserve_cus);
 }
 
 }  // namespace ff
