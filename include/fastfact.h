@@ -65,7 +65,16 @@ enum {
                                       classical update by rounding only; the
                                       bound grows as K^2 u max|X| max|Y|
                                       instead of K u sum|X||Y|. */
-    FF_FLAG_NO_LOOKAHEAD = 1u << 1 /* keep every step on `stream` in strict order */
+    FF_FLAG_NO_LOOKAHEAD = 1u << 1 /* keep every step on `stream` in strict order.
+                                      Without it (Cholesky and LU), the next
+                                      block's diagonal factorisation and panel
+                                      solves run on a second, library-owned
+                                      stream (default priority, ordered by
+                                      events; the call still returns with all
+                                      work ordered before later work on
+                                      `stream`) while the rest of the update
+                                      runs on all but a few CUs.  Both
+                                      schedules give bitwise identical factors. */
 };
 
 enum {
