@@ -183,66 +183,55 @@ bool failed = false;
 
 
 // ---------------------------------------------------------------------------
-// 16 x 16 tile primitives in the MFMA output layout: for the transposed tile
-// D'[a][b] = M(b, a), lane l holds row b = l % 16 and, in register r, column
-// a = acc_traits<T>::col(l, r).  These run on one wave.
-
+// MFMA output layout of a 16 x 16 tile: for the transposed tile D'[a][b] = M(b, a),
+// lane l holds row b = l % 16 and, in register r, column a = acc_traits<T>::col(l, r).
 template <typename T>
 __device__ __forceinline__ int tcol(int lane, int r) { return acc_traits<T>::col(lane, r); }
-// lane group and register that hold column a
-template <typename T> __device__ __forceinline__ int grp_of(int a);
-template <typename T> __device__ __forceinline__ int reg_of(int a);
-template <> __device__ __forceinline__ int grp_of<double>(int a) { return a & 3; }
-template <> __device__ __forceinline__ int reg_of<double>(int a) { return a >> 2; }
-template <> __device__ __forceinline__ int grp_of<float>(int a) { return a >> 2; }
-template <> __device__ __forceinline__ int reg_of<float>(int a) { return a & 3; }
 
-// Row-wise substitution x * U = v for a 16 x 16 upper-triangular U whose element
-// (k, a) is u[a + 16 k] (LDS); v holds the tile in the layout above and is
-// overwritten by x:  x_a = (v_a - sum_{k<a} x_k U(k, a)) * (1 / U(a, a)), the
-// subtractions applied in increasing k.  uinv[a] holds 1 / U(a, a) (correctly
-// rounded, so a power-of-two pivot gives the exact quotient); null for a unit
-// diagonal.
-template <typename T, typename V>
-__device__ __forceinline__ void tile_rsolve_upper(V& v, const T* u, const T* uinv, int lane) {
-    const int b = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int a = 0; a < 16; ++a) {
-        const int ga = grp_of<T>(a), ra = reg_of<T>(a);
-        T xa = __shfl(v[ra], b + 16 * ga);
-        if (uinv) xa = xa * uinv[a];
-        if (g == ga) v[ra] = xa;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int c = tcol<T>(lane, r);
-            if (c > a) v[r] -= xa * u[c + 16 * a];
-        }
-    }
+// Row-layout 16 x 16 tile primitives: lane l holds row i = l % 16 of the tile in
+// x[0..15] (x[c] = M(i, c)); the four lane groups hold the same rows and do the
+// same work, so only lanes 0..15 need to store.
+
+// value of v in lane l (l uniform across the wave)
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// In-register Cholesky of a 16 x 16 tile (lower part meaningful).  Returns the
-// first column j (0-based) whose pivot was not > 0, or -1.  Every lane computes
-// the same pivots, so the result is uniform across the wave.  The column below
-// the pivot is scaled by the correctly rounded reciprocal of L(j, j), which is
-// also returned in rinv[j] for the solves that follow.
-__device__ __forceinline__ int tile_potrf(d4_t& v, int lane, double (&rinv)[16]) {
-    const int b = lane & 15;
+// In-register Cholesky of a 16 x 16 tile in row layout (lane l holds row
+// i = l % 16), with the rows of L^-T formed alongside.  Column j: the pivot
+// d = M(j, j) is read from lane j, L(j, j) = sqrt(d) (returned in ljj[j]), every row
+// is scaled by the correctly rounded reciprocal r_j = 1 / L(j, j), and
+// M(i, c) -= L(i, j) L(c, j) for c > j, L(c, j) read from lane c.  Every entry below
+// the diagonal receives exactly these operations; the diagonal and the entries
+// above it are left with meaningless values (the caller stores ljj), and nothing
+// else reads them, so no lane masks are needed.
+// y enters as row i of the identity and leaves as row i of L^-T: the row-wise
+// substitution y L^T = e_i takes column j's step (y_j *= r_j, then
+// y_c -= y_j L(c, j) for c > j) with the same broadcast values.
+// Returns the first column j whose pivot was not > 0, or -1 (uniform).
+__device__ __forceinline__ int row_potrf(double (&x)[16], double (&y)[16], double (&ljj)[16]) {
     int bad = -1;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const int gj = grp_of<double>(j), rj = reg_of<double>(j);
-        double colj = __shfl(v[rj], b + 16 * gj);     // M(b, j)
-        const double d = __shfl(colj, j);              // M(j, j)
+        const double d = readlane_f64(x[j], j);
         if (!(d > 0.0) && bad < 0) bad = j;
-        const double ljj = sqrt(d);
-        rinv[j] = 1.0 / ljj;
-        const double lbj = (b == j) ? ljj : colj * rinv[j];
-        if ((lane >> 4) == gj && b >= j) v[rj] = lbj;
+        ljj[j] = sqrt(d);
+        const double rj = 1.0 / ljj[j];
+        const double lij = x[j] * rj;
+        x[j] = lij;
+        y[j] = y[j] * rj;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int c = tcol<double>(lane, r);
-            const double lcj = __shfl(v[rj], c + 16 * gj);   // L(c, j) (lane c of group gj)
-            if (c > j && b >= c) v[r] -= lbj * lcj;
+        for (int c = j + 1; c < 16; ++c) {
+            const double lcj = readlane_f64(lij, c);
+            x[c] -= lij * lcj;
+            y[c] -= y[j] * lcj;
+            // y is stored only at the end: without this the compiler sinks its
+            // updates there, and the 120 broadcasts they need exhaust the
+            // scalar registers
+            asm volatile("" : "+v"(y[c]));
         }
     }
     return bad;
@@ -252,115 +241,184 @@ __device__ __forceinline__ int tile_potrf(d4_t& v, int lane, double (&rinv)[16])
 // Cholesky of the w x w diagonal block (w <= LDS_DIAG_MAX) in ONE workgroup of
 // 1024 threads.  The lower triangle is held in LDS as 16 x 16 tiles (tile (i, j),
 // i >= j, at index i(i+1)/2 + j, element (r, c) at r + 16 c) padded with the
-// identity beyond w, and factored right-looking over tile columns: one wave
-// factors the diagonal tile, the waves solve the tiles below it, then update the
-// trailing tiles with 16 x 16 x 16 MFMA products.  S is the storage type; the
-// arithmetic is binary64 in every case.
+// identity beyond w, and factored right-looking over tile columns: the waves
+// solve the tiles below the factored diagonal tile, then update the trailing
+// tiles with 16 x 16 x 16 MFMA products.  Wave 0 updates the next diagonal tile
+// first and factors it while the other waves finish the trailing update, so the
+// serial diagonal factorisation overlaps the update of the step before.  S is the
+// storage type; the arithmetic is binary64 in every case.
 constexpr int DT = 16;
 constexpr int LDS_TMAX = LDS_DIAG_MAX / DT;
 constexpr int LDS_NTILE = LDS_TMAX * (LDS_TMAX + 1) / 2;
 constexpr int PT = 1024;
+constexpr int PW = PT / 64;
 
 __device__ __forceinline__ int ltile(int i, int j) { return (i * (i + 1) / 2 + j) * 256; }
 
-// Tiles staged per thread per batch: that many global loads are in flight at
-// once, where a loop of one element per iteration would wait on each in turn.
+// Staging and write-back of the block: the PT / 256 thread quarters take every
+// fourth tile, so PSTG slots per thread cover the largest block and all its
+// global loads are in flight at once.
+constexpr int PSTG = (LDS_NTILE + PT / 256 - 1) / (PT / 256);
+// Tiles staged per thread per batch in the triangular solve's staging loop.
 constexpr int STG = 8;
+
+// (i, j) of packed lower-triangle tile t + 4, given (i, j) of tile t
+__device__ __forceinline__ void tile_step4(int& i, int& j) {
+    j += 4;
+    while (j > i) { j -= i + 1; ++i; }
+}
+
+// Orders this wave's LDS stores before its later LDS loads from other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// c -= li lj^T for 16 x 16 tiles in LDS (one wave, MFMA layout)
+__device__ __forceinline__ void tile_syrk(double* c, const double* li, const double* lj, int lane) {
+    const int b = lane & 15;
+    d4_t acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = c[b + 16 * tcol<double>(lane, r)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = tcol<double>(lane, i);
+        acc = mfma_f64(-lj[b + 16 * k], li[b + 16 * k], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c[b + 16 * tcol<double>(lane, r)] = acc[r];
+}
+
+// Factors diagonal tile kt in place (one wave) and leaves Y = L_kk^-T in yt
+// (Y(r, c) at c + 16 r).  A pivot that is not > 0 sets fail and, inside the block,
+// the info word.
+__device__ __forceinline__ void diag_tile(double* tl, int kt, double* yt, int* fail, int lane, int w,
+                                          int* info, int col_base) {
+    double* dtile = tl + ltile(kt, kt);
+    const int b = lane & 15;
+    // the identity row is formed here, not kept from an earlier step: hoisted out
+    // of the caller's loop, its 16 lane masks would take 32 scalar registers
+    int bi = b;
+    asm volatile("" : "+v"(bi));
+    double x[16], y[16], ljj[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        x[c] = dtile[b + 16 * c];
+        y[c] = bi == c ? 1.0 : 0.0;
+    }
+    const int bad = row_potrf(x, y, ljj);
+    if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            dtile[b + 16 * c] = x[c];
+            yt[c + 16 * b] = y[c];
+        }
+    }
+    // the diagonal, over what the row stores left there (LDS operations of one
+    // wave complete in order)
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dtile[17 * j] = ljj[j];
+        if (bad >= 0) {
+            *fail = bad;
+            if (DT * kt + bad < w) *info = col_base + DT * kt + bad + 1;
+        }
+    }
+}
+
+// t <- t Y for a 16 x 16 tile t in LDS (one wave, MFMA layout); yt as above
+__device__ __forceinline__ void tile_mul_yt(double* t, const double* yt, int lane) {
+    const int b = lane & 15;
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = tcol<double>(lane, s);
+        acc = mfma_f64(yt[b + 16 * k], t[b + 16 * k], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t[b + 16 * tcol<double>(lane, r)] = acc[r];
+}
 
 template <typename S>
 __device__ __forceinline__ void potrf_block(int w, S* __restrict__ blk, int64_t ldb, int* info, int col_base)
 {
     if (*info != 0) return;
     __shared__ double tl[LDS_NTILE * 256];
-    __shared__ double dinv[16];       // 1 / L(j, j) of the current diagonal tile
+    __shared__ double yt[256];        // L_kk^-T of the last factored diagonal tile
     __shared__ int fail;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int T = (w + DT - 1) / DT;
     const int ntile = T * (T + 1) / 2;
+    // thread's entry rc of tiles q0 + 4u; (i0, j0) is tile q0 (q0 < 4)
+    const int rc = tid & 255, q0 = wave >> 2;
+    const int i0 = q0 == 0 ? 0 : (q0 == 3 ? 2 : 1), j0 = q0 - i0 * (i0 + 1) / 2;
     if (tid == 0) fail = -1;
-    // Stage the lower triangle; thread owns entry rc of tiles tid/256 + (PT/256) u.
-    // Entries outside the block read a valid address and are replaced by the identity.
+    // Stage the lower triangle.  Entries outside the block read a valid address
+    // and are replaced by the identity.
     {
-        const int rc = tid & 255;
-        for (int t0 = tid >> 8; t0 < ntile; t0 += (PT / 256) * STG) {
-            double v[STG];
+        double v[PSTG];
+        int i = i0, j = j0;
 #pragma unroll
-            for (int u = 0; u < STG; ++u) {
-                const int t = t0 + (PT / 256) * u;
-                const int i = tri_row(t), j = t - i * (i + 1) / 2;
+        for (int u = 0; u < PSTG; ++u) {
+            if (q0 + 4 * u < ntile) {
                 const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
-                const bool in = t < ntile && gr < w && gc < w && gr >= gc;
+                const bool in = gr < w && gc < w && gr >= gc;
                 const double x = (double)blk[in ? gr + (int64_t)gc * ldb : 0];
                 v[u] = in ? x : (gr == gc ? 1.0 : 0.0);
             }
-#pragma unroll
-            for (int u = 0; u < STG; ++u) {
-                const int t = t0 + (PT / 256) * u;
-                if (t < ntile) tl[t * 256 + rc] = v[u];
-            }
+            tile_step4(i, j);
         }
+#pragma unroll
+        for (int u = 0; u < PSTG; ++u)
+            if (q0 + 4 * u < ntile) tl[(q0 + 4 * u) * 256 + rc] = v[u];
     }
     __syncthreads();
-    const int b = lane & 15;
-    for (int kt = 0; kt < T; ++kt) {
-        double* dtile = tl + ltile(kt, kt);
-        if (wave == 0) {
-            d4_t v;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = dtile[b + 16 * tcol<double>(lane, r)];
-            double rinv[16];
-            const int bad = tile_potrf(v, lane, rinv);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dtile[b + 16 * tcol<double>(lane, r)] = v[r];
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (lane == j) dinv[j] = rinv[j];
-            if (bad >= 0 && lane == 0) {
-                fail = bad;
-                if (DT * kt + bad < w) *info = col_base + DT * kt + bad + 1;
-            }
-        }
-        __syncthreads();
+    if (wave == 0) diag_tile(tl, 0, yt, &fail, lane, w, info, col_base);
+    __syncthreads();
+    for (int kt = 0; kt + 1 < T; ++kt) {
         if (fail >= 0) return;
-        // tiles below: X L_kk^T = A  <=>  x * U = v with U(k, a) = L_kk(a, k) = dtile[a + 16 k]
-        for (int it = kt + 1 + wave; it < T; it += PT / 64) {
-            double* t = tl + ltile(it, kt);
-            d4_t v;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = t[b + 16 * tcol<double>(lane, r)];
-            tile_rsolve_upper<double>(v, dtile, dinv, lane);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) t[b + 16 * tcol<double>(lane, r)] = v[r];
-        }
+        // tiles below: X L_kk^T = A, i.e. X = A L_kk^-T, one wave per tile
+        for (int it = kt + 1 + wave; it < T; it += PW) tile_mul_yt(tl + ltile(it, kt), yt, lane);
         __syncthreads();
-        // trailing tiles (it, jt), kt < jt <= it: A -= L_it,kt L_jt,kt^T
-        const int nr = T - kt - 1;
-        const int npair = nr * (nr + 1) / 2;
-        for (int p = wave; p < npair; p += PT / 64) {
-            const int ii = tri_row(p);
-            const int jj = p - ii * (ii + 1) / 2;
-            const int it = kt + 1 + ii, jt = kt + 1 + jj;
-            double* c = tl + ltile(it, jt);
-            const double* li = tl + ltile(it, kt);
-            const double* lj = tl + ltile(jt, kt);
-            d4_t acc;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[r] = c[b + 16 * tcol<double>(lane, r)];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = tcol<double>(lane, i);
-                acc = mfma_f64(-lj[b + 16 * k], li[b + 16 * k], acc);
+        // trailing tiles (it, jt), kt < jt <= it: A -= L_it,kt L_jt,kt^T.  Pair p = 0
+        // is the next diagonal tile: wave 0 updates and factors it, the other waves
+        // take the remaining pairs.
+        if (wave == 0) {
+            tile_syrk(tl + ltile(kt + 1, kt + 1), tl + ltile(kt + 1, kt), tl + ltile(kt + 1, kt), lane);
+            wave_lds_sync();
+            diag_tile(tl, kt + 1, yt, &fail, lane, w, info, col_base);
+        } else {
+            const int nr = T - kt - 1;
+            const int npair = nr * (nr + 1) / 2;
+            for (int p = wave; p < npair; p += PW - 1) {
+                const int ii = tri_row(p);
+                const int jj = p - ii * (ii + 1) / 2;
+                const int it = kt + 1 + ii, jt = kt + 1 + jj;
+                tile_syrk(tl + ltile(it, jt), tl + ltile(it, kt), tl + ltile(jt, kt), lane);
             }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) c[b + 16 * tcol<double>(lane, r)] = acc[r];
         }
         __syncthreads();
     }
-    for (int e = tid; e < ntile * 256; e += PT) {
-        const int t = e >> 8, rc = e & 255;
-        const int i = tri_row(t), j = t - i * (i + 1) / 2;
-        const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
-        if (gr < w && gc < w && gr >= gc) blk[gr + (int64_t)gc * ldb] = (S)tl[e];
+    if (fail >= 0) return;
+    {
+        double v[PSTG];
+#pragma unroll
+        for (int u = 0; u < PSTG; ++u)
+            if (q0 + 4 * u < ntile) v[u] = tl[(q0 + 4 * u) * 256 + rc];
+        int i = i0, j = j0;
+        // walked again rather than kept from the staging loop, where the 2 PSTG
+        // tile coordinates would hold scalar registers through the whole kernel
+        asm volatile("" : "+s"(i), "+s"(j));
+#pragma unroll
+        for (int u = 0; u < PSTG; ++u) {
+            if (q0 + 4 * u < ntile) {
+                const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
+                if (gr < w && gc < w && gr >= gc) blk[gr + (int64_t)gc * ldb] = (S)v[u];
+            }
+            tile_step4(i, j);
+        }
     }
 }
 
