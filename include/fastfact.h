@@ -93,7 +93,10 @@ const char *ff_version(void);
  * with step s).  Reads only the lower triangle of the n x n matrix A and
  * overwrites it with L; the strict upper triangle is neither read nor written.
  *   n      order, >= 0 (n = 0 is a no-op)
- *   s      step size (columns per deferred update), >= 1; s >= n means no update
+ *   s      step size (columns per deferred update), >= 1; s >= n means no update.
+ *          Over the last 6144 columns a step above 192 is cut to 192, the
+ *          widest diagonal block one workgroup factors in LDS (there the small
+ *          trailing updates leave the block factorisation on the critical path).
  *   A      device pointer, double* for FF_F64, float* for FF_F32 / FF_BF16
  *   lda    >= max(1, n)
  *   dtype  ff_dtype

@@ -296,6 +296,18 @@ int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail, double upd
     return best;
 }
 
+// Width of the Cholesky block starting at column c0 for step size s.  Over the
+// last CHOL_TAIL_COLS columns a step wider than LDS_DIAG_MAX is cut to
+// LDS_DIAG_MAX: there the trailing update is small and the next block's
+// factorisation sets the pace, and a block that fits one workgroup's LDS is
+// factored by one kernel instead of a recursive chain of four or more (measured
+// at n = 16384, s = 320 and 512: the time is flat for thresholds 4608 to 8192).
+constexpr int CHOL_TAIL_COLS = 6144;
+inline int chol_block_width(int s, int c0, int n) {
+    const int w = (s > LDS_DIAG_MAX && n - c0 <= CHOL_TAIL_COLS) ? LDS_DIAG_MAX : s;
+    return std::min(w, n - c0);
+}
+
 template <typename S>
 int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, double* ws64, int* info,
                  int col_base, hipStream_t st, bool lookahead) {
@@ -310,8 +322,8 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
     }
     int rc = 0;
     if (!side) {
-        for (int c0 = 0; c0 < n && !rc; c0 += s) {
-            const int w = std::min(s, n - c0);
+        for (int c0 = 0, w = 0; c0 < n && !rc; c0 += w) {
+            w = chol_block_width(s, c0, n);
             const int m = n - c0 - w;
             rc = chol_panel<S>(n, c0, w, A, lda, dtype, ws64, info, col_base, st);
             if (rc || m <= 0) break;
@@ -326,18 +338,18 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
     if (!e0) { release_side(dev, side); return FF_ERR_HIP; }
     auto fail = [&](int code) { release_side(dev, side); return code; };
     if (hipEventRecord(e0, st) != hipSuccess || hipStreamWaitEvent(side, e0, 0) != hipSuccess) return fail(FF_ERR_HIP);
-    rc = chol_panel<S>(n, 0, std::min(s, n), A, lda, dtype, ws64, info, col_base, side);
+    rc = chol_panel<S>(n, 0, chol_block_width(s, 0, n), A, lda, dtype, ws64, info, col_base, side);
     if (rc) return fail(rc);
     hipEvent_t ep = evs.make();
     if (!ep || hipEventRecord(ep, side) != hipSuccess || hipStreamWaitEvent(st, ep, 0) != hipSuccess)
         return fail(FF_ERR_HIP);
-    for (int c0 = 0; c0 < n; c0 += s) {
-        const int w = std::min(s, n - c0);
+    for (int c0 = 0, w = 0; c0 < n; c0 += w) {
+        w = chol_block_width(s, c0, n);
         const int m = n - c0 - w;
         if (m <= 0) break;
         S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
         S* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
-        const int wn = std::min(s, m);        // width of the next block
+        const int wn = chol_block_width(s, c0 + w, n);    // width of the next block
         // 1) the next block's columns of the update, then hand them to the side stream
         rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, wn, dtype, flags & ~FF_FLAG_STRASSEN1, info, st);
         if (rc) return fail(rc);
