@@ -259,8 +259,6 @@ __device__ __forceinline__ int ltile(int i, int j) { return (i * (i + 1) / 2 + j
 // fourth tile, so PSTG slots per thread cover the largest block and all its
 // global loads are in flight at once.
 constexpr int PSTG = (LDS_NTILE + PT / 256 - 1) / (PT / 256);
-// Tiles staged per thread per batch in the triangular solve's staging loop.
-constexpr int STG = 8;
 
 // (i, j) of packed lower-triangle tile t + 4, given (i, j) of tile t
 __device__ __forceinline__ void tile_step4(int& i, int& j) {
@@ -444,7 +442,10 @@ void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int co
 // tile inverses are dyadic rationals of fewer than 53 significant bits, so every
 // intermediate stays exact.
 constexpr int TRSM_TMAX = TRSM_MAX / DT;
-constexpr int TRSM_NT = 512;
+constexpr int TRSM_NTILE = TRSM_TMAX * (TRSM_TMAX + 1) / 2;
+// Four waves, one per SIMD: the row-block solves are MFMA-bound, and a second
+// wave on a SIMD only queues behind the first.
+constexpr int TRSM_NT = 256;
 
 // Workgroup wg of nwg solving one panel (the row-block loop strides by nwg).
 template <typename T, bool XCOL>
@@ -460,46 +461,56 @@ __device__ __forceinline__ void trsm_block(int m, int w, T* x, int64_t xi, int64
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int Tn = (w + DT - 1) / DT;
     const int ntile = Tn * (Tn + 1) / 2;
-    // Stage T's upper tiles: thread owns entry ak of tiles tid/256 + 2u.
+    // Stage T's upper tiles: thread tid owns entry tid of every tile, and all its
+    // loads are in flight at once.  Tile coordinates are compile-time constants,
+    // so each load is one buffer instruction: the thread's own offset, the tile's
+    // scalar offset, and an out-of-range offset (reading zero) outside the upper
+    // triangle of the w x w block.  The pivots' reciprocals (1 past w, where the
+    // padding is the identity, and for a unit diagonal) come from the staged values.
+    static_assert(TRSM_NT == 256, "one tile entry per thread");
     {
-        const int ak = tid & 255;
-        for (int q0 = tid >> 8; q0 < ntile; q0 += (TRSM_NT / 256) * STG) {
-            T v[STG];
+        const int ko = tid >> 4, ao = tid & 15;
+        const rsrc_t rt = make_rsrc(t);
+        const int vo = (int)((ko * tk + ao * tj) * (int64_t)sizeof(T));
+        T v[TRSM_NTILE];
+        int tt = 0, jj = 0;
 #pragma unroll
-            for (int u = 0; u < STG; ++u) {
-                const int q = q0 + (TRSM_NT / 256) * u;
-                const int tt = tri_row(q), jj = q - tt * (tt + 1) / 2;
-                const int gk = DT * jj + (ak >> 4), ga = DT * tt + (ak & 15);
-                const bool in = q < ntile && gk < w && ga < w && gk <= ga;
-                const T xv = t[in ? (int64_t)gk * tk + (int64_t)ga * tj : 0];
-                v[u] = in ? xv : (gk == ga ? T(1) : T(0));
-            }
+        for (int q = 0; q < TRSM_NTILE; ++q) {
+            const int gk = DT * jj + ko, ga = DT * tt + ao;
+            const bool in = gk < w && ga < w && gk <= ga;
+            const int so = (int)((DT * jj * tk + DT * tt * tj) * (int64_t)sizeof(T));
+            v[q] = buf_load<T>(rt, in ? vo : BUF_OOB, so);
+            if (++jj > tt) { jj = 0; ++tt; }
+        }
+        tt = 0; jj = 0;
 #pragma unroll
-            for (int u = 0; u < STG; ++u) {
-                const int q = q0 + (TRSM_NT / 256) * u;
-                if (q < ntile) tu[q * 256 + ak] = v[u];
-            }
+        for (int q = 0; q < TRSM_NTILE; ++q) {
+            const int gk = DT * jj + ko, ga = DT * tt + ao;
+            const bool in = gk < w && ga < w && gk <= ga;
+            const T x = in ? v[q] : (gk == ga ? T(1) : T(0));
+            tu[q * 256 + tid] = x;
+            if (jj == tt && ko == ao) tinv[gk] = (gk < w && !unit) ? T(1) / x : T(1);
+            if (++jj > tt) { jj = 0; ++tt; }
         }
     }
-    // reciprocals of the pivots (1 past w, where the padding is the identity)
-    for (int j = tid; j < Tn * DT; j += TRSM_NT)
-        tinv[j] = (j < w && !unit) ? T(1) / t[(int64_t)j * tk + (int64_t)j * tj] : T(1);
     __syncthreads();
-    // Invert the diagonal tiles, one wave per tile, lane a < 16 owning column a of
-    // the inverse: v_a = 1/U(a,a), v_k = -(sum_{j>k} U(k,j) v_j) / U(k,k) for k < a.
-    for (int jq = wave; jq < Tn; jq += TRSM_NT / 64) {
-        T* dt = tu + (jq * (jq + 1) / 2 + jq) * 256;
-        const T* ri = tinv + DT * jq;
-        const int a = lane & 15;
-        T v[16];
+    // Invert the diagonal tiles, one 16-lane group per tile (all of them in one
+    // round), lane a owning column a of the inverse:
+    // v_a = 1/U(a,a), v_k = -(sum_{j>k} U(k,j) v_j) / U(k,k) for k < a.
+    static_assert(TRSM_NT / 16 >= TRSM_TMAX, "a lane group per diagonal tile");
+    {
+        const int jq = tid >> 4, a = lane & 15;
+        if (jq < Tn) {
+            T* dt = tu + (jq * (jq + 1) / 2 + jq) * 256;
+            const T* ri = tinv + DT * jq;
+            T v[16];
 #pragma unroll
-        for (int k = 15; k >= 0; --k) {
-            T acc = T(0);
+            for (int k = 15; k >= 0; --k) {
+                T acc = T(0);
 #pragma unroll
-            for (int j = k + 1; j < 16; ++j) acc += dt[j + 16 * k] * v[j];   // v_j = 0 for j > a
-            v[k] = k > a ? T(0) : (k == a ? ri[k] : -acc * ri[k]);
-        }
-        if (lane < 16) {
+                for (int j = k + 1; j < 16; ++j) acc += dt[j + 16 * k] * v[j];   // v_j = 0 for j > a
+                v[k] = k > a ? T(0) : (k == a ? ri[k] : -acc * ri[k]);
+            }
 #pragma unroll
             for (int k = 0; k < 16; ++k) dt[a + 16 * k] = v[k];
         }
@@ -628,6 +639,8 @@ hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, i
     // byte offsets inside one 16-row block (padded to whole tiles) must fit the buffer records
     const int64_t span = (16 * xi + (int64_t)(w + 16) * xj) * (int64_t)sizeof(T);
     if (span >= (int64_t)BUF_RECORDS) return hipErrorInvalidValue;
+    // T is read through one buffer resource: its w x w block must lie within the records
+    if ((int64_t)(w + DT) * (tk + tj) * (int64_t)sizeof(T) >= (int64_t)BUF_RECORDS) return hipErrorInvalidValue;
     int grid = (m + TRSM_NT / 4 - 1) / (TRSM_NT / 4);     // 16 rows per wave
     if (max_wg > 0 && grid > max_wg) grid = max_wg;
     if (xi == 1)
