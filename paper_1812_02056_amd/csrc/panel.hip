@@ -447,20 +447,75 @@ constexpr int TRSM_NTILE = TRSM_TMAX * (TRSM_TMAX + 1) / 2;
 // wave on a SIMD only queues behind the first.
 constexpr int TRSM_NT = 256;
 
+// The row blocks of the solve with NTT >= Tn tile columns, a compile-time count
+// so that every MFMA of the unrolled loops is unconditional.  Tile columns past
+// Tn are staged as the identity (diagonal tiles) and zeros, and their X entries
+// load as zero and are never stored, so they change nothing.
+template <typename T, bool XCOL, int NTT>
+__device__ __forceinline__ void trsm_rows(int m, int w, T* x, int64_t xi, int64_t xj, const T* tu, int lane,
+                                          int wave, int wg, int nwg)
+{
+    typedef acc_traits<T> AT;
+    typedef typename AT::vec V;
+    const int b = lane & 15;
+    constexpr int SZ = sizeof(T);
+    for (int r0 = (wg * (TRSM_NT / 64) + wave) * DT; r0 < m; r0 += nwg * (TRSM_NT / 64) * DT) {
+        const int row = r0 + b;
+        const bool rok = row < m;
+        V xr[NTT];
+        // every entry's whole offset is in the lane's register offset, out of
+        // range (loads read zero, stores are dropped) past row m and column w
+        const rsrc_t rx = make_rsrc(x + (int64_t)r0 * xi);
+        auto xoff = [&](int q, int r) -> int {
+            const int col = DT * q + tcol<T>(lane, r);
+            return (rok && col < w) ? (int)((b * xi + col * xj) * SZ) : BUF_OOB;
+        };
+#pragma unroll
+        for (int q = 0; q < NTT; ++q) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xr[q][r] = buf_load<T>(rx, xoff(q, r), 0);
+        }
+#pragma unroll
+        for (int jq = 0; jq < NTT; ++jq) {
+            const T* vt = tu + (jq * (jq + 1) / 2 + jq) * 256;
+            V y = zero_vec<V>();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = tcol<T>(lane, i);
+                y = AT::mfma(vt[b + 16 * k], xr[jq][i], y);
+            }
+            xr[jq] = y;
+            // one 4-deep K step at a time across all later tile columns: the MFMAs
+            // of a step are independent, so they issue back to back
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = tcol<T>(lane, i);
+#pragma unroll
+                for (int q = jq + 1; q < NTT; ++q)
+                    xr[q] = AT::mfma(-tu[(q * (q + 1) / 2 + jq) * 256 + b + 16 * k], xr[jq][i], xr[q]);
+            }
+            // one tile column's LDS operands at a time: hoisting them all spills
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int q = 0; q < NTT; ++q) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) buf_store<T>(rx, xoff(q, r), xr[q][r], 0);
+        }
+    }
+}
+
 // Workgroup wg of nwg solving one panel (the row-block loop strides by nwg).
 template <typename T, bool XCOL>
 __device__ __forceinline__ void trsm_block(int m, int w, T* x, int64_t xi, int64_t xj, const T* __restrict__ t,
                                            int64_t tk, int64_t tj, int unit, const int* info, int wg, int nwg)
 {
     if (info && *info != 0) return;
-    typedef acc_traits<T> AT;
-    typedef typename AT::vec V;
     __shared__ T tu[TRSM_TMAX * (TRSM_TMAX + 1) / 2 * 256];
     __shared__ T tinv[TRSM_MAX];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int Tn = (w + DT - 1) / DT;
-    const int ntile = Tn * (Tn + 1) / 2;
     // Stage T's upper tiles: thread tid owns entry tid of every tile, and all its
     // loads are in flight at once.  Tile coordinates are compile-time constants,
     // so each load is one buffer instruction: the thread's own offset, the tile's
@@ -517,64 +572,9 @@ __device__ __forceinline__ void trsm_block(int m, int w, T* x, int64_t xi, int64
     }
     __syncthreads();
     // Each wave walks 16-row blocks grid-stride; T stays staged for all of them.
-    const int b = lane & 15;
-    constexpr int SZ = sizeof(T);
-    for (int r0 = (wg * (TRSM_NT / 64) + wave) * DT; r0 < m; r0 += nwg * (TRSM_NT / 64) * DT) {
-        const int row = r0 + b;
-        const bool rok = row < m;
-        V xr[TRSM_TMAX];
-        // Column-major X: one register offset per lane (row, lane-group column),
-        // the tile column in the scalar offset; columns at or past w lie past the
-        // resource's records and rows past m get an out-of-range offset.
-        const rsrc_t rx = make_rsrc_n(x + (int64_t)r0 * xi, XCOL ? (int)((int64_t)w * xj * SZ) : BUF_RECORDS);
-        const int vx = rok ? (int)((b * xi + AT::col_lane(lane) * xj) * SZ) : BUF_OOB;
-        auto xoff = [&](int q, int r) -> int {   // row-major X: mask every entry
-            const int col = DT * q + tcol<T>(lane, r);
-            return (rok && col < w) ? (int)((b * xi + col * xj) * SZ) : BUF_OOB;
-        };
-#pragma unroll
-        for (int q = 0; q < TRSM_TMAX; ++q) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (XCOL) xr[q][r] = q < Tn ? buf_load<T>(rx, vx, (int)((DT * q + AT::col_reg(r)) * xj * SZ)) : T(0);
-                else xr[q][r] = q < Tn ? buf_load<T>(rx, xoff(q, r), 0) : T(0);
-            }
-        }
-#pragma unroll
-        for (int jq = 0; jq < TRSM_TMAX; ++jq) {
-            if (jq < Tn) {
-                const T* vt = tu + (jq * (jq + 1) / 2 + jq) * 256;
-                V y = zero_vec<V>();
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = tcol<T>(lane, i);
-                    y = AT::mfma(vt[b + 16 * k], xr[jq][i], y);
-                }
-                xr[jq] = y;
-                // one 4-deep K step at a time across all later tile columns: the
-                // MFMAs of a step are independent, so they issue back to back
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = tcol<T>(lane, i);
-#pragma unroll
-                    for (int q = jq + 1; q < TRSM_TMAX; ++q)
-                        if (q < Tn) xr[q] = AT::mfma(-tu[(q * (q + 1) / 2 + jq) * 256 + b + 16 * k], xr[jq][i], xr[q]);
-                    // keep the scheduler from hoisting every step's LDS reads at once
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < TRSM_TMAX; ++q) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (q < Tn) {
-                    if (XCOL) buf_store<T>(rx, vx, xr[q][r], (int)((DT * q + AT::col_reg(r)) * xj * SZ));
-                    else buf_store<T>(rx, xoff(q, r), xr[q][r], 0);
-                }
-            }
-        }
-    }
+    if (Tn <= 4) trsm_rows<T, XCOL, 4>(m, w, x, xi, xj, tu, lane, wave, wg, nwg);
+    else if (Tn <= 8) trsm_rows<T, XCOL, 8>(m, w, x, xi, xj, tu, lane, wave, wg, nwg);
+    else trsm_rows<T, XCOL, TRSM_TMAX>(m, w, x, xi, xj, tu, lane, wave, wg, nwg);
 }
 
 template <typename T, bool XCOL>
