@@ -188,6 +188,7 @@ def main():
                 "frac": round(achieved / peak, 4), "traffic": traffic, "traffic_unit": "bytes/launch",
                 "kernel": kname, "avg_launch_ms": round(avg_ms, 4), "launches": pk["launches"],
                 "flops_per_launch": avg_flops,
+                "algorithmic_bytes_per_launch": round(pk.get("total_bytes", 0.0) / max(1, pk["launches"])),
                 "time_share_of_step": round(pk["total_ms"] / (K * dt * 1e3), 4),
                 "other_update_shapes": {k: v for k, v in prof.items() if k != shape and v["launches"]}}
     log(f"[bench] dominant kernel {kname}: avg {avg_ms:.3f} ms/launch over {pk['launches']} launches, "

@@ -94,9 +94,10 @@ const char *ff_version(void);
  * overwrites it with L; the strict upper triangle is neither read nor written.
  *   n      order, >= 0 (n = 0 is a no-op)
  *   s      step size (columns per deferred update), >= 1; s >= n means no update.
- *          Over the last 6144 columns a step above 192 is cut to 192, the
- *          widest diagonal block one workgroup factors in LDS (there the small
- *          trailing updates leave the block factorisation on the critical path).
+ *          For the first block and over the last 6144 columns a step above 192
+ *          is cut to 192, the widest diagonal block one workgroup factors in LDS
+ *          (there the block factorisation, not the update, is on the critical
+ *          path).
  *   A      device pointer, double* for FF_F64, float* for FF_F32 / FF_BF16
  *   lda    >= max(1, n)
  *   dtype  ff_dtype
@@ -201,14 +202,17 @@ int ff_update_gemm(int64_t m, int64_t w, void *C, int64_t ldc, const void *X, in
  *   for shape FF_UPD_SHAPE_64 (64 x 64 tiles), FF_UPD_SHAPE_128 (128 x 128
  *   tiles, two workgroups per CU) and FF_UPD_SHAPE_256x128 (256 x 128 tiles, one
  *   workgroup per CU: the lookahead update); flops are the algorithmic
- *   2 K x (entries written) of each launch.  Host-synchronous; the tallies are
- *   process-wide.  Returns 0 or FF_ERR_HIP.
+ *   2 K x (entries written) of each launch, bytes its algorithmic HBM traffic
+ *   (each entry written read and written once, the M x K panel rows of the
+ *   region read once).  Host-synchronous; the tallies are process-wide.
+ *   Returns 0 or FF_ERR_HIP.
  */
 enum { FF_UPD_SHAPE_64 = 0, FF_UPD_SHAPE_128 = 1, FF_UPD_SHAPE_256x128 = 2, FF_UPD_NSHAPES = 3 };
 typedef struct {
     int64_t launches;
     double total_ms;
     double total_flops;
+    double total_bytes;
 } ff_kernel_profile;
 int ff_update_profile_enable(int enable);
 int ff_update_profile_read(ff_kernel_profile out[FF_UPD_NSHAPES]);

@@ -52,7 +52,8 @@ class ServerStats(ctypes.Structure):
 
 
 class KernelProfile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("total_flops", ctypes.c_double)]
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("total_flops", ctypes.c_double),
+                ("total_bytes", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -307,11 +308,13 @@ def update_profile_enable(enable: bool = True):
 
 
 def update_profile_read() -> dict:
-    """Per kernel shape: launches, total_ms, total_flops since the last enable (synchronises)."""
+    """Per kernel shape: launches, total_ms, total_flops, total_bytes (algorithmic)
+    since the last enable (synchronises)."""
     out = (KernelProfile * 3)()
     _check(load().ff_update_profile_read(out), "ff_update_profile_read")
     return {UPD_SHAPES[i]: {"launches": int(out[i].launches), "total_ms": float(out[i].total_ms),
-                            "total_flops": float(out[i].total_flops)} for i in range(3)}
+                            "total_flops": float(out[i].total_flops), "total_bytes": float(out[i].total_bytes)}
+            for i in range(3)}
 
 
 class Server:

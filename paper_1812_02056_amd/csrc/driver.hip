@@ -103,7 +103,7 @@ struct UpdProfile {
     bool on = false;
     struct Rec {
         hipEvent_t e0, e1;
-        double flops;
+        double flops, bytes;
         int shape;
     };
     std::vector<Rec> recs;
@@ -126,7 +126,7 @@ double region_entries(int M, int N, int shift) {
 
 struct UpdTimer {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    double flops = 0;
+    double flops = 0, bytes = 0;
     int shape = 0;
     hipStream_t st = nullptr;
     UpdTimer(int M, int N, int K, int shift, int reserve, hipStream_t s, double f0 = 0.0, double f1 = 1.0) : st(s) {
@@ -144,7 +144,11 @@ struct UpdTimer {
             return;
         }
         const double part = f1 < 1.0 ? update_range_entries(M, N, true, shift, reserve, f0, f1) : -1.0;
-        flops = 2.0 * (double)K * (part >= 0.0 ? part : region_entries(M, N, shift));
+        const double entries = part >= 0.0 ? part : region_entries(M, N, shift);
+        flops = 2.0 * (double)K * entries;
+        // C entries read and written once, the region's panel rows (its columns
+        // are rows of the same panel) read once
+        bytes = 8.0 * (2.0 * entries + (double)M * (double)K);
         shape = update_shape(M, N, reserve);
         (void)hipEventRecord(e0, st);
     }
@@ -153,7 +157,7 @@ struct UpdTimer {
         (void)hipEventRecord(e1, st);
         UpdProfile& p = upd_profile();
         std::lock_guard<std::mutex> lk(p.mu);
-        p.recs.push_back({e0, e1, flops, shape});
+        p.recs.push_back({e0, e1, flops, bytes, shape});
         e0 = e1 = nullptr;
     }
 };
@@ -296,15 +300,16 @@ int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail, double upd
     return best;
 }
 
-// Width of the Cholesky block starting at column c0 for step size s.  Over the
-// last CHOL_TAIL_COLS columns a step wider than LDS_DIAG_MAX is cut to
-// LDS_DIAG_MAX: there the trailing update is small and the next block's
-// factorisation sets the pace, and a block that fits one workgroup's LDS is
-// factored by one kernel instead of a recursive chain of four or more (measured
-// at n = 16384, s = 320 and 512: the time is flat for thresholds 4608 to 8192).
+// Width of the Cholesky block starting at column c0 for step size s.  The first
+// block, and every block over the last CHOL_TAIL_COLS columns, is cut to
+// LDS_DIAG_MAX when s is wider: nothing overlaps the first block's factorisation,
+// and near the end the trailing update is small and the next block's
+// factorisation sets the pace; a block that fits one workgroup's LDS is factored
+// by one kernel instead of a recursive chain of four or more (measured at
+// n = 16384, s = 320 and 512: the time is flat for thresholds 4608 to 8192).
 constexpr int CHOL_TAIL_COLS = 6144;
 inline int chol_block_width(int s, int c0, int n) {
-    const int w = (s > LDS_DIAG_MAX && n - c0 <= CHOL_TAIL_COLS) ? LDS_DIAG_MAX : s;
+    const int w = (s > LDS_DIAG_MAX && (c0 == 0 || n - c0 <= CHOL_TAIL_COLS)) ? LDS_DIAG_MAX : s;
     return std::min(w, n - c0);
 }
 
@@ -862,7 +867,7 @@ int ff_update_profile_enable(int enable) {
             (void)hipEventDestroy(r.e1);
         }
         p.recs.clear();
-        for (auto& t : p.tally) t = ff_kernel_profile{0, 0.0, 0.0};
+        for (auto& t : p.tally) t = ff_kernel_profile{0, 0.0, 0.0, 0.0};
     }
     p.on = enable != 0;
     return 0;
@@ -879,6 +884,7 @@ int ff_update_profile_read(ff_kernel_profile out[FF_UPD_NSHAPES]) {
         t.launches += 1;
         t.total_ms += ms;
         t.total_flops += r.flops;
+        t.total_bytes += r.bytes;
         (void)hipEventDestroy(r.e0);
         (void)hipEventDestroy(r.e1);
     }
