@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=16384)
-    p.add_argument("--s", type=str, default="64,118,168,256,320,512")
+    p.add_argument("--s", type=str, default="64,118,168,256,320,384,512")
     p.add_argument("--quick", action="store_true", help="headline only: no LU / Strassen / mixed / CPU legs")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-extras", action="store_true")
