@@ -195,6 +195,24 @@ def main():
         f"{achieved:.2f} TFLOP/s ({achieved/peak*100:.1f}% of FP64 MFMA peak), "
         f"{pk['total_ms'] / (K * dt * 1e3) * 100:.1f}% of step time")
 
+    # the same step with every block exactly s wide (Algorithm 1's schedule verbatim):
+    # by default blocks at the start and over the last 6144 columns are 192 wide
+    fixed = None
+    if s > 192:
+        copies = [A0.clone() for _ in range(W + K)]
+        for i in range(W):
+            ff.chol_factor(copies[i].t(), s, dtype="f64", info=info, fixed_step=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(W, W + K):
+            ff.chol_factor(copies[i].t(), s, dtype="f64", info=info, fixed_step=True)
+        torch.cuda.synchronize()
+        dtf = (time.perf_counter() - t0) / K
+        fixed = {"s": s, "ms": round(dtf * 1e3, 3), "tflops": round(flops / dtf / 1e12, 3), "info": int(info.item())}
+        log(f"[bench] fixed step s={s}: {dtf*1e3:.2f} ms  {flops/dtf/1e12:.2f} TFLOP/s")
+        del copies
+        torch.cuda.empty_cache()
+
     extras = {}
     if not args.quick and not args.no_extras:
         extras = run_extras(ff, torch, wl, dev, n, A0)
@@ -218,10 +236,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"Cholesky FP64 A=GG^T/n+I n={n}, step size s={s} (best of sweep {svals})",
+        "config": {"workload": f"Cholesky FP64 A=GG^T/n+I n={n}, step size s={s} (best of sweep {svals})"
+                               + ("; first block and last 6144 columns in 192-column blocks" if s > 192 else ""),
                    "n": n, "s": s, "parallelism": "single GPU"},
         "bwd_A": bwd,
         "s_sweep": {str(k): round(v["tflops"], 3) for k, v in sweep.items()},
+        "fixed_step": fixed,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

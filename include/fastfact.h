@@ -65,7 +65,7 @@ enum {
                                       classical update by rounding only; the
                                       bound grows as K^2 u max|X| max|Y|
                                       instead of K u sum|X||Y|. */
-    FF_FLAG_NO_LOOKAHEAD = 1u << 1 /* keep every step on `stream` in strict order.
+    FF_FLAG_NO_LOOKAHEAD = 1u << 1, /* keep every step on `stream` in strict order.
                                       Without it (Cholesky and LU), the next
                                       block's diagonal factorisation and panel
                                       solves run on a second, library-owned
@@ -75,6 +75,13 @@ enum {
                                       `stream`) while the rest of the update
                                       runs on all but a few CUs.  Both
                                       schedules give bitwise identical factors. */
+    FF_FLAG_FIXED_STEP = 1u << 2    /* Cholesky: every block exactly s columns
+                                      wide (the step of Sec. 2 Algorithm 1
+                                      verbatim).  Without it, when s > 192 the
+                                      first block and the blocks of the last
+                                      6144 columns are 192 wide (see
+                                      chol_factor).  Factors differ by rounding
+                                      only.  LU blocks are always s wide. */
 };
 
 enum {
@@ -97,7 +104,7 @@ const char *ff_version(void);
  *          For the first block and over the last 6144 columns a step above 192
  *          is cut to 192, the widest diagonal block one workgroup factors in LDS
  *          (there the block factorisation, not the update, is on the critical
- *          path).
+ *          path); FF_FLAG_FIXED_STEP keeps every block s wide.
  *   A      device pointer, double* for FF_F64, float* for FF_F32 / FF_BF16
  *   lda    >= max(1, n)
  *   dtype  ff_dtype

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_PKG, "libfastfact.so")
 F64, F32, BF16 = 0, 1, 2
 FLAG_STRASSEN1 = 1
 FLAG_NO_LOOKAHEAD = 2
+FLAG_FIXED_STEP = 4
 ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED = -100, -101, -102
 
 _DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
@@ -195,9 +196,10 @@ def chol_workspace_size(n: int, s: int, dtype="f64", strassen=False) -> int:
 
 
 def chol_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_lookahead=False, stream=None,
-                ws: torch.Tensor | None = None, info: torch.Tensor | None = None, sync=False):
+                ws: torch.Tensor | None = None, info: torch.Tensor | None = None, sync=False, fixed_step=False):
     """In-place Cholesky A = L L^T (tril(A) read and overwritten).  Returns the
-    device int32 info tensor, or (sync=True) its value as a Python int."""
+    device int32 info tensor, or (sync=True) its value as a Python int.
+    fixed_step: every block exactly s wide (FF_FLAG_FIXED_STEP)."""
     lib = load()
     dt = _dt(dtype)
     n = int(A.shape[0])
@@ -205,7 +207,8 @@ def chol_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_lookahe
         raise ValueError("A must be square")
     if A.dtype != _STORAGE[dt]:
         raise ValueError(f"A must be {_STORAGE[dt]} for dtype {dtype}")
-    flags = (FLAG_STRASSEN1 if strassen else 0) | (FLAG_NO_LOOKAHEAD if no_lookahead else 0)
+    flags = ((FLAG_STRASSEN1 if strassen else 0) | (FLAG_NO_LOOKAHEAD if no_lookahead else 0)
+             | (FLAG_FIXED_STEP if fixed_step else 0))
     need = int(lib.ff_chol_workspace_size(n, s, dt, flags))
     if ws is None:
         ws = _workspace(need, A.device)

@@ -308,8 +308,9 @@ int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail, double upd
 // by one kernel instead of a recursive chain of four or more (measured at
 // n = 16384, s = 320 and 512: the time is flat for thresholds 4608 to 8192).
 constexpr int CHOL_TAIL_COLS = 6144;
-inline int chol_block_width(int s, int c0, int n) {
-    const int w = (s > LDS_DIAG_MAX && (c0 == 0 || n - c0 <= CHOL_TAIL_COLS)) ? LDS_DIAG_MAX : s;
+inline int chol_block_width(int s, int c0, int n, unsigned flags) {
+    const bool edge = c0 == 0 || n - c0 <= CHOL_TAIL_COLS;
+    const int w = (s > LDS_DIAG_MAX && edge && !(flags & FF_FLAG_FIXED_STEP)) ? LDS_DIAG_MAX : s;
     return std::min(w, n - c0);
 }
 
@@ -328,7 +329,7 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
     int rc = 0;
     if (!side) {
         for (int c0 = 0, w = 0; c0 < n && !rc; c0 += w) {
-            w = chol_block_width(s, c0, n);
+            w = chol_block_width(s, c0, n, flags);
             const int m = n - c0 - w;
             rc = chol_panel<S>(n, c0, w, A, lda, dtype, ws64, info, col_base, st);
             if (rc || m <= 0) break;
@@ -343,18 +344,18 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
     if (!e0) { release_side(dev, side); return FF_ERR_HIP; }
     auto fail = [&](int code) { release_side(dev, side); return code; };
     if (hipEventRecord(e0, st) != hipSuccess || hipStreamWaitEvent(side, e0, 0) != hipSuccess) return fail(FF_ERR_HIP);
-    rc = chol_panel<S>(n, 0, chol_block_width(s, 0, n), A, lda, dtype, ws64, info, col_base, side);
+    rc = chol_panel<S>(n, 0, chol_block_width(s, 0, n, flags), A, lda, dtype, ws64, info, col_base, side);
     if (rc) return fail(rc);
     hipEvent_t ep = evs.make();
     if (!ep || hipEventRecord(ep, side) != hipSuccess || hipStreamWaitEvent(st, ep, 0) != hipSuccess)
         return fail(FF_ERR_HIP);
     for (int c0 = 0, w = 0; c0 < n; c0 += w) {
-        w = chol_block_width(s, c0, n);
+        w = chol_block_width(s, c0, n, flags);
         const int m = n - c0 - w;
         if (m <= 0) break;
         S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
         S* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
-        const int wn = chol_block_width(s, c0 + w, n);    // width of the next block
+        const int wn = chol_block_width(s, c0 + w, n, flags);    // width of the next block
         // 1) the next block's columns of the update, then hand them to the side stream
         rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, wn, dtype, flags & ~FF_FLAG_STRASSEN1, info, st);
         if (rc) return fail(rc);
@@ -537,7 +538,7 @@ int check_common(int64_t n, int64_t s, const void* A, int64_t lda, int dtype, un
     if (n > 0 && A == nullptr) return -3;
     if (lda < std::max<int64_t>(1, n)) return -4;
     if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -5;
-    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD)) return -6;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP)) return -6;
     return 0;
 }
 
@@ -731,7 +732,7 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t ld
     if (n > 0 && W == nullptr) return -6;
     if (ldw < std::max<int64_t>(1, n)) return -7;
     if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -8;
-    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD)) return -9;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP)) return -9;
     if (n > 0 && nrhs > 0 && B == nullptr) return -11;
     if (ldb < std::max<int64_t>(1, n)) return -12;
     if (n > 0 && nrhs > 0 && X == nullptr) return -13;
@@ -801,7 +802,7 @@ int ff_update_syrk(int64_t m, int64_t w, void* C, int64_t ldc, const void* P, in
     if (m > 0 && w > 0 && P == nullptr) return -5;
     if (ldp < std::max<int64_t>(1, m)) return -6;
     if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -7;
-    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD)) return -8;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP)) return -8;
     if ((flags & FF_FLAG_STRASSEN1) && dtype != FF_F64) return FF_ERR_UNSUPPORTED;
     if (m == 0 || w == 0) return 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -836,7 +837,7 @@ int ff_update_gemm(int64_t m, int64_t w, void* C, int64_t ldc, const void* X, in
     if (m > 0 && w > 0 && Y == nullptr) return -7;
     if (ldy < std::max<int64_t>(1, w)) return -8;
     if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -9;
-    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD)) return -10;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP)) return -10;
     if (dtype == FF_BF16) return FF_ERR_UNSUPPORTED;
     if ((flags & FF_FLAG_STRASSEN1) && dtype != FF_F64) return FF_ERR_UNSUPPORTED;
     if (m == 0 || w == 0) return 0;

@@ -45,6 +45,18 @@ def test_fullsize_chol_integer_family_bitwise(s):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("fixed_step", [False, True])
+def test_fullsize_chol_integer_family_bitwise_s384(fixed_step):
+    # the benchmark's best step; by default its first block and last 6144 columns
+    # are 192-wide blocks, with fixed_step every block is 384 wide
+    L0, A = wl.chol_int_family_device(N, seed=9, device=DEV)
+    Acm = A.t()
+    assert ff.chol_factor(Acm, 384, dtype="f64", fixed_step=fixed_step, sync=True) == 0
+    assert torch.equal(torch.tril(Acm), L0)
+    del L0, A, Acm
+    torch.cuda.empty_cache()
+
+
 def test_fullsize_chol_benchmark_matrix():
     s = 256
     A0 = wl.spd_scaled_device(N, seed=0, device=DEV)

@@ -235,6 +235,47 @@ def test_lu_f64_diag_dominant(s):
     assert oracle.bwd_lu(A, LU) <= 1e-13
 
 
+# Block widths: with s > 192 the first block and the blocks of the last 6144
+# columns are 192 wide unless FF_FLAG_FIXED_STEP keeps every block s wide.  The
+# factor is unique, so both schedules must reproduce the integer family exactly
+# and the oracle within the binary64 tolerance.
+
+@pytest.mark.parametrize("n,s", [(900, 320), (1300, 256), (2000, 384), (1500, 512)])
+@pytest.mark.parametrize("fixed_step", [False, True])
+@pytest.mark.parametrize("no_lookahead", [False, True])
+def test_chol_block_widths_integer_family_bitwise(n, s, fixed_step, no_lookahead):
+    L0, A = wl.chol_int_family(n, seed=3 * n + s)
+    Ad = dev(A, ld=n + 3)
+    assert ff.chol_factor(Ad, s, dtype="f64", fixed_step=fixed_step, no_lookahead=no_lookahead, sync=True) == 0
+    assert np.array_equal(np.tril(host(Ad)), L0)
+
+
+@pytest.mark.parametrize("s", [256, 384])
+def test_chol_block_widths_scaled_family(s):
+    n = 2048
+    A = wl.spd_scaled(n, seed=s)
+    Lo, _ = oracle.chol(A)
+    out = []
+    for fixed in (False, True):
+        Ad = dev(A)
+        assert ff.chol_factor(Ad, s, dtype="f64", fixed_step=fixed, sync=True) == 0
+        L = np.tril(host(Ad))
+        assert oracle.rel_lower(L, Lo) <= 1e-11
+        assert oracle.bwd_chol(A, L) <= 1e-13
+        out.append(L)
+    # 192-wide blocks instead of s-wide ones change the rounding, not the factor
+    assert not np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("n,s", [(2000, 384), (1300, 320)])
+def test_chol_fixed_step_lookahead_matches_in_order_bitwise(n, s):
+    A = wl.spd_scaled(n, seed=n + s)
+    A1, A2 = dev(A), dev(A)
+    assert ff.chol_factor(A1, s, fixed_step=True, sync=True) == 0
+    assert ff.chol_factor(A2, s, fixed_step=True, no_lookahead=True, sync=True) == 0
+    assert np.array_equal(host(A1), host(A2))
+
+
 @pytest.mark.parametrize("n,s", [(1000, 64), (1300, 168), (2000, 256)])
 def test_lu_lookahead_matches_in_order_bitwise(n, s):
     # the lookahead schedule splits each update into strips and a remainder (and a
