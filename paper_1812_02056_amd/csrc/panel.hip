@@ -11,11 +11,13 @@
 // Algorithm 2 (LU) splits the same way into getrf_diag_kernel and two
 // triangular solves L21 = A21 U11^-1 and U12 = L11^-1 A12.
 //
-// Both diagonal kernels run in ONE workgroup: the block is processed in panels
-// of 16 columns, each first brought up to date with the columns left of it by an
-// MFMA product (left-looking), then factored column by column with each thread
-// owning whole rows in registers.  Diagonal blocks are always binary64; for
-// binary32 storage they are widened into a workspace, factored, and rounded back.
+// Both diagonal kernels run in ONE workgroup.  The LU kernel processes the block
+// in panels of 16 columns, each first brought up to date with the columns left
+// of it by MFMA products (left-looking); one wave factors the panel's 16 x 16
+// diagonal tile in registers, then every thread takes whole rows below it.  The
+// Cholesky kernel holds the block in LDS as 16 x 16 tiles (right-looking, see
+// potrf_block).  Diagonal blocks are always binary64; for binary32 storage they
+// are widened into a workspace, factored, and rounded back.
 #include <math.h>
 
 #include "common.hpp"
@@ -25,9 +27,10 @@ namespace ff {
 
 namespace {
 
-constexpr int PNT = 256;     // threads of the single-workgroup diagonal kernels
+// threads of the LU diagonal kernel: 8 waves share the left-looking tile updates
+constexpr int PNT = 512;
 constexpr int PB = 16;       // panel width
-constexpr int MAXR = GETRF_DIAG_MAX / PNT;   // rows per thread in getrf_diag_kernel
+constexpr int MAXR = (GETRF_DIAG_MAX + PNT - 1) / PNT;   // rows per thread in getrf_diag_kernel
 
 __global__ void set_int_kernel(int* p, int v) { if (threadIdx.x == 0) *p = v; }
 
@@ -80,6 +83,14 @@ __device__ __forceinline__ void tile_update_f64(double* a, int64_t ld, const dou
     }
 }
 
+// value of v in lane l (l uniform across the wave)
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Doolittle LU without pivoting of the w x w diagonal block, in place (binary64).
 __global__ __launch_bounds__(PNT)
 void getrf_diag_kernel(int w, double* a, int64_t ld, int* info, int col_base)
@@ -106,55 +117,75 @@ void getrf_diag_kernel(int w, double* a, int64_t ld, int* info, int col_base)
             }
         }
         __syncthreads();
-        double p[MAXR][PB];
+        // The panel's 16 x 16 diagonal tile, on wave 0 in row layout (lane b holds
+        // row c + b): column j's pivot and U row come from lane j, and every row
+        // below j takes l = x_j / u, x_k -= l U(j, k) (k > j), with no barrier
+        // between columns.  Columns and rows past nbc are zero and stay zero.
+        if (wave == 0) {
+            const int b = lane & 15;
+            // lane masks are formed here, not kept across the panel loop
+            int bi = b;
+            asm volatile("" : "+v"(bi));
+            double x[PB];
 #pragma unroll
-        for (int q = 0; q < MAXR; ++q) {
-            const int i = c + tid + q * PNT;
+            for (int k = 0; k < PB; ++k) x[k] = (b < nbc && k < nbc) ? a[(c + b) + (int64_t)(c + k) * ld] : 0.0;
+            int bad = -1;
 #pragma unroll
-            for (int j = 0; j < PB; ++j) p[q][j] = (i < w && j < nbc) ? a[i + (int64_t)(c + j) * ld] : 0.0;
-        }
-bool failed = false;
-#pragma unroll
-        for (int j = 0; j < PB; ++j) {
-            if (j < nbc && !failed) {
-                if (tid == j) {
-#pragma unroll
-                    for (int k = 0; k < PB; ++k)
-                        if (k >= j) top[j][k] = p[0][k];
-                    const double u = p[0][j];
+            for (int j = 0; j < PB; ++j) {
+                if (j < nbc && bad < 0) {
+                    const double u = readlane_f64(x[j], j);
                     if (u == 0.0 || !isfinite(u)) {
-                        fail = 1;
-                        *info = col_base + c + j + 1;
-                    }
-                }
-                __syncthreads();
-                failed = fail != 0;
-                if (!failed) {
-                    const double u = top[j][j];
+                        bad = j;
+                    } else {
+                        double ur[PB];
 #pragma unroll
-                    for (int q = 0; q < MAXR; ++q) {
-                        const int li = tid + q * PNT;
-                        if (c + li < w && li > j) {
-                            const double l = p[q][j] / u;
-                            p[q][j] = l;
-                            if (li < PB) top[li][j] = l;
+                        for (int k = j + 1; k < PB; ++k) ur[k] = readlane_f64(x[k], j);
+                        if (bi > j) {
+                            const double l = x[j] / u;
+                            x[j] = l;
 #pragma unroll
-                            for (int k = 0; k < PB; ++k)
-                                if (k > j && k < nbc) p[q][k] -= l * top[j][k];
+                            for (int k = j + 1; k < PB; ++k) x[k] -= l * ur[k];
                         }
                     }
-                    __syncthreads();
+                }
+            }
+            if (bad >= 0) {
+                if (lane == 0) {
+                    fail = 1;
+                    *info = col_base + c + bad + 1;
+                }
+            } else if (lane < PB) {
+#pragma unroll
+                for (int k = 0; k < PB; ++k) {
+                    top[b][k] = x[k];
+                    if (b < nbc && k < nbc) a[(c + b) + (int64_t)(c + k) * ld] = x[k];
                 }
             }
         }
-        if (failed) return;
+        __syncthreads();
+        if (fail) return;
+        // rows below the tile: the same operations, row by row, with the tile's U
 #pragma unroll
         for (int q = 0; q < MAXR; ++q) {
-            const int i = c + tid + q * PNT;
+            const int i = pe + tid + q * PNT;
             if (i < w) {
+                double p[PB];
+#pragma unroll
+                for (int j = 0; j < PB; ++j) p[j] = j < nbc ? a[i + (int64_t)(c + j) * ld] : 0.0;
+#pragma unroll
+                for (int j = 0; j < PB; ++j) {
+                    if (j < nbc) {
+                        const double l = p[j] / top[j][j];
+                        p[j] = l;
+#pragma unroll
+                        for (int k = j + 1; k < PB; ++k) p[k] -= l * top[j][k];
+                    }
+                    // one row of the tile's U at a time (hoisted, they spill)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
 #pragma unroll
                 for (int j = 0; j < PB; ++j)
-                    if (j < nbc) a[i + (int64_t)(c + j) * ld] = p[q][j];
+                    if (j < nbc) a[i + (int64_t)(c + j) * ld] = p[j];
             }
         }
         __syncthreads();
@@ -172,6 +203,7 @@ bool failed = false;
                 for (int k = 0; k < PB; ++k)
                     if (k < j) x -= top[j][k] * u[k];
                 u[j] = x;
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int j = 0; j < PB; ++j)
@@ -192,13 +224,6 @@ __device__ __forceinline__ int tcol(int lane, int r) { return acc_traits<T>::col
 // x[0..15] (x[c] = M(i, c)); the four lane groups hold the same rows and do the
 // same work, so only lanes 0..15 need to store.
 
-// value of v in lane l (l uniform across the wave)
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const long long bits = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)bits, l);
-    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // In-register Cholesky of a 16 x 16 tile in row layout (lane l holds row
 // i = l % 16), with the rows of L^-T formed alongside.  Column j: the pivot
