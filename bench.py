@@ -198,7 +198,7 @@ def main():
     # the same step with every block exactly s wide (Algorithm 1's schedule verbatim):
     # by default blocks at the start and over the last 6144 columns are 192 wide
     fixed = None
-    if s > 192:
+    if s > 192 and not args.quick and not args.no_extras:
         copies = [A0.clone() for _ in range(W + K)]
         for i in range(W):
             ff.chol_factor(copies[i].t(), s, dtype="f64", info=info, fixed_step=True)
