@@ -22,7 +22,6 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 // Inner step used when a diagonal block is larger than the single-workgroup
 // diagonal kernels take: the block is itself factored by the same delayed-update
 // schedule with this step.
-constexpr int INNER_S = 256;
 
 struct Carver {
     char* base;
@@ -412,12 +411,19 @@ int chol_diag(int w, S* A11, int64_t lda, int dtype, double* ws64, int* info, in
 // LU panel of block [c0, c0 + w): GETRF-nopiv of the diagonal block, then
 // L21 = A21 U11^-1 and U12 = L11^-1 A12; max_wg caps the panel solves' grids.
 int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st);
+// GETRF-nopiv of the w x w diagonal block: one LDS kernel up to LU_LDS_MAX,
+// blocks of LU_LDS_MAX (in order) when wider.
+int lu_diag(int w, double* A11, int64_t lda, int* info, int col_base, hipStream_t st) {
+    if (w <= LU_LDS_MAX) {
+        FF_TRY(launch_getrf_lds(w, A11, lda, info, col_base, st));
+        return 0;
+    }
+    return lu_blocked(w, LU_LDS_MAX, A11, lda, FF_FLAG_NO_LOOKAHEAD, info, col_base, st);
+}
 int lu_panel(int n, int c0, int w, double* A, int64_t lda, int* info, int col_base, hipStream_t st, int max_wg = 0) {
     double* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
-    if (w <= GETRF_DIAG_MAX) {
-        FF_TRY(launch_getrf_diag(w, A11, lda, info, col_base + c0, st));
-    } else {
-        int rc = lu_blocked(w, INNER_S, A11, lda, FF_FLAG_NO_LOOKAHEAD, info, col_base + c0, st);
+    {
+        int rc = lu_diag(w, A11, lda, info, col_base + c0, st);
         if (rc) return rc;
     }
     const int m = n - c0 - w;
@@ -507,10 +513,8 @@ int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, 
         const int w = std::min(s, n - c0);
         const int m = n - c0 - w;
         double* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
-        if (w <= GETRF_DIAG_MAX) {
-            FF_TRY(launch_getrf_diag(w, A11, lda, info, col_base + c0, st));
-        } else {
-            int rc = lu_blocked(w, INNER_S, A11, lda, FF_FLAG_NO_LOOKAHEAD, info, col_base + c0, st);
+        {
+            int rc = lu_diag(w, A11, lda, info, col_base + c0, st);
             if (rc) return rc;
         }
         if (m <= 0) break;

@@ -5,12 +5,13 @@
 
 namespace ff {
 
-// Largest diagonal block the single-workgroup diagonal kernels take (the
-// Cholesky one keeps the block in LDS); larger blocks are factored recursively
-// by the host driver.  TRSM_MAX bounds the columns of one panel-solve launch;
-// wider panels are solved in column chunks by the host.
+// Largest diagonal blocks the single-workgroup diagonal kernels take, the block
+// held in LDS (Cholesky: its lower triangle; LU: the whole square); larger
+// blocks are factored recursively by the host driver.  TRSM_MAX bounds the
+// columns of one panel-solve launch; wider panels are solved in column chunks
+// by the host.
 constexpr int LDS_DIAG_MAX = 192;
-constexpr int GETRF_DIAG_MAX = 512;
+constexpr int LU_LDS_MAX = 128;
 constexpr int TRSM_MAX = 192;
 
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
@@ -89,7 +90,7 @@ int grouped_update_tile();
 // Diagonal factorisations and panel solves (panel.hip).
 template <typename S>
 hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, int* info, int col_base, hipStream_t st);
-hipError_t launch_getrf_diag(int w, double* a, int64_t ld, int* info, int col_base, hipStream_t st);
+hipError_t launch_getrf_lds(int w, double* a, int64_t ld, int* info, int col_base, hipStream_t st);
 template <typename T>
 hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, int64_t tk, int64_t tj,
                        int unit, const int* info, hipStream_t st, int max_wg = 0);

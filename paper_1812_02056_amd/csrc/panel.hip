@@ -6,18 +6,15 @@
 //     L[c,c] = sqrt(A[c,c] - sum_{k=z}^{c-1} L[c,k]^2)
 //     L[i,c] = (A[i,c] - sum_{k=z}^{c-1} L[i,k] L[c,k]) / L[c,c]      (i > c)
 // For the w pending columns of one block, the rows inside the block form the
-// w x w diagonal factorisation (potrf_diag_kernel) and the rows below it are a
-// triangular solve L21 = A21 L11^-T (trsm_kernel, rows independent).
-// Algorithm 2 (LU) splits the same way into getrf_diag_kernel and two
+// w x w diagonal factorisation (potrf_lds_kernel) and the rows below it are a
+// triangular solve L21 = A21 L11^-T (trsm_reg_kernel, rows independent).
+// Algorithm 2 (LU) splits the same way into getrf_lds_kernel and two
 // triangular solves L21 = A21 U11^-1 and U12 = L11^-1 A12.
 //
-// Both diagonal kernels run in ONE workgroup.  The LU kernel processes the block
-// in panels of 16 columns, each first brought up to date with the columns left
-// of it by MFMA products (left-looking); one wave factors the panel's 16 x 16
-// diagonal tile in registers, then every thread takes whole rows below it.  The
-// Cholesky kernel holds the block in LDS as 16 x 16 tiles (right-looking, see
-// potrf_block).  Diagonal blocks are always binary64; for binary32 storage they
-// are widened into a workspace, factored, and rounded back.
+// Both diagonal kernels run in ONE workgroup that holds the block in LDS as
+// 16 x 16 tiles and factors it right-looking over tile columns (potrf_block,
+// getrf_lds_kernel).  Diagonal blocks are always binary64; for binary32 storage
+// they are widened into a workspace, factored, and rounded back.
 #include <math.h>
 
 #include "common.hpp"
@@ -27,61 +24,7 @@ namespace ff {
 
 namespace {
 
-// threads of the LU diagonal kernel: 8 waves share the left-looking tile updates
-constexpr int PNT = 512;
-constexpr int PB = 16;       // panel width
-constexpr int MAXR = (GETRF_DIAG_MAX + PNT - 1) / PNT;   // rows per thread in getrf_diag_kernel
-
 __global__ void set_int_kernel(int* p, int v) { if (threadIdx.x == 0) *p = v; }
-
-// a[rows r0.., cols q0..] -= Lsrc[r0.., 0:c] * Usrc[0:c, q0..] for one 16 x 16
-// tile (one wave), with element accessors L(i, k) = a[i + k*ld] and
-// U(k, j) = ub[k*uk + j*uj].  Rows >= rmax, cols >= qmax, and (lower_only)
-// entries above the diagonal are not written.
-__device__ __forceinline__ void tile_update_f64(double* a, int64_t ld, const double* ub, int64_t uk, int64_t uj,
-                                                int r0, int q0, int c, int rmax, int qmax, bool lower_only,
-                                                int lane) {
-    d4_t acc0 = zero_vec<d4_t>(), acc1 = zero_vec<d4_t>();
-    const int ra = r0 + (lane & 15), qa = q0 + (lane & 15);
-    const bool rok = ra < rmax, qok = qa < qmax;
-    // K in blocks of 32, the next block's operands loaded while the current
-    // block's MFMAs run (the diagonal kernels have few waves to hide latency
-    // with).  acc0 takes the 4-deep K groups 0, 2, 4, ... of each 8 and acc1 the
-    // odd ones, in increasing K; positions past c contribute zeros.
-    double cur[4][4], nxt[4][4];
-    auto load32 = [&](int kb, double (&d)[4][4]) {
-#pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int k1 = kb + 8 * it + (lane >> 4), k2 = k1 + 4;
-            d[it][0] = (qok && k1 < c) ? ub[(int64_t)k1 * uk + (int64_t)qa * uj] : 0.0;
-            d[it][1] = (rok && k1 < c) ? a[(int64_t)ra + (int64_t)k1 * ld] : 0.0;
-            d[it][2] = (qok && k2 < c) ? ub[(int64_t)k2 * uk + (int64_t)qa * uj] : 0.0;
-            d[it][3] = (rok && k2 < c) ? a[(int64_t)ra + (int64_t)k2 * ld] : 0.0;
-        }
-    };
-    if (c > 0) load32(0, cur);
-    for (int kb = 0; kb < c; kb += 32) {
-        if (kb + 32 < c) load32(kb + 32, nxt);
-#pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            if (kb + 8 * it < c) {
-                acc0 = mfma_f64(cur[it][0], cur[it][1], acc0);
-                if (kb + 8 * it + 4 < c) acc1 = mfma_f64(cur[it][2], cur[it][3], acc1);
-            }
-        }
-#pragma unroll
-        for (int it = 0; it < 4; ++it)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) cur[it][e] = nxt[it][e];
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int gi = r0 + (lane & 15);
-        const int gj = q0 + acc_traits<double>::col(lane, r);
-        if (gi < rmax && gj < qmax && (!lower_only || gi >= gj))
-            a[(int64_t)gi + (int64_t)gj * ld] -= (acc0[r] + acc1[r]);
-    }
-}
 
 // value of v in lane l (l uniform across the wave)
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -90,129 +33,6 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-
-// Doolittle LU without pivoting of the w x w diagonal block, in place (binary64).
-__global__ __launch_bounds__(PNT)
-void getrf_diag_kernel(int w, double* a, int64_t ld, int* info, int col_base)
-{
-    if (*info != 0) return;
-    __shared__ double top[PB][PB + 1];
-    __shared__ int fail;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) fail = 0;
-    __syncthreads();
-
-    for (int c = 0; c < w; c += PB) {
-        const int nbc = min(PB, w - c);
-        const int pe = c + nbc;
-        if (c > 0) {
-            // column panel: rows c..w-1, cols c..pe-1; row panel: rows c..pe-1, cols pe..w-1
-            const int ncol_t = (w - c + 15) / 16;
-            const int nrow_t = (w - pe + 15) / 16;
-            for (int t = wave; t < ncol_t + nrow_t; t += PNT / 64) {
-                if (t < ncol_t)
-                    tile_update_f64(a, ld, a, 1, ld, c + 16 * t, c, c, w, pe, false, lane);
-                else
-                    tile_update_f64(a, ld, a, 1, ld, c, pe + 16 * (t - ncol_t), c, pe, w, false, lane);
-            }
-        }
-        __syncthreads();
-        // The panel's 16 x 16 diagonal tile, on wave 0 in row layout (lane b holds
-        // row c + b): column j's pivot and U row come from lane j, and every row
-        // below j takes l = x_j / u, x_k -= l U(j, k) (k > j), with no barrier
-        // between columns.  Columns and rows past nbc are zero and stay zero.
-        if (wave == 0) {
-            const int b = lane & 15;
-            // lane masks are formed here, not kept across the panel loop
-            int bi = b;
-            asm volatile("" : "+v"(bi));
-            double x[PB];
-#pragma unroll
-            for (int k = 0; k < PB; ++k) x[k] = (b < nbc && k < nbc) ? a[(c + b) + (int64_t)(c + k) * ld] : 0.0;
-            int bad = -1;
-#pragma unroll
-            for (int j = 0; j < PB; ++j) {
-                if (j < nbc && bad < 0) {
-                    const double u = readlane_f64(x[j], j);
-                    if (u == 0.0 || !isfinite(u)) {
-                        bad = j;
-                    } else {
-                        double ur[PB];
-#pragma unroll
-                        for (int k = j + 1; k < PB; ++k) ur[k] = readlane_f64(x[k], j);
-                        if (bi > j) {
-                            const double l = x[j] / u;
-                            x[j] = l;
-#pragma unroll
-                            for (int k = j + 1; k < PB; ++k) x[k] -= l * ur[k];
-                        }
-                    }
-                }
-            }
-            if (bad >= 0) {
-                if (lane == 0) {
-                    fail = 1;
-                    *info = col_base + c + bad + 1;
-                }
-            } else if (lane < PB) {
-#pragma unroll
-                for (int k = 0; k < PB; ++k) {
-                    top[b][k] = x[k];
-                    if (b < nbc && k < nbc) a[(c + b) + (int64_t)(c + k) * ld] = x[k];
-                }
-            }
-        }
-        __syncthreads();
-        if (fail) return;
-        // rows below the tile: the same operations, row by row, with the tile's U
-#pragma unroll
-        for (int q = 0; q < MAXR; ++q) {
-            const int i = pe + tid + q * PNT;
-            if (i < w) {
-                double p[PB];
-#pragma unroll
-                for (int j = 0; j < PB; ++j) p[j] = j < nbc ? a[i + (int64_t)(c + j) * ld] : 0.0;
-#pragma unroll
-                for (int j = 0; j < PB; ++j) {
-                    if (j < nbc) {
-                        const double l = p[j] / top[j][j];
-                        p[j] = l;
-#pragma unroll
-                        for (int k = j + 1; k < PB; ++k) p[k] -= l * top[j][k];
-                    }
-                    // one row of the tile's U at a time (hoisted, they spill)
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-#pragma unroll
-                for (int j = 0; j < PB; ++j)
-                    if (j < nbc) a[i + (int64_t)(c + j) * ld] = p[j];
-            }
-        }
-        __syncthreads();
-        // U row panel: U[c+j, q] = A[c+j, q] - sum_{k<j} L[c+j, c+k] U[c+k, q], q >= pe.
-        // The column's loads are all issued first and its stores come last, so
-        // the 16 rows cost one memory latency, not 16.
-        for (int q = pe + tid; q < w; q += PNT) {
-            double u[PB];
-#pragma unroll
-            for (int j = 0; j < PB; ++j) u[j] = j < nbc ? a[(int64_t)(c + j) + (int64_t)q * ld] : 0.0;
-#pragma unroll
-            for (int j = 0; j < PB; ++j) {
-                double x = u[j];
-#pragma unroll
-                for (int k = 0; k < PB; ++k)
-                    if (k < j) x -= top[j][k] * u[k];
-                u[j] = x;
-                __builtin_amdgcn_sched_barrier(0);
-            }
-#pragma unroll
-            for (int j = 0; j < PB; ++j)
-                if (j < nbc) a[(int64_t)(c + j) + (int64_t)q * ld] = u[j];
-        }
-        __syncthreads();
-    }
-}
-
 
 // ---------------------------------------------------------------------------
 // MFMA output layout of a 16 x 16 tile: for the transposed tile D'[a][b] = M(b, a),
@@ -445,6 +265,196 @@ __device__ __forceinline__ void potrf_block(int w, S* __restrict__ blk, int64_t 
     }
 }
 
+// ---------------------------------------------------------------------------
+// LU (Doolittle, no pivoting) of the w x w diagonal block, w <= LU_LDS_MAX, in
+// ONE workgroup, the block held in LDS as 16 x 16 tiles (tile (i, j) at index
+// i * LU_TMAX + j, element (r, c) at r + 16 c) padded with the identity beyond w.
+// Right-looking over tile columns: one wave factors the diagonal tile, forming
+// U_kk^-1 and L_kk^-1 alongside; the waves solve the tiles below (A U_kk^-1) and
+// to the right (L_kk^-1 A) with one MFMA product each, then update the trailing
+// tiles; wave 0 updates the next diagonal tile first and factors it while the
+// other waves finish the update.
+constexpr int LU_TMAX = LU_LDS_MAX / DT;
+constexpr int LU_PT = 512;
+constexpr int LU_PW = LU_PT / 64;
+constexpr int LSTG = LU_TMAX * LU_TMAX / (LU_PT / 256);
+
+__device__ __forceinline__ int utile(int i, int j) { return (i * LU_TMAX + j) * 256; }
+
+// In-register LU of a 16 x 16 tile in row layout (lane l holds row i = l % 16 in
+// x; bi is i), with the rows of U^-1 (in z) and of L^-T (in y) formed alongside.
+// Column j: the pivot u = U(j, j) and U's row j are read from lane j, and rows
+// i > j take l = x_j / u, x_k -= l U(j, k) for k > j.  z enters as row i of the
+// identity and takes column j's step of z U = e_i (z_j /= u, z_k -= z_j U(j, k));
+// y enters as row i of the identity and takes column j's step of y L^T = e_i
+// (y_c -= y_j L(c, j) for c > j, L(c, j) read from lane c).  Returns the first
+// column whose pivot was zero or not finite, or -1 (uniform across the wave).
+__device__ __forceinline__ int row_getrf(double (&x)[16], double (&z)[16], double (&y)[16], int bi) {
+    int bad = -1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (bad < 0) {
+            const double u = readlane_f64(x[j], j);
+            if (u == 0.0 || !isfinite(u)) {
+                bad = j;
+            } else {
+                double ur[16];
+#pragma unroll
+                for (int k = j + 1; k < 16; ++k) ur[k] = readlane_f64(x[k], j);
+                z[j] = z[j] / u;
+#pragma unroll
+                for (int k = j + 1; k < 16; ++k) {
+                    z[k] -= z[j] * ur[k];
+                    // kept next to its broadcast (sunk to the end, the
+                    // broadcasts it needs exhaust the scalar registers)
+                    asm volatile("" : "+v"(z[k]));
+                }
+                if (bi > j) {
+                    const double l = x[j] / u;
+                    x[j] = l;
+#pragma unroll
+                    for (int k = j + 1; k < 16; ++k) x[k] -= l * ur[k];
+                }
+#pragma unroll
+                for (int c = j + 1; c < 16; ++c) {
+                    y[c] -= y[j] * readlane_f64(x[j], c);
+                    asm volatile("" : "+v"(y[c]));
+                }
+            }
+        }
+    }
+    return bad;
+}
+
+// Factors diagonal tile kt in place (one wave) and leaves Z = U_kk^-1 in zt
+// (Z(r, c) at c + 16 r) and W = L_kk^-1 in wt (W(r, c) at r + 16 c).  A pivot
+// that is zero or not finite sets fail and, inside the block, the info word.
+__device__ __forceinline__ void lu_diag_tile(double* tl, int kt, double* zt, double* wt, int* fail, int lane, int w,
+                                             int* info, int col_base) {
+    double* dtile = tl + utile(kt, kt);
+    const int b = lane & 15;
+    // lane masks are formed here, not kept across the caller's loop
+    int bi = b;
+    asm volatile("" : "+v"(bi));
+    double x[16], z[16], y[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        x[c] = dtile[b + 16 * c];
+        z[c] = bi == c ? 1.0 : 0.0;
+        y[c] = z[c];
+    }
+    const int bad = row_getrf(x, z, y, bi);
+    if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            dtile[b + 16 * c] = x[c];
+            zt[c + 16 * b] = z[c];
+            wt[c + 16 * b] = y[c];
+        }
+    }
+    if (lane == 0 && bad >= 0) {
+        *fail = bad;
+        if (DT * kt + bad < w) *info = col_base + DT * kt + bad + 1;
+    }
+}
+
+// t <- W t for a 16 x 16 tile t in LDS (one wave, MFMA layout); wt as above
+__device__ __forceinline__ void tile_lmul_wt(double* t, const double* wt, int lane) {
+    const int b = lane & 15;
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = tcol<double>(lane, s);
+        acc = mfma_f64(t[k + 16 * b], wt[b + 16 * k], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t[b + 16 * tcol<double>(lane, r)] = acc[r];
+}
+
+// c -= l u for 16 x 16 tiles in LDS (one wave, MFMA layout)
+__device__ __forceinline__ void tile_gemm_sub(double* c, const double* l, const double* u, int lane) {
+    const int b = lane & 15;
+    d4_t acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = c[b + 16 * tcol<double>(lane, r)];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = tcol<double>(lane, s);
+        acc = mfma_f64(-u[k + 16 * b], l[b + 16 * k], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c[b + 16 * tcol<double>(lane, r)] = acc[r];
+}
+
+__global__ __launch_bounds__(LU_PT)
+void getrf_lds_kernel(int w, double* __restrict__ blk, int64_t ldb, int* info, int col_base)
+{
+    if (*info != 0) return;
+    __shared__ double tl[LU_TMAX * LU_TMAX * 256];
+    __shared__ double zt[256], wt[256];
+    __shared__ int fail;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int T = (w + DT - 1) / DT;
+    // thread's entry rc of tile slots q0 + 2u (slot q is tile (q / LU_TMAX, q % LU_TMAX))
+    const int rc = tid & 255, q0 = wave >> 2;
+    if (tid == 0) fail = -1;
+    {
+        double v[LSTG];
+#pragma unroll
+        for (int u = 0; u < LSTG; ++u) {
+            const int q = q0 + 2 * u, i = q / LU_TMAX, j = q % LU_TMAX;
+            if (i < T && j < T) {
+                const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
+                const bool in = gr < w && gc < w;
+                const double x = blk[in ? gr + (int64_t)gc * ldb : 0];
+                v[u] = in ? x : (gr == gc ? 1.0 : 0.0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < LSTG; ++u) {
+            const int q = q0 + 2 * u;
+            if (q / LU_TMAX < T && q % LU_TMAX < T) tl[q * 256 + rc] = v[u];
+        }
+    }
+    __syncthreads();
+    if (wave == 0) lu_diag_tile(tl, 0, zt, wt, &fail, lane, w, info, col_base);
+    __syncthreads();
+    for (int kt = 0; kt + 1 < T; ++kt) {
+        if (fail >= 0) return;
+        const int nr = T - kt - 1;
+        // the tiles below (A U_kk^-1) and to the right (L_kk^-1 A), one wave each
+        for (int t = wave; t < 2 * nr; t += LU_PW) {
+            if (t < nr) tile_mul_yt(tl + utile(kt + 1 + t, kt), zt, lane);
+            else tile_lmul_wt(tl + utile(kt, kt + 1 + (t - nr)), wt, lane);
+        }
+        __syncthreads();
+        // trailing tiles (it, jt), it, jt > kt: A -= L_it,kt U_kt,jt.  Pair p = 0
+        // is the next diagonal tile: wave 0 updates and factors it, the other
+        // waves take the remaining pairs.
+        if (wave == 0) {
+            tile_gemm_sub(tl + utile(kt + 1, kt + 1), tl + utile(kt + 1, kt), tl + utile(kt, kt + 1), lane);
+            wave_lds_sync();
+            lu_diag_tile(tl, kt + 1, zt, wt, &fail, lane, w, info, col_base);
+        } else {
+            for (int p = wave; p < nr * nr; p += LU_PW - 1) {
+                const int it = kt + 1 + p / nr, jt = kt + 1 + p % nr;
+                tile_gemm_sub(tl + utile(it, jt), tl + utile(it, kt), tl + utile(kt, jt), lane);
+            }
+        }
+        __syncthreads();
+    }
+    if (fail >= 0) return;
+#pragma unroll
+    for (int u = 0; u < LSTG; ++u) {
+        const int q = q0 + 2 * u, i = q / LU_TMAX, j = q % LU_TMAX;
+        if (i < T && j < T) {
+            const int gr = DT * i + (rc & 15), gc = DT * j + (rc >> 4);
+            if (gr < w && gc < w) blk[gr + (int64_t)gc * ldb] = tl[q * 256 + rc];
+        }
+    }
+}
+
 template <typename S>
 __global__ __launch_bounds__(PT)
 void potrf_lds_kernel(int w, S* __restrict__ blk, int64_t ldb, int* info, int col_base)
@@ -649,10 +659,10 @@ hipError_t launch_potrf_diag(int w, S* blk, int64_t ldb, int* info, int col_base
     return hipGetLastError();
 }
 
-hipError_t launch_getrf_diag(int w, double* a, int64_t ld, int* info, int col_base, hipStream_t st) {
+hipError_t launch_getrf_lds(int w, double* a, int64_t ld, int* info, int col_base, hipStream_t st) {
     if (w <= 0) return hipSuccess;
-    if (w > GETRF_DIAG_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(getrf_diag_kernel, dim3(1), dim3(PNT), 0, st, w, a, ld, info, col_base);
+    if (w > LU_LDS_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(getrf_lds_kernel, dim3(1), dim3(LU_PT), 0, st, w, a, ld, info, col_base);
     return hipGetLastError();
 }
 
