@@ -257,27 +257,50 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
 // CUs to keep free for the next block's diagonal factorisation and panel solve
 // while the rest of the update runs: 32 if the panel estimate fits under the
 // update's estimate there, else the one of 32/64 that minimises the longer of
-// the two.  Model: the diagonal block costs about diag_us; the panel solve
-// takes 128 rows per free CU per round, a round being two 16-row blocks per
-// SIMD of 4 T(T+1)/2 MFMAs of 64 cycles each (T = 16-column tiles), at the
-// measured fraction of the peak issue rate.
+// the two.  Model: the diagonal block costs diag_us, the panel solve trsm_us.
 // *tail: the fraction of the update's tiles (its last ones) that the reserved
 // CUs can take after the panel work and still finish with the rest, which runs
 // on the other CUs: (U - P) / (U (1 + (C - R) / R)) for update and panel
 // estimates U and P, less a margin (0 when the panel is the longer).
 // upd_factor: update flops per mr^2 w (1 for the lower-triangle product, 2 for
 // LU's full product); n_solves: panel solves per step (1 Cholesky, 2 LU);
-// diag_extra_us: added to the diagonal-block estimate.
-int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail, double upd_factor = 1.0, int n_solves = 1,
-                      double diag_extra_us = 0.0) {
+// diag_us: the next block's diagonal factorisation (chol_diag_us, lu_diag_us).
+//
+// The estimates are fitted to kernel traces on MI355X (binary64):
+//  - a panel-solve round: one workgroup of four waves solves 64 rows of a chunk
+//    of up to TRSM_MAX columns, ~7 us of staging and tile inverses plus ~16 us of
+//    MFMA solve at 12 tiles, growing with the tile pairs;
+//  - chunks after the first subtract the solved columns first (an update on the
+//    same CUs) and launch a second solve.
+double trsm_us(int mr, int wn, int r, int cus, size_t sz, double rate) {
+    double t = 0.0;
+    for (int c0 = 0; c0 < wn; c0 += TRSM_MAX) {
+        const int tiles = (std::min(TRSM_MAX, wn - c0) + 15) / 16;
+        const double round = 7.0 + 16.0 * tiles * (tiles + 1) / 156.0 * (sz == sizeof(double) ? 1.0 : 0.5);
+        t += std::ceil((double)mr / (64.0 * r)) * round;
+        if (c0 > 0) t += 2.0 * mr * (double)(wn - c0) * c0 / (rate * r / cus) * 1e6 + 5.0;
+    }
+    return t;
+}
+// Cholesky diagonal block: one LDS kernel up to LDS_DIAG_MAX (68 us at 192
+// columns), else LDS_DIAG_MAX-wide blocks with a solve and an update between.
+double chol_diag_us(int wn) {
+    auto one = [](int w) { return 10.0 + 0.3 * w; };
+    if (wn <= LDS_DIAG_MAX) return one(wn);
+    double t = 0.0;
+    for (int c0 = 0; c0 < wn; c0 += LDS_DIAG_MAX) t += one(std::min(LDS_DIAG_MAX, wn - c0)) + (c0 > 0 ? 45.0 : 0.0);
+    return t;
+}
+// LU diagonal block: one LDS kernel up to LU_LDS_MAX (62 us at 128 columns), else
+// LU_LDS_MAX-wide blocks with two solves and an update between.
+double lu_diag_us(int wn) {
+    double t = 0.0;
+    for (int c0 = 0; c0 < wn; c0 += LU_LDS_MAX) t += 6.0 + 0.44 * std::min(LU_LDS_MAX, wn - c0) + (c0 > 0 ? 60.0 : 0.0);
+    return t;
+}
+int lookahead_reserve(int mr, int w, int wn, size_t sz, double diag_us, double* tail, double upd_factor = 1.0,
+                      int n_solves = 1) {
     const double rate = (sz == sizeof(double) ? 50e12 : 90e12);
-    const int tiles = (std::min(wn, TRSM_MAX) + 15) / 16;
-    // measured rounds take about twice their MFMA issue time (dependent MFMA
-    // chains, operand loads): ~33 us for 192 columns
-    const double round_us = 2.0 * (double)tiles * (tiles + 1) * 4.0 * 64.0 / 2400.0 * (sz == sizeof(double) ? 1.0 : 0.5);
-    // diagonal block, plus for wn > 192 the second panel-solve chunk and the
-    // update between the chunks (fitted to traces at wn = 256)
-    const double diag_us = (wn <= 64 ? 30.0 : wn <= 128 ? 60.0 : wn <= 192 ? 110.0 : 290.0 + (wn - 256)) + diag_extra_us;
     const int cus = update_workers(0);
     // At least 4 free CUs per XCD: with fewer, the side stream's workgroups are
     // often placed behind the update's (the free CUs of an XCD are not all
@@ -286,8 +309,7 @@ int lookahead_reserve(int mr, int w, int wn, size_t sz, double* tail, double upd
     double best_t = 1e30, best_u = 0, best_p = 0;
     for (int r : {32, 64}) {
         const double upd_us = upd_factor * (double)mr * (double)mr * (double)w / (rate * (double)(cus - r) / cus) * 1e6;
-        const double pan_us = diag_us + n_solves * std::ceil((double)mr / (128.0 * r)) * round_us *
-                                            (wn > TRSM_MAX ? 1.1 : 1.0);
+        const double pan_us = diag_us + n_solves * trsm_us(mr, wn, r, cus, sz, rate);
         const double t = std::max(upd_us, pan_us);
         if (t < best_t) { best_t = t; best = r; best_u = upd_us; best_p = pan_us; }
         if (pan_us <= upd_us) break;
@@ -365,7 +387,7 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         //    `reserve` CUs; the panel solve's grid is sized to those free CUs,
         //    which then take the last `tail` of the update's tile order
         double tail = 0.0;
-        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S), &tail);
+        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S), chol_diag_us(wn), &tail);
         if ((flags & FF_FLAG_STRASSEN1) || dtype == FF_BF16 || tail < 0.01 ||
             !update_splittable(m - wn, m - wn, true, 0, reserve))
             tail = 0.0;
@@ -479,7 +501,7 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
         //    rest of the update on the others, its tail on the reserved CUs after
         //    the panel
         double tail = 0.0;
-        const int reserve = lookahead_reserve(mr, w, wn, sizeof(double), &tail, 2.0, 2, 60.0);
+        const int reserve = lookahead_reserve(mr, w, wn, sizeof(double), lu_diag_us(wn), &tail, 2.0, 2);
         const bool strassen = (flags & FF_FLAG_STRASSEN1) != 0;
         if (strassen || tail < 0.01 || mr <= 0 || !update_splittable(mr, mr, false, 0, reserve)) tail = 0.0;
         rc = lu_panel(n, c0 + w, wn, A, lda, info, col_base, side, reserve);
