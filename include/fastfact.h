@@ -75,13 +75,15 @@ enum {
                                       `stream`) while the rest of the update
                                       runs on all but a few CUs.  Both
                                       schedules give bitwise identical factors. */
-    FF_FLAG_FIXED_STEP = 1u << 2    /* Cholesky: every block exactly s columns
-                                      wide (the step of Sec. 2 Algorithm 1
-                                      verbatim).  Without it, when s > 192 the
-                                      first block and the blocks of the last
-                                      6144 columns are 192 wide (see
-                                      chol_factor).  Factors differ by rounding
-                                      only.  LU blocks are always s wide. */
+    FF_FLAG_FIXED_STEP = 1u << 2    /* every block exactly s columns wide (the
+                                      step of Sec. 2 Algorithms 1 and 2
+                                      verbatim).  Without it, the first block
+                                      and the blocks near the end are narrower
+                                      when s is wide: Cholesky 192 columns over
+                                      the last 6144 when s > 192, LU 128 over
+                                      the last 4096 when s > 128 (see
+                                      chol_factor, lu_nopiv_factor).  Factors
+                                      differ by rounding only. */
 };
 
 enum {
@@ -124,7 +126,9 @@ int chol_factor(int64_t n, int64_t s, void *A, int64_t lda, int dtype, unsigned 
  * Doolittle-packed: the strict lower triangle holds the unit-lower L, the upper
  * triangle including the diagonal holds U.  (Algorithm 2 returns the Crout form
  * L_c = L D, U_c = D^-1 U with D = diag(U); the deferred products are equal in
- * both forms.)  Only FF_F64 is implemented.
+ * both forms.)  Only FF_F64 is implemented.  For the first block and over the
+ * last 4096 columns a step above 128 is cut to 128, the widest diagonal block
+ * one workgroup factors in LDS; FF_FLAG_FIXED_STEP keeps every block s wide.
  */
 size_t ff_lu_workspace_size(int64_t n, int64_t s, int dtype, unsigned flags);
 int lu_nopiv_factor(int64_t n, int64_t s, void *A, int64_t lda, int dtype, unsigned flags,

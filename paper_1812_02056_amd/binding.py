@@ -224,14 +224,16 @@ def chol_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_lookahe
 
 
 def lu_nopiv_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_lookahead=False, stream=None,
-                    info: torch.Tensor | None = None, sync=False):
-    """In-place LU without pivoting, Doolittle packed (unit-lower L below the diagonal, U on and above)."""
+                    info: torch.Tensor | None = None, sync=False, fixed_step=False):
+    """In-place LU without pivoting, Doolittle packed (unit-lower L below the diagonal, U on and above).
+    fixed_step: every block exactly s wide (FF_FLAG_FIXED_STEP)."""
     lib = load()
     dt = _dt(dtype)
     n = int(A.shape[0])
     if A.shape[1] != n:
         raise ValueError("A must be square")
-    flags = (FLAG_STRASSEN1 if strassen else 0) | (FLAG_NO_LOOKAHEAD if no_lookahead else 0)
+    flags = ((FLAG_STRASSEN1 if strassen else 0) | (FLAG_NO_LOOKAHEAD if no_lookahead else 0)
+             | (FLAG_FIXED_STEP if fixed_step else 0))
     need = int(lib.ff_lu_workspace_size(n, s, dt, flags))
     ws = _workspace(need, A.device)
     if info is None:

@@ -45,13 +45,14 @@ def test_fullsize_chol_integer_family_bitwise(s):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("s", [384, 640])
 @pytest.mark.parametrize("fixed_step", [False, True])
-def test_fullsize_chol_integer_family_bitwise_s384(fixed_step):
-    # the benchmark's best step; by default its first block and last 6144 columns
-    # are 192-wide blocks, with fixed_step every block is 384 wide
+def test_fullsize_chol_integer_family_bitwise_wide_steps(s, fixed_step):
+    # the benchmark's steps; by default the first block and the last 6144 columns
+    # are 192-wide blocks, with fixed_step every block is s wide
     L0, A = wl.chol_int_family_device(N, seed=9, device=DEV)
     Acm = A.t()
-    assert ff.chol_factor(Acm, 384, dtype="f64", fixed_step=fixed_step, sync=True) == 0
+    assert ff.chol_factor(Acm, s, dtype="f64", fixed_step=fixed_step, sync=True) == 0
     assert torch.equal(torch.tril(Acm), L0)
     del L0, A, Acm
     torch.cuda.empty_cache()
@@ -81,11 +82,12 @@ def test_fullsize_chol_benchmark_matrix():
     torch.cuda.empty_cache()
 
 
-def test_fullsize_lu_integer_family_bitwise():
+@pytest.mark.parametrize("s", [168, 768])
+def test_fullsize_lu_integer_family_bitwise(s):
     L0, U0, A = wl.lu_int_family_device(N, seed=6, device=DEV)
     Acm = colmajor(A)
     del A
-    assert ff.lu_nopiv_factor(Acm, 168, sync=True) == 0
+    assert ff.lu_nopiv_factor(Acm, s, sync=True) == 0
     assert torch.equal(torch.tril(Acm, -1), torch.tril(L0, -1))
     assert torch.equal(torch.triu(Acm), U0)
     del L0, U0, Acm

@@ -276,7 +276,37 @@ def test_chol_fixed_step_lookahead_matches_in_order_bitwise(n, s):
     assert np.array_equal(host(A1), host(A2))
 
 
-@pytest.mark.parametrize("n,s", [(1000, 64), (1300, 168), (2000, 256)])
+# LU block widths: with s > 128 the first block and the blocks of the last 4096
+# columns are 128 wide unless FF_FLAG_FIXED_STEP keeps every block s wide.
+
+@pytest.mark.parametrize("n,s", [(700, 256), (1300, 384), (2100, 768)])
+@pytest.mark.parametrize("fixed_step", [False, True])
+@pytest.mark.parametrize("no_lookahead", [False, True])
+def test_lu_block_widths_integer_family_bitwise(n, s, fixed_step, no_lookahead):
+    L0, U0, A = wl.lu_int_family(n, seed=7 * n + s)
+    Ad = dev(A, ld=n + 1)
+    assert ff.lu_nopiv_factor(Ad, s, fixed_step=fixed_step, no_lookahead=no_lookahead, sync=True) == 0
+    LU = host(Ad)
+    assert np.array_equal(np.tril(LU, -1) + np.eye(n), L0)
+    assert np.array_equal(np.triu(LU), U0)
+
+
+@pytest.mark.parametrize("fixed_step", [False, True])
+def test_lu_block_widths_diag_dominant(fixed_step):
+    n, s = 1536, 384
+    A = wl.diag_dominant(n, seed=13)
+    Ad = dev(A)
+    assert ff.lu_nopiv_factor(Ad, s, fixed_step=fixed_step, sync=True) == 0
+    LU = host(Ad)
+    LUo, _ = oracle.lu(A)
+    Lg, Lo = np.tril(LU, -1), np.tril(LUo, -1)
+    Ug, Uo = np.triu(LU), np.triu(LUo)
+    assert np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo + np.eye(n)) <= 1e-11
+    assert np.linalg.norm(Ug - Uo) / np.linalg.norm(Uo) <= 1e-11
+    assert oracle.bwd_lu(A, LU) <= 1e-13
+
+
+@pytest.mark.parametrize("n,s", [(1000, 64), (1300, 168), (2000, 256), (2100, 768)])
 def test_lu_lookahead_matches_in_order_bitwise(n, s):
     # the lookahead schedule splits each update into strips and a remainder (and a
     # tail on the other stream); every entry sees the same products in the same order
