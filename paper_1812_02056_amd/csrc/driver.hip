@@ -321,7 +321,8 @@ int lookahead_reserve(int mr, int w, int wn, size_t sz, double diag_us, double* 
     return best;
 }
 
-// Width of the Cholesky block starting at column c0 for step size s.  The first
+// Width of the Cholesky block starting at column c0 for step size s (the closing
+// remarks of Sec. 2 allow s to change during the run).  The first
 // block, and every block over the last CHOL_TAIL_COLS columns, is cut to
 // LDS_DIAG_MAX when s is wider: nothing overlaps the first block's factorisation,
 // and near the end the trailing update is small and the next block's
