@@ -230,8 +230,8 @@ int ff_update_profile_read(ff_kernel_profile out[FF_UPD_NSHAPES]);
 
 /*
  * Serving: many independent SPD systems A_i X_i = B_i (binary64), each factored
- * by Algorithm 1 (Sec. 2) with its own step s = round(n^0.5286) (at most 192)
- * and solved with the factor.  A server keeps every admitted factorisation in
+ * by Algorithm 1 (Sec. 2) with step s = min(n, 192) (the widest diagonal block
+ * one workgroup factors) and solved with the factor.  A server keeps every admitted factorisation in
  * flight: each ff_server_step advances all of them by one block of s columns
  * with three grouped launches (the diagonal blocks of every matrix, then their
  * panel solves, then their trailing updates), and starts the solves of those
