@@ -275,10 +275,12 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
 double trsm_us(int mr, int wn, int r, int cus, size_t sz, double rate) {
     double t = 0.0;
     for (int c0 = 0; c0 < wn; c0 += TRSM_MAX) {
-        const int tiles = (std::min(TRSM_MAX, wn - c0) + 15) / 16;
+        const int wc = std::min(TRSM_MAX, wn - c0);
+        const int tiles = (wc + 15) / 16;
         const double round = 7.0 + 16.0 * tiles * (tiles + 1) / 156.0 * (sz == sizeof(double) ? 1.0 : 0.5);
         t += std::ceil((double)mr / (64.0 * r)) * round;
-        if (c0 > 0) t += 2.0 * mr * (double)(wn - c0) * c0 / (rate * r / cus) * 1e6 + 5.0;
+        // the chunk's columns less the solved ones: mr x wc x c0
+        if (c0 > 0) t += 2.0 * mr * (double)wc * c0 / (rate * r / cus) * 1e6 + 5.0;
     }
     return t;
 }
