@@ -301,7 +301,7 @@ double lu_diag_us(int wn) {
     return t;
 }
 int lookahead_reserve(int mr, int w, int wn, size_t sz, double diag_us, double* tail, double upd_factor = 1.0,
-                      int n_solves = 1) {
+                      int n_solves = 1, double* upd_est = nullptr, double* pan_est = nullptr) {
     const double rate = (sz == sizeof(double) ? 50e12 : 90e12);
     const int cus = update_workers(0);
     // At least 4 free CUs per XCD: with fewer, the side stream's workgroups are
@@ -320,7 +320,35 @@ int lookahead_reserve(int mr, int w, int wn, size_t sz, double diag_us, double* 
         const double f = best_u > best_p ? (best_u - best_p) / (best_u * (1.0 + (double)(cus - best) / best)) : 0.0;
         *tail = 0.9 * f;
     }
+    if (upd_est) *upd_est = best_u;
+    if (pan_est) *pan_est = best_p;
     return best;
+}
+
+// The update's main part runs in rounds of one tile per workgroup, so a part
+// that ends a few tiles into a round leaves most of the workgroups idle for that
+// round.  Given the tile order's T tiles, the main part's nwg workgroups, the r
+// reserved CUs and the model's update (u, all T tiles on the main CUs) and panel
+// (p) estimates, moves the split to the whole round nearest it when that shortens
+// the longer of the main part and the panel plus the tail.
+double round_aligned_tail(int T, int nwg, int r, double f, double u, double p) {
+    if (T <= 0 || nwg <= 0 || r <= 0 || f <= 0.0) return f;
+    const double tau = u * nwg / T;      // one round of the main part
+    auto cost = [&](int nmain) {
+        const double main = std::ceil((double)nmain / nwg) * tau;
+        const double rest = T > nmain ? p + std::ceil((double)(T - nmain) / r) * tau : 0.0;
+        return std::max(main, rest);
+    };
+    const int n0 = std::min(T, std::max(0, (int)((1.0 - f) * T + 0.5)));
+    int best = n0;
+    double bc = cost(n0);
+    for (int k = n0 / nwg - 1; k <= n0 / nwg + 1; ++k) {
+        const int nm = std::min(T, k * nwg);
+        if (nm <= 0) continue;
+        const double c = cost(nm);
+        if (c < bc) { bc = c; best = nm; }
+    }
+    return 1.0 - (double)best / T;
 }
 
 // Width of the Cholesky block starting at column c0 for step size s (the closing
@@ -389,11 +417,14 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         // 2) the rest of the update, concurrently with the next panel, on all but
         //    `reserve` CUs; the panel solve's grid is sized to those free CUs,
         //    which then take the last `tail` of the update's tile order
-        double tail = 0.0;
-        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S), chol_diag_us(wn), &tail);
+        double tail = 0.0, u_est = 0.0, p_est = 0.0;
+        const int reserve = lookahead_reserve(m - wn, w, wn, sizeof(S), chol_diag_us(wn), &tail, 1.0, 1, &u_est, &p_est);
         if ((flags & FF_FLAG_STRASSEN1) || dtype == FF_BF16 || tail < 0.01 ||
             !update_splittable(m - wn, m - wn, true, 0, reserve))
             tail = 0.0;
+        else
+            tail = round_aligned_tail(update_order_tiles(m - wn, m - wn, true, 0, reserve), update_workers(reserve),
+                                      reserve, tail, u_est, p_est);
         rc = chol_panel<S>(n, c0 + w, wn, A, lda, dtype, ws64, info, col_base, side, reserve);
         if (rc) return fail(rc);
         if (tail > 0.0) {
@@ -513,10 +544,14 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
         // 2) the next panel on the side stream, sized to the reserved CUs; the
         //    rest of the update on the others, its tail on the reserved CUs after
         //    the panel
-        double tail = 0.0;
-        const int reserve = lookahead_reserve(mr, w, wn, sizeof(double), lu_diag_us(wn), &tail, 2.0, 2);
+        double tail = 0.0, u_est = 0.0, p_est = 0.0;
+        const int reserve = lookahead_reserve(mr, w, wn, sizeof(double), lu_diag_us(wn), &tail, 2.0, 2, &u_est, &p_est);
         const bool strassen = (flags & FF_FLAG_STRASSEN1) != 0;
-        if (strassen || tail < 0.01 || mr <= 0 || !update_splittable(mr, mr, false, 0, reserve)) tail = 0.0;
+        if (strassen || tail < 0.01 || mr <= 0 || !update_splittable(mr, mr, false, 0, reserve))
+            tail = 0.0;
+        else
+            tail = round_aligned_tail(update_order_tiles(mr, mr, false, 0, reserve), update_workers(reserve), reserve,
+                                      tail, u_est, p_est);
         rc = lu_panel(n, c0 + w, wn, A, lda, info, col_base, side, reserve);
         if (rc) return fail(rc);
         double* C2 = A22 + wn + (int64_t)wn * lda;

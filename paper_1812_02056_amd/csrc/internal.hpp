@@ -42,6 +42,8 @@ int update_shape(int M, int N, int reserve_cus);
 bool update_splittable(int M, int N, bool lower, int shift, int reserve_cus);
 // Entries of C that the [f0, f1) part of that split order writes (-1: no split order).
 double update_range_entries(int M, int N, bool lower, int shift, int reserve_cus, double f0, double f1);
+// Tiles in that split order (0: no split order).
+int update_order_tiles(int M, int N, bool lower, int shift, int reserve_cus);
 // One Strassen level over 128 x 128 super-tiles of 64 x 64 quadrants
 // (strassen.hip): C -= P P^T on the lower triangle of the m x m C (P m x w), or
 // C -= X Y on all of it (X m x w, Y w x m column-major).  One workgroup per CU on

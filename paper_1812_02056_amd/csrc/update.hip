@@ -508,6 +508,14 @@ double update_range_entries(int M, int N, bool lower, int shift, int reserve_cus
     return n;
 }
 
+int update_order_tiles(int M, int N, bool lower, int shift, int reserve_cus) {
+    const int shape = update_shape(M, N, reserve_cus);
+    if (shape == FF_UPD_SHAPE_64) return 0;
+    Grid g = shape == FF_UPD_SHAPE_256x128 ? make_grid(256, 128, 4, 8, M, N, lower, shift)
+                                           : make_grid(128, M, N, lower, shift);
+    return g.balanced ? g.ntiles : 0;
+}
+
 bool update_splittable(int M, int N, bool lower, int shift, int reserve_cus) {
     const int shape = update_shape(M, N, reserve_cus);
     if (shape == FF_UPD_SHAPE_64) return false;
