@@ -74,3 +74,27 @@ def test_workspace_sizes(lib):
     assert lib.ff_trisolve_workspace_size(130, 0) >= 3 * 64 * 64 * 8
     assert lib.ff_solve_workspace_size(1000, 64, 4, 1) > lib.ff_solve_workspace_size(1000, 64, 1, 1)
     assert lib.ff_solve_workspace_size(0, 64, 4, 1) == 0
+
+
+def _header_without_comments():
+    return re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+
+
+def test_flag_constants_match_the_header():
+    # the binding's flag values are the header's FF_FLAG_* enumerators
+    from paper_1812_02056_amd import binding
+    text = _header_without_comments()
+    flags = dict(re.findall(r"\b(FF_FLAG_[A-Z0-9_]+)\s*=\s*1u\s*<<\s*(\d+)", text))
+    assert set(flags) == {"FF_FLAG_STRASSEN1", "FF_FLAG_NO_LOOKAHEAD", "FF_FLAG_FIXED_STEP"}
+    for name, shift in flags.items():
+        assert getattr(binding, name[3:]) == 1 << int(shift), name
+
+
+def test_kernel_profile_layout_matches_the_header():
+    # ff_kernel_profile: the ctypes mirror has the header's fields, in order
+    from paper_1812_02056_amd import binding
+    text = _header_without_comments()
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*ff_kernel_profile;", text).group(1)
+    fields = re.findall(r"(int64_t|double)\s+(\w+);", body)
+    ctype = {"int64_t": ctypes.c_int64, "double": ctypes.c_double}
+    assert [(n, ctype[t]) for t, n in fields] == list(binding.KernelProfile._fields_)
