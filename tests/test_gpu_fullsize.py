@@ -45,7 +45,7 @@ def test_fullsize_chol_integer_family_bitwise(s):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("s", [384, 640])
+@pytest.mark.parametrize("s", [384, 640, 768])
 @pytest.mark.parametrize("fixed_step", [False, True])
 def test_fullsize_chol_integer_family_bitwise_wide_steps(s, fixed_step):
     # the benchmark's steps; by default the first block and the last 6144 columns
@@ -117,11 +117,13 @@ def test_fullsize_lu_strassen_integer_family_bitwise():
     torch.cuda.empty_cache()
 
 
-def test_fullsize_chol_benchmark_matrix_s320():
-    # the step size the benchmark picks: backward error of the timed configuration
+@pytest.mark.parametrize("s", [320, 640, 768])
+def test_fullsize_chol_benchmark_matrix_wide_steps(s):
+    # the step sizes the benchmark's sweep picks between: backward error of the
+    # timed configuration
     A0 = wl.spd_scaled_device(N, seed=0, device=DEV)
     Acm = A0.clone().t()
-    assert ff.chol_factor(Acm, 320, dtype="f64", sync=True) == 0
+    assert ff.chol_factor(Acm, s, dtype="f64", sync=True) == 0
     L = torch.tril(Acm)
     bwd = float(torch.linalg.norm(A0.t() - L @ L.t().contiguous()) / torch.linalg.norm(A0))
     assert bwd <= 1e-13
@@ -129,7 +131,8 @@ def test_fullsize_chol_benchmark_matrix_s320():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("dtype,s", [("f64", 256), ("f32", 256), ("bf16", 512)])
+@pytest.mark.parametrize("dtype,s", [("f64", 256), ("f32", 256), ("bf16", 512), ("f64", 640), ("f32", 640),
+                                     ("bf16", 768)])
 def test_fullsize_refined_solve_integer_solution(dtype, s):
     # the benchmark family (kappa ~ 5); b = A x0 by torch's GEMM, so x0 is recovered
     # to about kappa * 1e-16 (the integer family's triangular factors are too
