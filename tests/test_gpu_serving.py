@@ -55,8 +55,13 @@ def drain(srv, limit=100000):
         if left == 0:
             break
     torch.cuda.synchronize()
-    for r in srv.poll():
-        out[r["id"]] = r
+    # poll hands out at most max_out results per call: collect until none is left
+    while True:
+        got = srv.poll()
+        if not got:
+            break
+        for r in got:
+            out[r["id"]] = r
     return out
 
 
