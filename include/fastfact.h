@@ -73,8 +73,10 @@ enum {
                                       events; the call still returns with all
                                       work ordered before later work on
                                       `stream`) while the rest of the update
-                                      runs on all but a few CUs.  Both
-                                      schedules give bitwise identical factors. */
+                                      runs on all but a few CUs; the last
+                                      min(1536, n/4) columns are factored in
+                                      order on `stream`.  Both schedules give
+                                      bitwise identical factors. */
     FF_FLAG_FIXED_STEP = 1u << 2    /* every block exactly s columns wide (the
                                       step of Sec. 2 Algorithms 1 and 2
                                       verbatim).  Without it, the first block

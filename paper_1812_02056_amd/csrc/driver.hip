@@ -360,6 +360,9 @@ double round_aligned_tail(int T, int nwg, int r, double f, double u, double p) {
 // by one kernel instead of a recursive chain of four or more (measured at
 // n = 16384, s = 320 and 512: the time is flat for thresholds 4608 to 8192).
 constexpr int CHOL_TAIL_COLS = 6144;
+// Columns (at most a quarter of the matrix) after which the lookahead schedule
+// finishes in order on one stream.
+constexpr int CHOL_INORDER_COLS = 1536;
 inline int chol_block_width(int s, int c0, int n, unsigned flags) {
     const bool edge = c0 == 0 || n - c0 <= CHOL_TAIL_COLS;
     const int w = (s > LDS_DIAG_MAX && edge && !(flags & FF_FLAG_FIXED_STEP)) ? LDS_DIAG_MAX : s;
@@ -378,9 +381,10 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         side = acquire_side(dev);
         if (!side) return FF_ERR_HIP;
     }
-    int rc = 0;
-    if (!side) {
-        for (int c0 = 0, w = 0; c0 < n && !rc; c0 += w) {
+    // blocks from column c_start on, in order on `st`
+    auto in_order = [&](int c_start) {
+        int rc = 0;
+        for (int c0 = c_start, w = 0; c0 < n && !rc; c0 += w) {
             w = chol_block_width(s, c0, n, flags);
             const int m = n - c0 - w;
             rc = chol_panel<S>(n, c0, w, A, lda, dtype, ws64, info, col_base, st);
@@ -390,7 +394,10 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
             rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, m, dtype, flags, info, st);
         }
         return rc;
-    }
+    };
+    int rc = 0;
+    if (!side) return in_order(0);
+    const int last_in_order = std::min(CHOL_INORDER_COLS, n / 4);
     // lookahead schedule
     hipEvent_t e0 = evs.make();
     if (!e0) { release_side(dev, side); return FF_ERR_HIP; }
@@ -407,6 +414,13 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         if (m <= 0) break;
         S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
         S* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
+        if (m <= last_in_order) {
+            // the last steps in order on `st`: there the whole update is shorter
+            // than the two hand-overs between the streams a lookahead step makes
+            rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, m, dtype, flags, info, st);
+            release_side(dev, side);
+            return rc ? rc : in_order(c0 + w);
+        }
         const int wn = chol_block_width(s, c0 + w, n, flags);    // width of the next block
         // 1) the next block's columns of the update, then hand them to the side stream
         rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, wn, dtype, flags & ~FF_FLAG_STRASSEN1, info, st);
@@ -471,6 +485,9 @@ int chol_diag(int w, S* A11, int64_t lda, int dtype, double* ws64, int* info, in
 // LU_LDS_MAX when s is wider (one LDS kernel each), unless FF_FLAG_FIXED_STEP
 // (measured at n = 16384, s = 512 and 768: best at 4096, within 0.2 ms at 6144).
 constexpr int LU_TAIL_COLS = 4096;
+// Columns (at most a quarter of the matrix) after which the lookahead schedule
+// finishes in order on one stream.
+constexpr int LU_INORDER_COLS = 1536;
 inline int lu_block_width(int s, int c0, int n, unsigned flags) {
     const bool edge = c0 == 0 || n - c0 <= LU_TAIL_COLS;
     const int w = (s > LU_LDS_MAX && edge && !(flags & FF_FLAG_FIXED_STEP)) ? LU_LDS_MAX : s;
@@ -504,6 +521,36 @@ int lu_panel(int n, int c0, int w, double* A, int64_t lda, int* info, int col_ba
     return trsm_blocked<double>(m, w, A12, lda, false, A11, lda, true, 1, info, st, max_wg);
 }
 
+// Blocks from column c_start on, in order on `st`.
+int lu_in_order(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st,
+                int c_start) {
+    for (int c0 = c_start, w = 0; c0 < n; c0 += w) {
+        w = lu_block_width(s, c0, n, flags);
+        const int m = n - c0 - w;
+        double* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
+        {
+            int rc = lu_diag(w, A11, lda, info, col_base + c0, st);
+            if (rc) return rc;
+        }
+        if (m <= 0) break;
+        double* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
+        double* A12 = A + (int64_t)c0 + (int64_t)(c0 + w) * lda;
+        double* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
+        // L21 U11 = A21: T(k, j) = U11(k, j) = A11[k + j*lda]
+        int rc = trsm_blocked<double>(m, w, A21, lda, true, A11, lda, false, 0, info, st);
+        if (rc) return rc;
+        // L11 U12 = A12  <=>  U12^T L11^T = A12^T: rows of X are columns of A12,
+        // T(k, j) = L11(j, k) with unit diagonal
+        rc = trsm_blocked<double>(m, w, A12, lda, false, A11, lda, true, 1, info, st);
+        if (rc) return rc;
+        if (flags & FF_FLAG_STRASSEN1)
+            FF_TRY(launch_update_gemm_strassen_f64(m, w, A22, lda, A21, lda, A12, lda, info, st));
+        else
+            FF_TRY(launch_update<double>(m, m, w, A22, lda, A21, lda, A12, lda, false, false, 0, info, st));
+    }
+    return 0;
+}
+
 // Lookahead schedule of the LU (as for Cholesky): while the rest of update k
 // runs on `st` on all but `reserve` CUs, the side stream factors block k + 1
 // (whose column and row strips were updated first) and then takes the tail of
@@ -518,6 +565,7 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
     hipEvent_t e0 = evs.make();
     if (!e0 || hipEventRecord(e0, st) != hipSuccess || hipStreamWaitEvent(side, e0, 0) != hipSuccess)
         return fail(FF_ERR_HIP);
+    const int last_in_order = std::min(LU_INORDER_COLS, n / 4);
     int rc = lu_panel(n, 0, lu_block_width(s, 0, n, flags), A, lda, info, col_base, side);
     if (rc) return fail(rc);
     hipEvent_t ep = evs.make();
@@ -530,6 +578,15 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
         double* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
         double* A12 = A + (int64_t)c0 + (int64_t)(c0 + w) * lda;
         double* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
+        if (m <= last_in_order) {
+            // the last steps in order on `st`: there the whole update is shorter
+            // than the two hand-overs between the streams a lookahead step makes
+            hipError_t e = (flags & FF_FLAG_STRASSEN1)
+                               ? launch_update_gemm_strassen_f64(m, w, A22, lda, A21, lda, A12, lda, info, st)
+                               : launch_update<double>(m, m, w, A22, lda, A21, lda, A12, lda, false, false, 0, info, st);
+            release_side(dev, side);
+            return e != hipSuccess ? FF_ERR_HIP : lu_in_order(n, s, A, lda, flags, info, col_base, st, c0 + w);
+        }
         const int wn = lu_block_width(s, c0 + w, n, flags);
         const int mr = m - wn;
         // 1) the next block's column strip (all rows) and row strip
@@ -579,31 +636,7 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
 
 int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st) {
     if (n > s && !(flags & FF_FLAG_NO_LOOKAHEAD)) return lu_lookahead(n, s, A, lda, flags, info, col_base, st);
-    for (int c0 = 0, w = 0; c0 < n; c0 += w) {
-        w = lu_block_width(s, c0, n, flags);
-        const int m = n - c0 - w;
-        double* A11 = A + (int64_t)c0 + (int64_t)c0 * lda;
-        {
-            int rc = lu_diag(w, A11, lda, info, col_base + c0, st);
-            if (rc) return rc;
-        }
-        if (m <= 0) break;
-        double* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
-        double* A12 = A + (int64_t)c0 + (int64_t)(c0 + w) * lda;
-        double* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
-        // L21 U11 = A21: T(k, j) = U11(k, j) = A11[k + j*lda]
-        int rc = trsm_blocked<double>(m, w, A21, lda, true, A11, lda, false, 0, info, st);
-        if (rc) return rc;
-        // L11 U12 = A12  <=>  U12^T L11^T = A12^T: rows of X are columns of A12,
-        // T(k, j) = L11(j, k) with unit diagonal
-        rc = trsm_blocked<double>(m, w, A12, lda, false, A11, lda, true, 1, info, st);
-        if (rc) return rc;
-        if (flags & FF_FLAG_STRASSEN1)
-            FF_TRY(launch_update_gemm_strassen_f64(m, w, A22, lda, A21, lda, A12, lda, info, st));
-        else
-            FF_TRY(launch_update<double>(m, m, w, A22, lda, A21, lda, A12, lda, false, false, 0, info, st));
-    }
-    return 0;
+    return lu_in_order(n, s, A, lda, flags, info, col_base, st, 0);
 }
 
 int check_common(int64_t n, int64_t s, const void* A, int64_t lda, int dtype, unsigned flags) {
