@@ -361,7 +361,8 @@ double round_aligned_tail(int T, int nwg, int r, double f, double u, double p) {
 // n = 16384, s = 320 and 512: the time is flat for thresholds 4608 to 8192).
 constexpr int CHOL_TAIL_COLS = 6144;
 // Columns (at most a quarter of the matrix) after which the lookahead schedule
-// finishes in order on one stream.
+// finishes in order on one stream (measured at n = 16384, s = 768: 0.25 ms
+// faster than lookahead to the end, flat for thresholds 1152 to 2304).
 constexpr int CHOL_INORDER_COLS = 1536;
 inline int chol_block_width(int s, int c0, int n, unsigned flags) {
     const bool edge = c0 == 0 || n - c0 <= CHOL_TAIL_COLS;
@@ -486,7 +487,8 @@ int chol_diag(int w, S* A11, int64_t lda, int dtype, double* ws64, int* info, in
 // (measured at n = 16384, s = 512 and 768: best at 4096, within 0.2 ms at 6144).
 constexpr int LU_TAIL_COLS = 4096;
 // Columns (at most a quarter of the matrix) after which the lookahead schedule
-// finishes in order on one stream.
+// finishes in order on one stream (measured at n = 16384, s = 768: 0.4 ms
+// faster than lookahead to the end, flat for thresholds 1024 to 3072).
 constexpr int LU_INORDER_COLS = 1536;
 inline int lu_block_width(int s, int c0, int n, unsigned flags) {
     const bool edge = c0 == 0 || n - c0 <= LU_TAIL_COLS;
