@@ -164,98 +164,121 @@ void oracle_lu_solve(int64_t n, int64_t nrhs, const double *LU, int64_t ldlu,
 }
 
 /*
- * Algorithm 1 of Sec. 2 with step size s, 0-based.  z is the first column not
- * yet folded into the trailing matrix.  When s columns are pending (c == z+s)
- * the block R = L[c.., z..c-1] gives S = R R^T, which is subtracted from the
- * whole trailing square A[c.., c..] of the working matrix; then column c is
- * formed from the working matrix and the pending columns z..c-1 only.
+ * The step-s algorithms of Sec. 2 (Algorithms 1 and 2) in block terms.  With
+ * the columns cut into consecutive blocks of w = min(s, columns left), the
+ * columns of one block are formed from the working matrix, which already holds
+ * every earlier block's deferred product, and from the block's own earlier
+ * columns only.  For a block starting at column c0 that is
+ *   (i)   the factorisation of its w x w diagonal block,
+ *   (ii)  the triangular solve of the rows below it against that factor (LU:
+ *         also of the columns to its right),
+ *   (iii) if rows remain, the deferred product of the block's m x w columns
+ *         with their transposed partner, subtracted from the whole m x m
+ *         trailing square of the working matrix (one "update").
+ * Each entry is one running difference started from the working matrix and
+ * taken over the block's columns in ascending order, followed by one division.
+ */
+
+/* Working-matrix helpers shared by the two step-s routines below. */
+static double *copy_square(int64_t n, const double *A, int64_t lda)
+{
+    double *W = (double *)malloc((size_t)n * (size_t)n * sizeof(double));
+    for (int64_t j = 0; j < n; ++j)
+        memcpy(W + (size_t)j * (size_t)n, A + (size_t)j * (size_t)lda, (size_t)n * sizeof(double));
+    return W;
+}
+
+/* Aw[r.., r..] -= X Y over the whole trailing square, where X(i, k) = Lw[r+i, c0+k]
+ * and Y(k, j) = Rw[c0+k, r+j] (k < w); each entry's product is summed first. */
+static void subtract_block_product(int64_t n, int64_t c0, int64_t w, double *Aw,
+                                   const double *Lw, const double *Rw)
+{
+    const int64_t r = c0 + w;
+    for (int64_t j = r; j < n; ++j)
+        for (int64_t i = r; i < n; ++i) {
+            double prod = 0.0;
+            for (int64_t k = c0; k < r; ++k) prod += Lw[IDX(i, k, n)] * Rw[IDX(k, j, n)];
+            Aw[IDX(i, j, n)] -= prod;
+        }
+}
+
+/*
+ * Algorithm 1 of Sec. 2 with step s.  Per block: (i) Cholesky of the diagonal
+ * block, (ii) rows below divided through by the block's factor transposed,
+ * (iii) the symmetric deferred product R R^T.  Rt holds the transposed factor
+ * so that (iii) has the same shape as the LU product.
  */
 int64_t oracle_chol_alg1(int64_t n, int64_t s, const double *A, int64_t lda,
                          double *L, int64_t ldl)
 {
     if (n <= 0) return 0;
-    const size_t nn = (size_t)n * (size_t)n;
-    double *Aw = (double *)malloc(nn * sizeof(double));
-    double *Lw = (double *)calloc(nn, sizeof(double)); /* column-major n x n */
-    for (int64_t j = 0; j < n; ++j)
-        for (int64_t i = 0; i < n; ++i) Aw[IDX(i, j, n)] = A[IDX(i, j, lda)];
-    int64_t z = 0, updates = 0;
-    for (int64_t c = 0; c < n; ++c) {
-        if (c == z + s) {
-            const int64_t m = n - c;
-            double *S = (double *)malloc((size_t)m * (size_t)m * sizeof(double));
-            for (int64_t j = 0; j < m; ++j)
-                for (int64_t i = 0; i < m; ++i) {
-                    double t = 0.0;
-                    for (int64_t k = z; k < c; ++k) t += Lw[IDX(c + i, k, n)] * Lw[IDX(c + j, k, n)];
-                    S[IDX(i, j, m)] = t;
-                }
-            for (int64_t j = 0; j < m; ++j)
-                for (int64_t i = 0; i < m; ++i) Aw[IDX(c + i, c + j, n)] -= S[IDX(i, j, m)];
-            free(S);
-            z = c;
-            ++updates;
+    double *Aw = copy_square(n, A, lda);
+    double *Lw = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
+    double *Rt = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
+    int64_t updates = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += s) {
+        const int64_t w = (n - c0 < s) ? n - c0 : s;
+        /* (i) + (ii): column by column over the block; the pivot comes from the
+         * diagonal entry, the rows below (inside and under the block) share it. */
+        for (int64_t c = c0; c < c0 + w; ++c) {
+            double piv = Aw[IDX(c, c, n)];
+            for (int64_t k = c0; k < c; ++k) piv -= Lw[IDX(c, k, n)] * Lw[IDX(c, k, n)];
+            const double root = sqrt(piv);
+            Lw[IDX(c, c, n)] = root;
+            for (int64_t i = c + 1; i < n; ++i) {
+                double v = Aw[IDX(i, c, n)];
+                for (int64_t k = c0; k < c; ++k) v -= Lw[IDX(i, k, n)] * Lw[IDX(c, k, n)];
+                Lw[IDX(i, c, n)] = v / root;
+            }
         }
-        double d = Aw[IDX(c, c, n)];
-        for (int64_t k = z; k < c; ++k) d -= Lw[IDX(c, k, n)] * Lw[IDX(c, k, n)];
-        const double lcc = sqrt(d);
-        Lw[IDX(c, c, n)] = lcc;
-        for (int64_t i = c + 1; i < n; ++i) {
-            double t = Aw[IDX(i, c, n)];
-            for (int64_t k = z; k < c; ++k) t -= Lw[IDX(i, k, n)] * Lw[IDX(c, k, n)];
-            Lw[IDX(i, c, n)] = t / lcc;
-        }
+        if (c0 + w >= n) break;
+        /* (iii) */
+        for (int64_t k = c0; k < c0 + w; ++k)
+            for (int64_t j = c0 + w; j < n; ++j) Rt[IDX(k, j, n)] = Lw[IDX(j, k, n)];
+        subtract_block_product(n, c0, w, Aw, Lw, Rt);
+        ++updates;
     }
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < n; ++i) L[IDX(i, j, ldl)] = Lw[IDX(i, j, n)];
     free(Aw);
     free(Lw);
+    free(Rt);
     return updates;
 }
 
 /*
- * Algorithm 2 of Sec. 2 with step size s, 0-based: Crout factors (L lower with
- * its diagonal, U unit upper).  The deferred product is S = R_L R_U with
- * R_L = L[c.., z..c-1] and R_U = U[z..c-1, c..].
+ * Algorithm 2 of Sec. 2 with step s, Crout form (L lower with its diagonal, U
+ * unit upper).  Per block, column c of L and then row c of U, ascending:
+ * L(i, c) for rows i >= c (the diagonal block and the rows below it, solved
+ * against the block's unit U), then U(c, j) for columns j >= c (solved against
+ * the block's L and divided by L(c, c)); then (iii) S = R_L R_U.
  */
 int64_t oracle_lu_alg2(int64_t n, int64_t s, const double *A, int64_t lda,
                        double *L, int64_t ldl, double *U, int64_t ldu)
 {
     if (n <= 0) return 0;
-    const size_t nn = (size_t)n * (size_t)n;
-    double *Aw = (double *)malloc(nn * sizeof(double));
-    double *Lw = (double *)calloc(nn, sizeof(double));
-    double *Uw = (double *)calloc(nn, sizeof(double));
-    for (int64_t j = 0; j < n; ++j)
-        for (int64_t i = 0; i < n; ++i) Aw[IDX(i, j, n)] = A[IDX(i, j, lda)];
-    int64_t z = 0, updates = 0;
-    for (int64_t c = 0; c < n; ++c) {
-        if (c == z + s) {
-            const int64_t m = n - c;
-            double *S = (double *)malloc((size_t)m * (size_t)m * sizeof(double));
-            for (int64_t j = 0; j < m; ++j)
-                for (int64_t i = 0; i < m; ++i) {
-                    double t = 0.0;
-                    for (int64_t k = z; k < c; ++k) t += Lw[IDX(c + i, k, n)] * Uw[IDX(k, c + j, n)];
-                    S[IDX(i, j, m)] = t;
-                }
-            for (int64_t j = 0; j < m; ++j)
-                for (int64_t i = 0; i < m; ++i) Aw[IDX(c + i, c + j, n)] -= S[IDX(i, j, m)];
-            free(S);
-            z = c;
-            ++updates;
+    double *Aw = copy_square(n, A, lda);
+    double *Lw = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
+    double *Uw = (double *)calloc((size_t)n * (size_t)n, sizeof(double));
+    int64_t updates = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += s) {
+        const int64_t w = (n - c0 < s) ? n - c0 : s;
+        for (int64_t c = c0; c < c0 + w; ++c) {
+            for (int64_t i = c; i < n; ++i) {
+                double v = Aw[IDX(i, c, n)];
+                for (int64_t k = c0; k < c; ++k) v -= Lw[IDX(i, k, n)] * Uw[IDX(k, c, n)];
+                Lw[IDX(i, c, n)] = v;
+            }
+            const double piv = Lw[IDX(c, c, n)];
+            for (int64_t j = c; j < n; ++j) {
+                double v = Aw[IDX(c, j, n)];
+                for (int64_t k = c0; k < c; ++k) v -= Lw[IDX(c, k, n)] * Uw[IDX(k, j, n)];
+                Uw[IDX(c, j, n)] = v / piv;
+            }
         }
-        for (int64_t i = c; i < n; ++i) {
-            double t = Aw[IDX(i, c, n)];
-            for (int64_t k = z; k < c; ++k) t -= Lw[IDX(i, k, n)] * Uw[IDX(k, c, n)];
-            Lw[IDX(i, c, n)] = t;
-        }
-        const double lcc = Lw[IDX(c, c, n)];
-        for (int64_t i = c; i < n; ++i) {
-            double t = Aw[IDX(c, i, n)];
-            for (int64_t k = z; k < c; ++k) t -= Lw[IDX(c, k, n)] * Uw[IDX(k, i, n)];
-            Uw[IDX(c, i, n)] = t / lcc;
-        }
+        if (c0 + w >= n) break;
+        subtract_block_product(n, c0, w, Aw, Lw, Uw);
+        ++updates;
     }
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < n; ++i) {

@@ -4,9 +4,10 @@ This module only draws random matrices and right-hand sides; it holds none of
 the factorisation arithmetic, so both the GPU path and the CPU oracle can take
 their inputs from it.  Every generator is deterministic in ``seed``.
 
-The paper's own experiment used "a symmetric matrix with random entries and
-large values in the diagonal" (Sec. 3, timing paragraph) without stating the
-distribution; the families here are concrete stand-ins with known conditioning:
+The paper times its method on a random symmetric matrix whose diagonal is made
+large (Sec. 2, the timing paragraph after the cost analysis) and does not say
+how the entries are drawn; the families here are concrete stand-ins with known
+conditioning:
 
 * ``spd_shifted``  A = G G^T + n I            (G i.i.d. N(0,1); kappa ~ 5)
 * ``spd_scaled``   A = G G^T / n + lam I      (kappa ~ 5 / 4e3 / 2e6 for lam = 1 / 1e-3 / 1e-6)
