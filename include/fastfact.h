@@ -177,13 +177,18 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double *A64, int64_t ld
 /*
  * Triangular solve with a Cholesky factor: X = L^-T L^-1 X in place (forward
  * then back substitution, in the storage precision of L: double for FF_F64,
- * float otherwise; X has the same type).  L is n x n lower (only tril read).
- * The solve works on 64-row blocks and first forms the inverses of the 64 x 64
- * diagonal blocks of L in the workspace (binary64 arithmetic, stored in L's
- * precision).  Asynchronous; a bounded wait that expired (which does not happen
- * unless the device is shared with work that starves the launch) is reported
- * in the workspace and by chol_solve.
- *   ws   device workspace >= ff_trisolve_workspace_size(n, dtype)
+ * float otherwise; X has the same type).  L is n x n lower (only tril read);
+ * used to solve A x = b once A = L L^T is known (Introduction).  The solve
+ * works on 64-row blocks: it first forms, in the workspace, the inverses of
+ * the 64 x 64 diagonal blocks (binary64 arithmetic, stored in L's precision)
+ * and copies of the tiles next to the diagonal, then runs one forward and one
+ * backward sweep per group of at most 16 right-hand sides.  Asynchronous.
+ *   ws   device workspace >= ff_trisolve_workspace_size(n, dtype).  Its first
+ *        int32 is an error word: the call sets it to 0, and it becomes
+ *        nonzero if a bounded wait between the workgroups of a sweep expired
+ *        (which does not happen unless the device is shared with work that
+ *        starves the launch); X is then unspecified.  Read it after the stream
+ *        has reached the end of the call.
  */
 size_t ff_trisolve_workspace_size(int64_t n, int dtype);
 int chol_trisolve(int64_t n, int64_t nrhs, const void *L, int64_t ldl, int dtype,

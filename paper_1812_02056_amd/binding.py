@@ -277,8 +277,13 @@ def chol_solve(A64: torch.Tensor, B: torch.Tensor, s: int, dtype="f32", W: torch
     return X, W, out.as_dict()
 
 
+def trisolve_workspace_size(n: int, dtype="f64") -> int:
+    return int(load().ff_trisolve_workspace_size(n, _dt(dtype)))
+
+
 def chol_trisolve(L: torch.Tensor, X: torch.Tensor, dtype="f64", stream=None, ws: torch.Tensor | None = None):
-    """X <- L^-T L^-1 X in place, in L's storage precision."""
+    """X <- L^-T L^-1 X in place, in L's storage precision.  The first int32 of
+    the workspace is the error word (nonzero if a bounded wait expired)."""
     lib = load()
     dt = _dt(dtype)
     n = int(L.shape[0])

@@ -653,11 +653,9 @@ int check_common(int64_t n, int64_t s, const void* A, int64_t lda, int dtype, un
 
 template <typename S>
 struct SolveWs {
+    TriWs<S> tri;
     double* diag64;
     int* d_info;
-    S* linv;
-    int* flags;
-    S* parts;
     double* rpart;
     double* R;
     S* D;
@@ -666,15 +664,24 @@ struct SolveWs {
     size_t bytes;
 };
 
+// Triangular-solve workspace: the control words first, so that the error word
+// is the first int32 of the workspace.
+template <typename S>
+TriWs<S> carve_tri(Carver& cv, int64_t n) {
+    TriWs<S> t;
+    t.ctl = cv.take<int>(TRI_CTL);
+    t.fac = cv.take<S>(trisolve_fac_elems((int)n));
+    t.pub = cv.take<S>(trisolve_pub_elems((int)n));
+    return t;
+}
+
 template <typename S>
 SolveWs<S> carve_solve(void* base, int64_t n, int64_t s, int64_t nrhs, int dtype) {
     Carver cv(base);
     SolveWs<S> w;
+    w.tri = carve_tri<S>(cv, n);
     w.diag64 = cv.take<double>(diag_ws_bytes(n, s, dtype) / sizeof(double));
     w.d_info = cv.take<int>(1);
-    w.linv = cv.take<S>(trisolve_linv_elems((int)n));
-    w.flags = cv.take<int>(trisolve_flag_ints((int)n));
-    w.parts = cv.take<S>(trisolve_part_elems((int)n));
     w.rpart = cv.take<double>(residual_part_doubles((int)n));
     w.R = cv.take<double>((size_t)n * (size_t)nrhs);
     w.D = cv.take<S>((size_t)n * (size_t)nrhs);
@@ -689,6 +696,7 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
                unsigned flags, int w_is_factored, const double* B, int64_t ldb, double* X, int64_t ldx,
                double tol, int max_iter, void* ws, hipStream_t st, ff_solve_info* out) {
     SolveWs<S> w = carve_solve<S>(ws, n, s, nrhs, dtype);
+    FF_TRY(launch_set_int(w.tri.ctl, 0, st));
     out->info = 0;
     out->iters = 0;
     out->converged = 0;
@@ -711,7 +719,7 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
     }
     // iteration 0: X = W^-T W^-1 B in the factor's precision
     FF_TRY(launch_convert_from_f64<S>(n, nrhs, B, ldb, w.D, n, st));
-    FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.linv, w.flags, w.parts, true, st));
+    FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.tri, true, st));
     FF_TRY(launch_widen<S>(n, nrhs, w.D, n, X, ldx, st));
     double prev = -1.0;
     double host[2];
@@ -719,7 +727,7 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
     for (int it = 1; it <= max_iter; ++it) {
         FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, nullptr, w.rpart, st));
         FF_TRY(launch_convert_from_f64<S>(n, nrhs, w.R, n, w.D, n, st));
-        FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.linv, w.flags, w.parts, false, st));
+        FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.tri, false, st));
         FF_TRY(launch_axpy_max<S>(n, nrhs, w.D, n, X, ldx, w.norms, st));
         FF_TRY(hipMemcpyAsync(host, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         FF_TRY(hipStreamSynchronize(st));
@@ -737,14 +745,9 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
     FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, w.rowsum, w.rpart, st));
     FF_TRY(launch_norms(n, nrhs, w.rowsum, X, ldx, nullptr, 0, w.R, n, B, ldb, w.norms, st));
     std::vector<double> nh(3 + 3 * (size_t)nrhs);
-    int wait_err[2] = {0, 0};
     FF_TRY(hipMemcpyAsync(nh.data(), w.norms, nh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    FF_TRY(hipMemcpyAsync(&wait_err[0], w.flags + trisolve_error_index((int)n, 0), sizeof(int), hipMemcpyDeviceToHost,
-                          st));
-    FF_TRY(hipMemcpyAsync(&wait_err[1], w.flags + trisolve_error_index((int)n, 1), sizeof(int), hipMemcpyDeviceToHost,
-                          st));
+    FF_TRY(hipMemcpyAsync(&bad_wait, w.tri.ctl, sizeof(int), hipMemcpyDeviceToHost, st));
     FF_TRY(hipStreamSynchronize(st));
-    bad_wait = wait_err[0] | wait_err[1];
     if (bad_wait) return FF_ERR_HIP;
     const double anorm = nh[2];
     double be = 0.0;
@@ -756,6 +759,27 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
     out->backward_err = be;
     if (max_iter == 0) out->converged = 0;
     return 0;
+}
+
+// Solve with the triangular-solve workspace already carved; clears the error word first.
+int trisolve_entry(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtype, void* X, int64_t ldx, void* ws,
+                   hipStream_t st) {
+    Carver cv(ws);
+    hipError_t e;
+    if (dtype == FF_F64) {
+        TriWs<double> t = carve_tri<double>(cv, n);
+        e = launch_set_int(t.ctl, 0, st);
+        if (e == hipSuccess)
+            e = trisolve_impl<double>((int)n, (int)nrhs, static_cast<const double*>(L), ldl, static_cast<double*>(X),
+                                      ldx, t, true, st);
+    } else {
+        TriWs<float> t = carve_tri<float>(cv, n);
+        e = launch_set_int(t.ctl, 0, st);
+        if (e == hipSuccess)
+            e = trisolve_impl<float>((int)n, (int)nrhs, static_cast<const float*>(L), ldl, static_cast<float*>(X), ldx,
+                                     t, true, st);
+    }
+    return e == hipSuccess ? 0 : FF_ERR_HIP;
 }
 
 }  // namespace
@@ -866,9 +890,10 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t ld
 
 size_t ff_trisolve_workspace_size(int64_t n, int dtype) {
     if (n <= 0) return 0;
-    const size_t es = (dtype == FF_F64) ? sizeof(double) : sizeof(float);
-    return align_up(trisolve_linv_elems((int)n) * es) + align_up(trisolve_flag_ints((int)n) * sizeof(int)) +
-           align_up(trisolve_part_elems((int)n) * es);
+    Carver cv(nullptr);
+    if (dtype == FF_F64) (void)carve_tri<double>(cv, n);
+    else (void)carve_tri<float>(cv, n);
+    return cv.off;
 }
 
 int chol_trisolve(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtype, void* X, int64_t ldx, void* ws,
@@ -882,24 +907,7 @@ int chol_trisolve(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtype
     if (ldx < std::max<int64_t>(1, n)) return -7;
     if (n == 0 || nrhs == 0) return 0;
     if (ws == nullptr || ws_bytes < ff_trisolve_workspace_size(n, dtype)) return FF_ERR_WORKSPACE;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    Carver cv(ws);
-    if (dtype == FF_F64) {
-        double* linv = cv.take<double>(trisolve_linv_elems((int)n));
-        int* flags = cv.take<int>(trisolve_flag_ints((int)n));
-        double* parts = cv.take<double>(trisolve_part_elems((int)n));
-        if (trisolve_impl<double>((int)n, (int)nrhs, static_cast<const double*>(L), ldl, static_cast<double*>(X), ldx,
-                                  linv, flags, parts, true, st) != hipSuccess)
-            return FF_ERR_HIP;
-    } else {
-        float* linv = cv.take<float>(trisolve_linv_elems((int)n));
-        int* flags = cv.take<int>(trisolve_flag_ints((int)n));
-        float* parts = cv.take<float>(trisolve_part_elems((int)n));
-        if (trisolve_impl<float>((int)n, (int)nrhs, static_cast<const float*>(L), ldl, static_cast<float*>(X), ldx,
-                                 linv, flags, parts, true, st) != hipSuccess)
-            return FF_ERR_HIP;
-    }
-    return 0;
+    return trisolve_entry(n, nrhs, L, ldl, dtype, X, ldx, ws, static_cast<hipStream_t>(stream));
 }
 
 int ff_update_syrk(int64_t m, int64_t w, void* C, int64_t ldc, const void* P, int64_t ldp, int dtype, unsigned flags,

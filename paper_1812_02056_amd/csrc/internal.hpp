@@ -102,23 +102,36 @@ template <typename S>
 hipError_t launch_copy_lower_from_f64(int n, const double* A, int64_t lda, S* W, int64_t ldw, hipStream_t st);
 template <typename S>
 hipError_t launch_convert_from_f64(int n, int nrhs, const double* B, int64_t ldb, S* X, int64_t ldx, hipStream_t st);
-// Solve L L^T X = X in place with 64-row blocks; Linv holds (or, when
-// make_inverses, receives) the inverses of the 64 x 64 diagonal blocks
-// (trisolve_linv_elems(n) elements); flags needs trisolve_flag_ints(n) ints and
-// parts trisolve_part_elems(n) elements.  The word at trisolve_error_index(n, k)
-// of flags becomes nonzero if a bounded wait of sweep k (0 forward, 1 backward)
-// expired.
-constexpr int TRISOLVE_TP = 8;      // workgroups per 64-row block
+// Triangular solves with a Cholesky factor (solve.hip).  X = L^-T L^-1 X in
+// place, 64-row blocks, at most TRI_RC right-hand sides per sweep.  Memory:
+//   fac   per-factor data, trisolve_fac_elems(n) elements of the factor's
+//         type: the inverses of the 64 x 64 diagonal blocks, the same
+//         transposed, and the tiles L(j, j-f) and L(j+f, j)^T, f = 1..TRI_F,
+//         that the solving workgroup folds itself, all laid out in the order
+//         its threads read them.  Formed when make_fac is set, reusable while
+//         L is unchanged.
+//   pub   hand-off area of trisolve_pub_elems(n) elements (solved blocks and
+//         partial sums, pre-filled with a sentinel before every sweep).
+//   ctl   TRI_CTL ints: [0] error word (nonzero once a bounded wait of any
+//         sweep expired; never cleared here, callers clear it once per call),
+//         [1], [2] the two sweeps' workgroup tickets.
+constexpr int TRI_TB = 64;          // row block
+constexpr int TRI_RC = 16;          // right-hand sides per sweep
+constexpr int TRI_F = 2;            // newest solved blocks the solving workgroup folds itself
+constexpr int TRI_CTL = 4;
 constexpr int RESIDUAL_CB = 16;     // 64-column blocks per residual workgroup
-inline int trisolve_nblk(int n) { return (n + 63) / 64; }
-inline size_t trisolve_linv_elems(int n) { return (size_t)trisolve_nblk(n) * 64 * 64; }
-inline size_t trisolve_sweep_ints(int n) { return 2 + (size_t)trisolve_nblk(n) * (1 + TRISOLVE_TP); }
-inline size_t trisolve_flag_ints(int n) { return 2 * trisolve_sweep_ints(n); }
-inline size_t trisolve_error_index(int n, int sweep) { return sweep * trisolve_sweep_ints(n) + 1; }
-inline size_t trisolve_part_elems(int n) { return (size_t)trisolve_nblk(n) * (TRISOLVE_TP - 1) * 64 * 16; }
+inline int trisolve_nblk(int n) { return (n + TRI_TB - 1) / TRI_TB; }
+inline size_t trisolve_fac_elems(int n) { return (size_t)trisolve_nblk(n) * (2 + 2 * TRI_F) * TRI_TB * TRI_TB; }
+inline size_t trisolve_pub_elems(int n) { return (size_t)4 * trisolve_nblk(n) * TRI_TB * TRI_RC; }
 template <typename S>
-hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, S* Linv, int* flags, S* parts,
-                         bool make_inverses, hipStream_t st);
+struct TriWs {
+    int* ctl;
+    S* fac;
+    S* pub;
+};
+template <typename S>
+hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, const TriWs<S>& w,
+                         bool make_fac, hipStream_t st);
 // part: residual_part_doubles(n) doubles of scratch.
 inline size_t residual_part_doubles(int n) {
     const size_t nch = ((size_t)trisolve_nblk(n) + RESIDUAL_CB - 1) / RESIDUAL_CB;

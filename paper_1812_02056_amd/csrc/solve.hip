@@ -5,15 +5,26 @@
 // from the low-precision factor, x += d) is how the mixed-precision factor wins
 // back binary64 accuracy.
 //
-// Triangular solves: the n rows are cut into 64-row blocks, and each block gets
-// TP workgroups that take tickets from an atomic counter in block order.  The
-// first TP - 1 fold disjoint sets of already-solved blocks into partial sums as
-// those blocks' flags appear (streaming their tiles of L, the next tile loaded
-// while the current one is applied); the last one folds the newest solved block,
-// adds the partial sums in a fixed order, applies the precomputed inverse of the
-// 64 x 64 diagonal block and publishes the block.  Every wait is on a workgroup
-// with a smaller ticket, so every wait ends; each is also bounded: past the spin
-// limit the workgroup records an error and exits.
+// Triangular solves: the n rows are cut into 64-row blocks, solved in order
+// (forward sweep L y = b, then backward sweep L^T x = y).  Block j needs
+// b_j - sum_i L(j, i) x_i over the blocks solved before it.  One persistent
+// workgroup (the solver) walks the blocks: it keeps the newest TRI_F solutions
+// in LDS, folds their tiles (held in registers, loaded one block ahead)
+// itself, adds the partial sum of all older blocks, and applies the
+// precomputed inverse of the diagonal block.  The older blocks are folded by
+// one helper workgroup per block, which takes each solved block as it appears
+// and hands its partial sum over when done.  The chain from one block to the
+// next therefore stays inside one workgroup; the helpers have TRI_F blocks of
+// the solver's time to deliver.
+//
+// Hand-over between workgroups goes through values, not flags: solved blocks
+// and partial sums are written with relaxed agent-scope atomic stores into an
+// area filled beforehand with a sentinel bit pattern (a NaN that is never
+// stored: NaN results are stored as the canonical quiet NaN), and a reader
+// polls each value with relaxed atomic loads until it is no longer the
+// sentinel.  Each value is its own flag, so no release fence is needed.  Every
+// wait is bounded: past the spin limit, or once another workgroup has recorded
+// an expired wait, the workgroup records the error and leaves.
 //
 // The binary64 residual R = B - A X reads tril(A) once per use of symmetry:
 // workgroups own (row block, chunk of column blocks) pairs and write partial
@@ -27,11 +38,12 @@ namespace ff {
 
 namespace {
 
-constexpr int TB = 64;          // row block of the triangular solves
-constexpr int RHS_CHUNK = 16;   // right-hand sides per launch
-constexpr int TP = TRISOLVE_TP; // workgroups per row block of a triangular solve
+constexpr int TB = TRI_TB;      // row block of the triangular solves
+constexpr int RHS_CHUNK = 16;   // right-hand sides per residual launch
+constexpr int RC = TRI_RC;      // right-hand sides per triangular sweep
+constexpr int NQ = RC / 4;      // columns a thread owns in the sweep's reductions (at most)
 constexpr int RCB = RESIDUAL_CB;// column blocks per residual workgroup
-constexpr int SPIN_LIMIT = 1 << 24;
+constexpr int SPIN_LIMIT = 1 << 20;
 
 template <typename S>
 __global__ void copy_lower_kernel(int n, const double* __restrict__ A, int64_t lda, S* __restrict__ W, int64_t ldw) {
@@ -47,14 +59,26 @@ __global__ void convert_kernel(int n, const double* __restrict__ B, int64_t ldb,
         X[i + (int64_t)j * ldx] = (S)B[i + (int64_t)j * ldb];
 }
 
-// Inverse of the 64 x 64 lower-triangular diagonal blocks of L, computed in
-// binary64 by column-wise forward substitution, stored in S (block b at
-// Linv + b*64*64, column-major, ld 64; entries above the diagonal are zero).
+// Per-factor data of the triangular solves: 64 x 64 tiles stored in the order
+// the solving workgroup's threads read them ("thread-major"): element (r, k)
+// at ((k / 16) * 64 + r) * 16 + k % 16, so thread (r, g) = (lane, wave) finds
+// row r, columns 16g..16g+15 as 16 contiguous values.  Tile index:
+//   [0, nblk)                       inverse of diagonal block j
+//   [nblk, 2 nblk)                  its transpose
+//   2 nblk + j F + f - 1            L(j, j - f)          (forward sweep), j >= f
+//   2 nblk + nblk F + j F + f - 1   L(j + f, j)^T        (backward sweep), j + f < nblk
+// with F = TRI_F, rows or columns past n zero.
+__device__ __forceinline__ int tm_index(int r, int k) { return ((k >> 4) * TB + r) * 16 + (k & 15); }
+
+// Inverses of the 64 x 64 lower-triangular diagonal blocks of L, computed in
+// binary64 by column-wise forward substitution and rounded to S (zero above
+// the diagonal and outside a short last block).
 template <typename S>
 __global__ __launch_bounds__(64)
-void inv_diag_kernel(int n, const S* __restrict__ L, int64_t ldl, S* __restrict__ Linv) {
+void inv_diag_kernel(int n, const S* __restrict__ L, int64_t ldl, S* __restrict__ fac) {
     __shared__ double x[TB][TB + 1];    // x[i][c]
     __shared__ double l[TB][TB + 1];    // l[i][k]
+    const int nblk = (n + TB - 1) / TB;
     const int b = blockIdx.x;
     const int r0 = b * TB;
     const int nb = min(TB, n - r0);
@@ -72,210 +96,428 @@ void inv_diag_kernel(int n, const S* __restrict__ L, int64_t ldl, S* __restrict_
         }
         x[i][c] = v;
     }
-    for (int i = 0; i < TB; ++i) Linv[(int64_t)b * TB * TB + i + (int64_t)c * TB] = (S)x[i][c];
+    __syncthreads();
+    S* inv = fac + (size_t)b * TB * TB;
+    S* invt = fac + ((size_t)nblk + b) * TB * TB;
+    for (int e = c; e < TB * TB; e += 64) {
+        const int tm = e >> 4, r = tm & (TB - 1), k = ((tm >> 6) << 4) | (e & 15);
+        inv[e] = (S)x[r][k];
+        invt[e] = (S)x[k][r];
+    }
 }
 
-// Spin on a relaxed load (an acquire load would invalidate the caches on every
-// iteration); callers issue one acquire fence after the flag is seen.
-__device__ __forceinline__ bool wait_flag(const int* f) {
+// The tiles the solving workgroup folds itself (blockIdx.z = 0: L(j, j - f) of
+// the forward sweep; 1: L(j + f, j)^T of the backward sweep), f = blockIdx.y + 1.
+template <typename S>
+__global__ __launch_bounds__(256)
+void near_tiles_kernel(int n, const S* __restrict__ L, int64_t ldl, S* __restrict__ fac) {
+    __shared__ S t[TB][TB + 1];
+    const int nblk = (n + TB - 1) / TB;
+    const int j = blockIdx.x, f = blockIdx.y + 1;
+    const bool back = blockIdx.z == 1;
+    const int i = back ? j + f : j - f;
+    if (i < 0 || i >= nblk) return;
+    // the tile's rows belong to block rb (possibly short), its columns to block cb (whole)
+    const int rb = back ? i : j, cb = back ? j : i;
+    const int r0 = rb * TB, c0 = cb * TB, nbr = min(TB, n - r0);
+    for (int e = threadIdx.x; e < TB * TB; e += 256) {
+        const int a = e % TB, c = e / TB;
+        t[a][c] = a < nbr ? L[(int64_t)(r0 + a) + (int64_t)(c0 + c) * ldl] : S(0);
+    }
+    __syncthreads();
+    S* out = fac + ((size_t)2 * nblk + (back ? (size_t)nblk * TRI_F : 0) + (size_t)j * TRI_F + f - 1) * TB * TB;
+    for (int e = threadIdx.x; e < TB * TB; e += 256) {
+        const int tm = e >> 4, r = tm & (TB - 1), k = ((tm >> 6) << 4) | (e & 15);
+        out[e] = back ? t[k][r] : t[r][k];
+    }
+}
+
+// 16 contiguous values of a thread-major tile (16-byte aligned), as vector loads.
+template <typename S>
+__device__ __forceinline__ void load16(const S* __restrict__ p, S (&v)[16]) {
+    if constexpr (sizeof(S) == 4) {
+        const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float4 w = q[u];
+            v[4 * u] = w.x; v[4 * u + 1] = w.y; v[4 * u + 2] = w.z; v[4 * u + 3] = w.w;
+        }
+    } else {
+        const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double2 w = q[u];
+            v[2 * u] = w.x; v[2 * u + 1] = w.y;
+        }
+    }
+}
+
+// Bit patterns of the hand-off area: SENT marks "not written yet"; a NaN
+// result is stored as QNAN so that no stored value equals SENT.
+template <typename S> struct PubBits;
+template <> struct PubBits<float> {
+    typedef unsigned int U;
+    static constexpr U SENT = 0xFFFFFFFFu;
+    static constexpr U QNAN = 0x7FC00000u;
+    static __device__ __forceinline__ U bits(float v) { return __float_as_uint(v); }
+    static __device__ __forceinline__ float val(U b) { return __uint_as_float(b); }
+};
+template <> struct PubBits<double> {
+    typedef unsigned long long U;
+    static constexpr U SENT = 0xFFFFFFFFFFFFFFFFull;
+    static constexpr U QNAN = 0x7FF8000000000000ull;
+    static __device__ __forceinline__ U bits(double v) { return (U)__double_as_longlong(v); }
+    static __device__ __forceinline__ double val(U b) { return __longlong_as_double((long long)b); }
+};
+
+template <typename S>
+__device__ __forceinline__ void pub_put(S* p, S v) {
+    using B = PubBits<S>;
+    typename B::U b = B::bits(v);
+    if (b == B::SENT) b = B::QNAN;
+    __hip_atomic_store(reinterpret_cast<typename B::U*>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename S>
+__device__ __forceinline__ typename PubBits<S>::U pub_peek(const S* p) {
+    using U = typename PubBits<S>::U;
+    return __hip_atomic_load(reinterpret_cast<U*>(const_cast<S*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Poll *p until it holds a published value; b holds the value last read.
+// False when the wait expired or another workgroup recorded an error.
+template <typename S>
+__device__ __forceinline__ bool pub_wait(const S* p, typename PubBits<S>::U& b, const int* err) {
     int spins = 0;
-    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    while (b == PubBits<S>::SENT) {
         if (++spins > SPIN_LIMIT) return false;
-        __builtin_amdgcn_s_sleep(2);
+        if ((spins & 127) == 0 &&
+            __hip_atomic_load(const_cast<int*>(err), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            return false;
+        __builtin_amdgcn_s_sleep(1);
+        b = pub_peek(p);
     }
     return true;
 }
 
-// Make this workgroup's global writes visible at agent scope, then set *f.  The
-// barrier orders every wave's writes before thread 0's release fence (which is
-// cumulative over them), so one fence, one L2 write-back, serves the
-// workgroup; the flag store after it may then be relaxed.
-__device__ __forceinline__ void publish(int* f) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+__device__ __forceinline__ void record_error(int* err, int* sh_bad) {
+    *sh_bad = 1;
+    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Row r of the 64 x 64 LDS tile t (column r of it for TRANS) times the columns
-// c = g + 4q of xv.  With nr <= 4 a thread has one live column (q = 0), whose
-// dependent chain is on the critical path of a block: it is summed as four
-// interleaved partial sums added in a fixed order.  With more columns each is a
-// plain sum over k, the columns giving the thread independent chains.  (So a
-// column's rounding depends on whether nr <= 4; results are deterministic for
-// a given nr.)
-template <bool TRANS, typename S>
-__device__ __forceinline__ void dots64(const S (&t)[TB][TB + 1], const S (&xv)[TB][RHS_CHUNK], int r, int g, int nr,
-                                       S (&out)[RHS_CHUNK / 4]) {
-    constexpr int NQ = RHS_CHUNK / 4;
-    if (nr <= 4) {
-        S s0 = S(0), s1 = S(0), s2 = S(0), s3 = S(0);
-#pragma unroll 4
-        for (int k = 0; k < TB; k += 4) {
-            if (!TRANS) {
-                s0 += t[r][k] * xv[k][g];
-                s1 += t[r][k + 1] * xv[k + 1][g];
-                s2 += t[r][k + 2] * xv[k + 2][g];
-                s3 += t[r][k + 3] * xv[k + 3][g];
-            } else {
-                s0 += t[k][r] * xv[k][g];
-                s1 += t[k + 1][r] * xv[k + 1][g];
-                s2 += t[k + 2][r] * xv[k + 2][g];
-                s3 += t[k + 3][r] * xv[k + 3][g];
-            }
-        }
-        out[0] = (s0 + s1) + (s2 + s3);
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) out[q] = S(0);
-        return;
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int c = g + 4 * q;
-        S sum = S(0);
-        if (!TRANS) { for (int k = 0; k < TB; ++k) sum += t[r][k] * xv[k][c]; }
-        else        { for (int k = 0; k < TB; ++k) sum += t[k][r] * xv[k][c]; }
-        out[q] = sum;
-    }
-}
+// LDS of the sweep kernel, shared by the two roles (elements of S):
+//   solver: ring[TRI_F][TB][RC] (newest solutions), red[4][TB][RC + 1], ys[TB][RC]
+//   helper: xs[2][TB][RC] (solved block), red[4][TB][RC + 1], stg[4][16][68]
+constexpr int RED_ELEMS = 4 * TB * (RC + 1);
+constexpr int SOLVER_ELEMS = TRI_F * TB * RC + RED_ELEMS + TB * RC;
+constexpr int HELPER_ELEMS = 2 * TB * RC + RED_ELEMS + 4 * 16 * 68;
+constexpr int SWEEP_LDS_ELEMS = SOLVER_ELEMS > HELPER_ELEMS ? SOLVER_ELEMS : HELPER_ELEMS;
 
-// Forward (TRANS = false: L y = b) or backward (TRANS = true: L^T x = y)
-// substitution on nr <= 16 columns of X in place.  fl: [0] ticket, [1] error
-// word, [2, 2 + nblk) block flags, then nblk * TP partial flags; all start at
-// zero.  parts: (TP - 1) partial sums of 64 x 16 per block.
-template <typename S, bool TRANS>
-__global__ __launch_bounds__(256)
-void trisolve_kernel(int n, int nr, const S* __restrict__ L, int64_t ldl, const S* __restrict__ Linv,
-                     S* X, int64_t ldx, int* fl, S* __restrict__ parts)
-{
-    __shared__ S tile[TB][TB + 1];
-    __shared__ S xv[TB][RHS_CHUNK];
-    __shared__ int sh_ticket, bad;
+// The solving workgroup of a sweep (forward: L y = b; TRANS: L^T x = y), all
+// blocks in sweep order jj (block j = jj, or nblk - 1 - jj backward).  Thread
+// (r, g) = (lane, wave) owns row r of a block and the quarter g of its inner
+// index (columns 16g..16g+15 of a tile); in the reductions it owns the
+// right-hand-side columns c = g + 4q.  NRC >= nr columns are computed.
+template <typename S, bool TRANS, int NRC>
+__device__ void tri_solver(int n, int nr, const S* __restrict__ L, int64_t ldl, const S* __restrict__ fac, S* X,
+                           int64_t ldx, S* xpub, const S* part, int* err, S* smem, int* sh_bad) {
+    constexpr int F = TRI_F;
+    constexpr int QN = (NRC + 3) / 4;   // column slots c = g + 4q that can hold a column
+    using U = typename PubBits<S>::U;
     const int nblk = (n + TB - 1) / TB;
-    int* const err = fl + 1;
-    int* const bflag = fl + 2;
-    int* const pflag = fl + 2 + nblk;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        sh_ticket = atomicAdd(&fl[0], 1);
-        bad = 0;
-    }
-    __syncthreads();
-    const int jj = sh_ticket / TP, p = sh_ticket % TP;   // jj blocks are solved before this one
-    const int j = TRANS ? (nblk - 1 - jj) : jj;
-    const int r0 = j * TB;
-    const int nbr = min(TB, n - r0);
-    const int r = tid % TB, g = tid / TB;
-    const bool fin = p == TP - 1;
-    S acc[RHS_CHUNK / 4];
+    const int tid = threadIdx.x, r = tid & (TB - 1), g = tid >> 6;
+    S (*ring)[TB][RC] = reinterpret_cast<S (*)[TB][RC]>(smem);
+    S (*red)[TB][RC + 1] = reinterpret_cast<S (*)[TB][RC + 1]>(smem + F * TB * RC);
+    S (*ys)[RC] = reinterpret_cast<S (*)[RC]>(smem + F * TB * RC + RED_ELEMS);
+    const S* inv = fac + (TRANS ? (size_t)nblk * TB * TB : 0);
+    const S* nearb = fac + ((size_t)2 * nblk + (TRANS ? (size_t)nblk * TRI_F : 0)) * TB * TB;
+
+    S T[F][16];     // fold tiles of the current block: distance f + 1, row r, inner quarter g
+    S V[16];        // inverse of the current diagonal block: row r, inner quarter g
+    S bq[QN];       // right-hand side (r, g + 4q) of the current block, as loaded
+    U pq[QN];       // older blocks' partial sum (r, g + 4q) of the current block, as loaded (SENT: not yet seen)
+
+    // Prefetches for block jj.  Each issues the same loads whatever jj, nr and
+    // the block's height (addresses clamped into the buffers), and keeps the
+    // raw values: masks are applied where the values are used, so the number of
+    // loads in flight does not depend on the path, nothing waits at issue, and
+    // each wait covers only the loads it needs.
+    auto load_fold = [&](int jj) {
+        const int jc = min(jj, nblk - 1);
+        const int j = TRANS ? nblk - 1 - jc : jc;
 #pragma unroll
-    for (int q = 0; q < RHS_CHUNK / 4; ++q) {
-        const int c = g + 4 * q;
-        acc[q] = (fin && r < nbr && c < nr) ? X[(int64_t)(r0 + r) + (int64_t)c * ldx] : S(0);
-    }
-    // Blocks folded here, by distance d from block j: the finisher takes d = 1,
-    // workgroup p < TP - 1 takes d = p + 2, p + 2 + (TP - 1), ... and walks them
-    // oldest first, so it works through the blocks already solved while the newer
-    // ones are still being solved.
-    const int dlo = fin ? 1 : p + 2;
-    const int d0 = fin ? 1 : (jj >= dlo ? dlo + (jj - dlo) / (TP - 1) * (TP - 1) : 0);
-    const int dstep = fin ? -(jj + 1) : -(TP - 1);
-    constexpr int NE = TB * TB / 256;
-    S tv[NE];
-    auto load_tile = [&](int d) {
-        const int i = TRANS ? j + d : j - d;
-        const int i0 = i * TB, nbi = min(TB, n - i0);
+        for (int f = 0; f < F; ++f) load16(nearb + ((size_t)j * F + f) * TB * TB + tid * 16, T[f]);
+    };
+    auto load_inv = [&](int jj) {
+        const int jc = min(jj, nblk - 1);
+        const int j = TRANS ? nblk - 1 - jc : jc;
+        load16(inv + (size_t)j * TB * TB + tid * 16, V);
+    };
+    auto load_rhs = [&](int jj) {
+        const int jc = min(jj, nblk - 1);
+        const int j = TRANS ? nblk - 1 - jc : jc;
+        const int j0 = j * TB, nbr = min(TB, n - j0);
+        const int rr = r < nbr ? r : 0;
 #pragma unroll
-        for (int u = 0; u < NE; ++u) {
-            const int e = tid + 256 * u;
-            const int a = e % TB, b = e / TB;    // a: row within the tile (contiguous), b: column
-            const bool in = !TRANS ? (a < nbr && b < nbi) : (a < nbi && b < nbr);
-            const int64_t off = !TRANS ? (int64_t)(r0 + a) + (int64_t)(i0 + b) * ldl
-                                       : (int64_t)(i0 + a) + (int64_t)(r0 + b) * ldl;
-            const S v = L[in ? off : 0];
-            tv[u] = in ? v : S(0);
+        for (int q = 0; q < QN; ++q) {
+            const int cc = g + 4 * q < nr ? g + 4 * q : 0;
+            bq[q] = X[(int64_t)(j0 + rr) + (int64_t)cc * ldx];
+            pq[q] = pub_peek(part + ((size_t)jc * TB + r) * RC + cc);
         }
     };
-    S* const mine = parts + ((int64_t)j * (TP - 1)) * TB * RHS_CHUNK;
-    S lv[NE];                                    // the finisher's inverse diagonal block, loaded early
-    if (fin) {
-        // partial sums first (their blocks were solved earlier), all flags at once
-        if (tid < TP - 1 && !wait_flag(&pflag[j * TP + tid])) bad = 1;
-        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __syncthreads();
-        if (bad) {
-            if (tid == 0) atomicExch(err, 1);
-            return;
-        }
-#pragma unroll
-        for (int pp = 0; pp < TP - 1; ++pp)
-#pragma unroll
-            for (int q = 0; q < RHS_CHUNK / 4; ++q) acc[q] += mine[(int64_t)pp * TB * RHS_CHUNK + r * RHS_CHUNK + g + 4 * q];
-#pragma unroll
-        for (int u = 0; u < NE; ++u) lv[u] = Linv[(int64_t)j * TB * TB + tid + 256 * u];
-    }
-    if (d0 >= dlo && d0 <= jj) load_tile(d0);
-    for (int d = d0; d >= dlo && d <= jj; d += dstep) {
-        const int i = TRANS ? j + d : j - d;
-        const int i0 = i * TB, nbi = min(TB, n - i0);
-#pragma unroll
-        for (int u = 0; u < NE; ++u) {
-            const int e = tid + 256 * u;
-            tile[e % TB][e / TB] = tv[u];
-        }
-        if (d + dstep >= dlo) load_tile(d + dstep);      // next tile in flight during this one
-        // one wave takes the acquire (the invalidation acts for the whole CU)
-        if (tid == 0 && !wait_flag(&bflag[i])) bad = 1;
-        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __syncthreads();
-        if (bad) {
-            if (tid == 0) atomicExch(err, 1);
-            return;
-        }
-        for (int e = tid; e < TB * RHS_CHUNK; e += 256) {
-            const int a = e % TB, c = e / TB;
-            xv[a][c] = (a < nbi && c < nr) ? X[(int64_t)(i0 + a) + (int64_t)c * ldx] : S(0);
-        }
-        __syncthreads();
+
+    // Each of the next block's prefetches is issued after the last use of its
+    // registers in this block: fold tiles after the fold, the inverse after the
+    // inverse, right-hand side and partial sum after the publish (by then the
+    // helper has had TRI_F - 1 blocks of time since its last source appeared).
+    load_fold(0);
+    load_inv(0);
+    load_rhs(0);
+    for (int jj = 0; jj < nblk; ++jj) {
+        const int j = TRANS ? nblk - 1 - jj : jj;
+        const int j0 = j * TB, nbr = min(TB, n - j0);
+        // 1. fold the newest solved blocks over this thread's inner quarter (one
+        //    column: four interleaved partial sums, added in a fixed order)
         {
-            S sum[RHS_CHUNK / 4];
-            dots64<TRANS>(tile, xv, r, g, nr, sum);
+            constexpr int NS = NRC == 1 ? 4 : 1;
+            S s[NS][NRC];
 #pragma unroll
-            for (int q = 0; q < RHS_CHUNK / 4; ++q)
-                if (g + 4 * q < nr) acc[q] -= sum[q];
+            for (int u = 0; u < NS; ++u)
+#pragma unroll
+                for (int c = 0; c < NRC; ++c) s[u][c] = S(0);
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                if (f < jj) {
+                    const int slot = (jj - 1 - f) % F;
+#pragma unroll
+                    for (int t = 0; t < 16; ++t) {
+                        const S tv = T[f][t];
+                        const S* xr = ring[slot][16 * g + t];
+#pragma unroll
+                        for (int c = 0; c < NRC; ++c) s[t % NS][c] += tv * xr[c];
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NRC; ++c) {
+                S v = s[0][c];
+                if constexpr (NS == 4) v = (s[0][c] + s[1][c]) + (s[2][c] + s[3][c]);
+                red[g][r][c] = v;
+            }
+        }
+        load_fold(jj + 1);
+        __syncthreads();
+        // 2. y = b - (older blocks) - (newest blocks) for the columns this thread owns
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int c = g + 4 * q;
+            if (c < NRC) {
+                S p = S(0);
+                if (jj > F && c < nr) {
+                    ok &= pub_wait(part + ((size_t)jj * TB + r) * RC + c, pq[q], err);
+                    p = PubBits<S>::val(pq[q]);
+                }
+                const S b = (c < nr && r < nbr) ? bq[q] : S(0);
+                ys[r][c] = b - p - ((red[0][r][c] + red[1][r][c]) + (red[2][r][c] + red[3][r][c]));
+            }
+        }
+        if (!ok) record_error(err, sh_bad);
+        __syncthreads();
+        if (*sh_bad) return;
+        // 3. x = (inverse of the diagonal block) y, over this thread's inner quarter
+        {
+            constexpr int NS = NRC == 1 ? 4 : 1;
+            S u[NS][NRC];
+#pragma unroll
+            for (int v = 0; v < NS; ++v)
+#pragma unroll
+                for (int c = 0; c < NRC; ++c) u[v][c] = S(0);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const S* yr = ys[16 * g + t];
+#pragma unroll
+                for (int c = 0; c < NRC; ++c) u[t % NS][c] += V[t] * yr[c];
+            }
+#pragma unroll
+            for (int c = 0; c < NRC; ++c) {
+                S v = u[0][c];
+                if constexpr (NS == 4) v = (u[0][c] + u[1][c]) + (u[2][c] + u[3][c]);
+                red[g][r][c] = v;
+            }
+        }
+        load_inv(jj + 1);
+        __syncthreads();
+        // 4. publish the solved block (the next block's right-hand side and
+        //    partial sum are requested first)
+        load_rhs(jj + 1);
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int c = g + 4 * q;
+            if (c < NRC) {
+                const S x = (red[0][r][c] + red[1][r][c]) + (red[2][r][c] + red[3][r][c]);
+                ring[jj % F][r][c] = x;
+                if (c < nr) {
+                    if (r < nbr) X[(int64_t)(j0 + r) + (int64_t)c * ldx] = x;
+                    pub_put(xpub + ((size_t)jj * TB + r) * RC + c, x);
+                }
+            }
         }
         __syncthreads();
     }
-    if (!fin) {
-#pragma unroll
-        for (int q = 0; q < RHS_CHUNK / 4; ++q) mine[(int64_t)p * TB * RHS_CHUNK + r * RHS_CHUNK + g + 4 * q] = acc[q];
-        publish(&pflag[j * TP + p]);
-        return;
-    }
-    // apply the inverse diagonal block (column-major, ld 64)
-#pragma unroll
-    for (int u = 0; u < NE; ++u) {
-        const int e = tid + 256 * u;
-        tile[e % TB][e / TB] = lv[u];
-    }
-#pragma unroll
-    for (int q = 0; q < RHS_CHUNK / 4; ++q) xv[r][g + 4 * q] = acc[q];
-    __syncthreads();
-    {
-        S sum[RHS_CHUNK / 4];
-        dots64<TRANS>(tile, xv, r, g, nr, sum);
-#pragma unroll
-        for (int q = 0; q < RHS_CHUNK / 4; ++q) {
-            const int c = g + 4 * q;
-            if (c < nr && r < nbr) X[(int64_t)(r0 + r) + (int64_t)c * ldx] = sum[q];
-        }
-    }
-    publish(&bflag[j]);
 }
 
-__global__ void fill_int_kernel(int* p, int count, int v) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = v;
+// A helper workgroup: the partial sum over the blocks at distance > TRI_F from
+// block jj (sweep order), taken oldest first as they are published.
+template <typename S, bool TRANS, int NRC>
+__device__ void tri_helper(int jj, int n, int nr, const S* __restrict__ L, int64_t ldl, const S* xpub, S* part,
+                           int* err, S* smem, int* sh_bad) {
+    constexpr int F = TRI_F;
+    constexpr int QN = (NRC + 3) / 4;
+    using U = typename PubBits<S>::U;
+    const int nblk = (n + TB - 1) / TB;
+    const int tid = threadIdx.x, r = tid & (TB - 1), g = tid >> 6;
+    S (*xs)[TB][RC] = reinterpret_cast<S (*)[TB][RC]>(smem);
+    S (*red)[TB][RC + 1] = reinterpret_cast<S (*)[TB][RC + 1]>(smem + 2 * TB * RC);
+    S (*stg)[16][68] = reinterpret_cast<S (*)[16][68]>(smem + 2 * TB * RC + RED_ELEMS);
+    const int j = TRANS ? nblk - 1 - jj : jj;
+    const int j0 = j * TB, nbr = min(TB, n - j0);
+    const int nsrc = jj - F;        // sources ii = 0 .. nsrc - 1
+    S acc[NRC];
+#pragma unroll
+    for (int c = 0; c < NRC; ++c) acc[c] = S(0);
+    S Tn[16], Tc[16];
+    // Tile of source ii as loaded: (r, g) layout forward; backward a 16-row slab
+    // of L(i, j) per wave, lane (a, cb) = (r & 15, r >> 4) holding row a and
+    // columns cb + 4u, turned into (r, g) layout through the wave's own LDS.
+    auto load_tile = [&](int ii) {
+        if (!TRANS) {
+            const int i0 = ii * TB;
+            const S* src = L + (int64_t)(j0 + (r < nbr ? r : 0)) + (int64_t)(i0 + 16 * g) * ldl;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const S v = src[(int64_t)t * ldl];
+                Tn[t] = r < nbr ? v : S(0);
+            }
+        } else {
+            const int i = nblk - 1 - ii, i0 = i * TB, nbi = min(TB, n - i0);
+            const int a = r & 15, cb = r >> 4;
+            const bool in = 16 * g + a < nbi;
+            const S* src = L + (int64_t)(i0 + (in ? 16 * g + a : 0)) + (int64_t)(j0 + cb) * ldl;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const S v = src[(int64_t)(4 * u) * ldl];
+                Tn[u] = in ? v : S(0);
+            }
+        }
+    };
+    auto settle_tile = [&]() {
+        if (!TRANS) {
+#pragma unroll
+            for (int t = 0; t < 16; ++t) Tc[t] = Tn[t];
+        } else {
+            const int a = r & 15, cb = r >> 4;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) stg[g][a][cb + 4 * u] = Tn[u];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = 0; t < 16; ++t) Tc[t] = stg[g][t][r];
+            __builtin_amdgcn_wave_barrier();
+        }
+    };
+    load_tile(0);
+    for (int ii = 0; ii < nsrc; ++ii) {
+        settle_tile();
+        if (ii + 1 < nsrc) load_tile(ii + 1);
+        S (*xb)[RC] = xs[ii & 1];
+        bool ok = true;
+        U b[QN];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int c = g + 4 * q;
+            b[q] = (c < NRC && c < nr) ? pub_peek(xpub + ((size_t)ii * TB + r) * RC + c) : PubBits<S>::bits(S(0));
+        }
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int c = g + 4 * q;
+            if (c < NRC) {
+                if (c < nr) ok &= pub_wait(xpub + ((size_t)ii * TB + r) * RC + c, b[q], err);
+                xb[r][c] = PubBits<S>::val(b[q]);
+            }
+        }
+        if (!ok) record_error(err, sh_bad);
+        __syncthreads();
+        if (*sh_bad) return;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const S tv = Tc[t];
+            const S* xr = xb[16 * g + t];
+#pragma unroll
+            for (int c = 0; c < NRC; ++c) acc[c] += tv * xr[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NRC; ++c) red[g][r][c] = acc[c];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+        const int c = g + 4 * q;
+        if (c < NRC && c < nr)
+            pub_put(part + ((size_t)jj * TB + r) * RC + c,
+                    (red[0][r][c] + red[1][r][c]) + (red[2][r][c] + red[3][r][c]));
+    }
+}
+
+// One sweep over nr <= RC right-hand sides (X in place).  Workgroup tickets in
+// start order: ticket 0 is the solver, ticket t >= 1 the helper of block
+// TRI_F + t.  pub: solved blocks (nblk*64 x RC) then partial sums (nblk*64 x
+// RC), all SENT on entry.
+template <typename S, bool TRANS, int NRC>
+__global__ __launch_bounds__(256)
+void trisolve_kernel(int n, int nr, const S* __restrict__ L, int64_t ldl, const S* __restrict__ fac, S* X,
+                     int64_t ldx, S* pub, int* err, int* ticket)
+{
+    __shared__ S smem[SWEEP_LDS_ELEMS];
+    __shared__ int sh_ticket, sh_bad;
+    if (threadIdx.x == 0) {
+        sh_ticket = atomicAdd(ticket, 1);
+        sh_bad = 0;
+    }
+    __syncthreads();
+    const int nblk = (n + TB - 1) / TB;
+    S* xpub = pub;
+    S* part = pub + (size_t)nblk * TB * RC;
+    if (sh_ticket == 0)
+        tri_solver<S, TRANS, NRC>(n, nr, L, ldl, fac, X, ldx, xpub, part, err, smem, &sh_bad);
+    else
+        tri_helper<S, TRANS, NRC>(TRI_F + sh_ticket, n, nr, L, ldl, xpub, part, err, smem, &sh_bad);
+}
+
+// Fill the hand-off area with SENT and clear the two sweep tickets.
+template <typename S>
+__global__ void pub_reset_kernel(S* pub, size_t count, int* tickets) {
+    using U = typename PubBits<S>::U;
+    U* q = reinterpret_cast<U*>(pub);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        q[i] = PubBits<S>::SENT;
+    if (blockIdx.x == 0 && threadIdx.x < 2) tickets[threadIdx.x] = 0;
+}
+
+template <typename S, bool TRANS>
+hipError_t launch_sweep(int n, int nr, const S* L, int64_t ldl, const S* fac, S* X, int64_t ldx, S* pub, int* err,
+                        int* ticket, hipStream_t st) {
+    const int nblk = (n + TB - 1) / TB;
+    const dim3 grid(1 + std::max(0, nblk - TRI_F - 1));
+    if (nr == 1)
+        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, 1>), grid, dim3(256), 0, st, n, nr, L, ldl, fac, X, ldx, pub,
+                           err, ticket);
+    else if (nr <= 4)
+        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, 4>), grid, dim3(256), 0, st, n, nr, L, ldl, fac, X, ldx, pub,
+                           err, ticket);
+    else
+        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, RC>), grid, dim3(256), 0, st, n, nr, L, ldl, fac, X, ldx, pub,
+                           err, ticket);
+    return hipGetLastError();
 }
 
 // Partial products of R = B - A X in binary64 with A symmetric, only tril(A)
@@ -503,34 +745,34 @@ hipError_t launch_convert_from_f64(int n, int nrhs, const double* B, int64_t ldb
 }
 
 template <typename S>
-hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, S* Linv, int* flags,
-                         S* parts, bool make_inverses, hipStream_t st) {
+hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, const TriWs<S>& w,
+                         bool make_fac, hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
-    const int nblk = (n + TB - 1) / TB;
-    if (make_inverses) {
-        hipLaunchKernelGGL((inv_diag_kernel<S>), dim3(nblk), dim3(64), 0, st, n, L, ldl, Linv);
+    const int nblk = trisolve_nblk(n);
+    if (make_fac) {
+        hipLaunchKernelGGL((inv_diag_kernel<S>), dim3(nblk), dim3(64), 0, st, n, L, ldl, w.fac);
+        if (nblk > 1)
+            hipLaunchKernelGGL((near_tiles_kernel<S>), dim3(nblk, TRI_F, 2), dim3(256), 0, st, n, L, ldl, w.fac);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int per = (int)trisolve_sweep_ints(n);
-    for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
-        const int nr = (nrhs - c0 < RHS_CHUNK) ? nrhs - c0 : RHS_CHUNK;
+    const size_t all = trisolve_pub_elems(n);
+    const size_t sweep = all / 2;
+    const int rgrid = (int)std::min<size_t>(1024, (all + 255) / 256);
+    for (int c0 = 0; c0 < nrhs; c0 += RC) {
+        const int nr = std::min(RC, nrhs - c0);
         S* Xc = X + (int64_t)c0 * ldx;
-        hipLaunchKernelGGL(fill_int_kernel, dim3(std::min(64, (2 * per + 255) / 256)), dim3(256), 0, st, flags,
-                           2 * per, 0);
-        hipLaunchKernelGGL((trisolve_kernel<S, false>), dim3(nblk * TP), dim3(256), 0, st, n, nr, L, ldl, Linv, Xc,
-                           ldx, flags, parts);
-        hipLaunchKernelGGL((trisolve_kernel<S, true>), dim3(nblk * TP), dim3(256), 0, st, n, nr, L, ldl, Linv, Xc,
-                           ldx, flags + per, parts);
-        hipError_t e = hipGetLastError();
+        hipLaunchKernelGGL((pub_reset_kernel<S>), dim3(rgrid), dim3(256), 0, st, w.pub, all, w.ctl + 1);
+        hipError_t e = launch_sweep<S, false>(n, nr, L, ldl, w.fac, Xc, ldx, w.pub, w.ctl, w.ctl + 1, st);
+        if (e == hipSuccess) e = launch_sweep<S, true>(n, nr, L, ldl, w.fac, Xc, ldx, w.pub + sweep, w.ctl, w.ctl + 2, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-template hipError_t trisolve_impl<double>(int, int, const double*, int64_t, double*, int64_t, double*, int*, double*, bool,
-                                          hipStream_t);
-template hipError_t trisolve_impl<float>(int, int, const float*, int64_t, float*, int64_t, float*, int*, float*, bool,
+template hipError_t trisolve_impl<double>(int, int, const double*, int64_t, double*, int64_t, const TriWs<double>&,
+                                          bool, hipStream_t);
+template hipError_t trisolve_impl<float>(int, int, const float*, int64_t, float*, int64_t, const TriWs<float>&, bool,
                                          hipStream_t);
 
 hipError_t launch_residual_f64(int n, int nrhs, const double* A, int64_t lda, const double* X, int64_t ldx,
