@@ -91,7 +91,8 @@ enum {
 enum {
     FF_ERR_HIP = -100,
     FF_ERR_WORKSPACE = -101,
-    FF_ERR_UNSUPPORTED = -102
+    FF_ERR_UNSUPPORTED = -102,
+    FF_ERR_SCRATCH = -103   /* larger than the static scratch of chol_trisolve_noalloc */
 };
 
 const char *ff_status_string(int code);
@@ -193,6 +194,26 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double *A64, int64_t ld
 size_t ff_trisolve_workspace_size(int64_t n, int dtype);
 int chol_trisolve(int64_t n, int64_t nrhs, const void *L, int64_t ldl, int dtype,
                   void *X, int64_t ldx, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * chol_trisolve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same solve, with its workspace in a static device array of
+ * FF_NOALLOC_SCRATCH_BYTES bytes that the library holds on every device it
+ * runs on until the process ends.  No allocation of any kind is made.
+ *   Arguments as chol_trisolve, without the workspace;
+ *   d_status  device int32 or NULL: receives the error word (0, or nonzero if
+ *             a bounded wait expired and X is unspecified).
+ * Returns FF_ERR_SCRATCH when ff_trisolve_workspace_size(n, dtype) exceeds
+ * FF_NOALLOC_SCRATCH_BYTES (binary64: n <= 9344; binary32: n <= 18688).
+ * Every call on one device uses that device's one array, which keeps the last
+ * call's contents (everything the solve needs is rewritten at its start):
+ * calls that overlap on one device (different streams or host threads) race
+ * and give wrong results; serialise them.
+ */
+#define FF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int chol_trisolve_noalloc(int64_t n, int64_t nrhs, const void *L, int64_t ldl, int dtype,
+                          void *X, int64_t ldx, int32_t *d_status, void *stream);
 
 /*
  * The deferred update on its own (Sec. 2: S = R R^T, then A -= S over the

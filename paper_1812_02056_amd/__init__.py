@@ -6,7 +6,7 @@ include/fastfact.h); `binding` marshals torch tensors to it.  The API names are
 the C entry points: chol_factor, lu_nopiv_factor, chol_solve, chol_trisolve,
 update_syrk, update_gemm.
 """
-_API = ("chol_factor", "lu_nopiv_factor", "chol_solve", "chol_trisolve", "update_syrk", "update_gemm",
+_API = ("chol_factor", "lu_nopiv_factor", "chol_solve", "chol_trisolve", "chol_trisolve_noalloc", "update_syrk", "update_gemm",
         "chol_workspace_size", "solve_workspace_size", "trisolve_workspace_size", "status_string", "version", "to_device",
         "colmajor_empty", "FastFactError", "load", "update_profile_enable", "update_profile_read", "Server")
 

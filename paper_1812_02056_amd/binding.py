@@ -24,7 +24,7 @@ F64, F32, BF16 = 0, 1, 2
 FLAG_STRASSEN1 = 1
 FLAG_NO_LOOKAHEAD = 2
 FLAG_FIXED_STEP = 4
-ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED = -100, -101, -102
+ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_SCRATCH = -100, -101, -102, -103
 
 _DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
 _STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
@@ -33,7 +33,7 @@ _STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
 EXPORTED = (
     "ff_status_string", "ff_version", "ff_chol_workspace_size", "chol_factor",
     "ff_lu_workspace_size", "lu_nopiv_factor", "ff_solve_workspace_size", "chol_solve",
-    "ff_trisolve_workspace_size", "chol_trisolve", "ff_update_syrk", "ff_update_gemm",
+    "ff_trisolve_workspace_size", "chol_trisolve", "chol_trisolve_noalloc", "ff_update_syrk", "ff_update_gemm",
     "ff_update_profile_enable", "ff_update_profile_read",
     "ff_server_create", "ff_server_destroy", "ff_server_submit", "ff_server_step", "ff_server_poll",
     "ff_server_get_stats",
@@ -105,6 +105,8 @@ def load():
     lib.ff_trisolve_workspace_size.restype = sz
     lib.chol_trisolve.argtypes = [i64, i64, vp, i64, i32, vp, i64, vp, sz, vp]
     lib.chol_trisolve.restype = i32
+    lib.chol_trisolve_noalloc.argtypes = [i64, i64, vp, i64, i32, vp, i64, vp, vp]
+    lib.chol_trisolve_noalloc.restype = i32
     lib.ff_update_syrk.argtypes = [i64, i64, vp, i64, vp, i64, i32, u32, vp]
     lib.ff_update_syrk.restype = i32
     lib.ff_update_gemm.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, i32, u32, vp]
@@ -292,6 +294,16 @@ def chol_trisolve(L: torch.Tensor, X: torch.Tensor, dtype="f64", stream=None, ws
     rc = lib.chol_trisolve(n, int(X.shape[1]), _ptr(L), _ld(L, "L"), dt, _ptr(X), _ld(X, "X"),
                            _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream))
     _check(rc, "chol_trisolve")
+    return X
+
+
+def chol_trisolve_noalloc(L: torch.Tensor, X: torch.Tensor, dtype="f64", status: torch.Tensor | None = None,
+                          stream=None):
+    """chol_trisolve with the library's static device scratch (no allocation
+    anywhere).  status: optional device int32 tensor receiving the error word."""
+    rc = load().chol_trisolve_noalloc(int(L.shape[0]), int(X.shape[1]), _ptr(L), _ld(L, "L"), _dt(dtype), _ptr(X),
+                                      _ld(X, "X"), _ptr(status), _stream(stream))
+    _check(rc, "chol_trisolve_noalloc")
     return X
 
 

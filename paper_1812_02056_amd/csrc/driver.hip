@@ -13,6 +13,9 @@
 #include "fastfact.h"
 #include "internal.hpp"
 
+// Device scratch of the allocation-free entry point (see noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[FF_NOALLOC_SCRATCH_BYTES];
+
 namespace ff {
 namespace {
 
@@ -782,6 +785,27 @@ int trisolve_entry(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtyp
     return e == hipSuccess ? 0 : FF_ERR_HIP;
 }
 
+// Scratch of chol_trisolve_noalloc: a file-scope device array (one copy per
+// device, held until the process ends).  Host code never passes `scratch`
+// itself to a kernel: its device address is taken once per device with
+// hipGetSymbolAddress and kept in noalloc_scratch_ptr.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)FF_NOALLOC_SCRATCH_BYTES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+void* noalloc_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+int noalloc_scratch(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return FF_ERR_HIP;
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (noalloc_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return FF_ERR_HIP;
+        noalloc_scratch_ptr[dev] = p;
+    }
+    *out = noalloc_scratch_ptr[dev];
+    return 0;
+}
 }  // namespace
 }  // namespace ff
 
@@ -795,6 +819,7 @@ const char* ff_status_string(int code) {
         case FF_ERR_HIP: return "HIP runtime error";
         case FF_ERR_WORKSPACE: return "workspace too small";
         case FF_ERR_UNSUPPORTED: return "unsupported argument combination";
+        case FF_ERR_SCRATCH: return "problem larger than the static scratch of the allocation-free entry point";
         default: break;
     }
     if (code < 0 && code > -100) return "invalid argument (index = -code)";
@@ -908,6 +933,30 @@ int chol_trisolve(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtype
     if (n == 0 || nrhs == 0) return 0;
     if (ws == nullptr || ws_bytes < ff_trisolve_workspace_size(n, dtype)) return FF_ERR_WORKSPACE;
     return trisolve_entry(n, nrhs, L, ldl, dtype, X, ldx, ws, static_cast<hipStream_t>(stream));
+}
+
+int chol_trisolve_noalloc(int64_t n, int64_t nrhs, const void* L, int64_t ldl, int dtype, void* X, int64_t ldx,
+                          int32_t* d_status, void* stream) {
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return -1;
+    if (nrhs < 0) return -2;
+    if (n > 0 && L == nullptr) return -3;
+    if (ldl < std::max<int64_t>(1, n)) return -4;
+    if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -5;
+    if (n > 0 && nrhs > 0 && X == nullptr) return -6;
+    if (ldx < std::max<int64_t>(1, n)) return -7;
+    if (ff_trisolve_workspace_size(n, dtype) > NOALLOC_SCRATCH_BYTES) return FF_ERR_SCRATCH;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0 || nrhs == 0) {
+        if (d_status != nullptr && launch_set_int(d_status, 0, st) != hipSuccess) return FF_ERR_HIP;
+        return 0;
+    }
+    void* ws = nullptr;
+    int rc = noalloc_scratch(&ws);
+    if (rc) return rc;
+    rc = trisolve_entry(n, nrhs, L, ldl, dtype, X, ldx, ws, st);
+    if (rc == 0 && d_status != nullptr && launch_copy_int(static_cast<const int*>(ws), d_status, st) != hipSuccess)
+        return FF_ERR_HIP;
+    return rc;
 }
 
 int ff_update_syrk(int64_t m, int64_t w, void* C, int64_t ldc, const void* P, int64_t ldp, int dtype, unsigned flags,

@@ -15,6 +15,7 @@ constexpr int LU_LDS_MAX = 128;
 constexpr int TRSM_MAX = 192;
 
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
+hipError_t launch_copy_int(const int* src, int* dst, hipStream_t st);
 
 // Trailing updates (update.hip).
 // C(i, j) -= sum_k X(i, k) Y(j, k) for i < M, j < N; X column-major M x K;

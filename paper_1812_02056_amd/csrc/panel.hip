@@ -25,6 +25,7 @@ namespace ff {
 namespace {
 
 __global__ void set_int_kernel(int* p, int v) { if (threadIdx.x == 0) *p = v; }
+__global__ void copy_int_kernel(const int* src, int* dst) { if (threadIdx.x == 0) *dst = *src; }
 
 // value of v in lane l (l uniform across the wave)
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -648,6 +649,11 @@ void trsm_grouped_kernel(const GroupTrsm* __restrict__ jobs, int njobs)
 
 hipError_t launch_set_int(int* p, int v, hipStream_t st) {
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, st, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_int(const int* src, int* dst, hipStream_t st) {
+    hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(64), 0, st, src, dst);
     return hipGetLastError();
 }
 

@@ -98,3 +98,18 @@ def test_kernel_profile_layout_matches_the_header():
     fields = re.findall(r"(int64_t|double)\s+(\w+);", body)
     ctype = {"int64_t": ctypes.c_int64, "double": ctypes.c_double}
     assert [(n, ctype[t]) for t, n in fields] == list(binding.KernelProfile._fields_)
+
+
+def test_noalloc_rejects_sizes_beyond_its_scratch(lib):
+    # the size check runs on the host before any device work: the pointers are
+    # never dereferenced
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    assert lib.ff_trisolve_workspace_size(9344, 0) <= 32 << 20 < lib.ff_trisolve_workspace_size(9345, 0)
+    assert lib.ff_trisolve_workspace_size(18688, 1) <= 32 << 20 < lib.ff_trisolve_workspace_size(18689, 1)
+    assert lib.chol_trisolve_noalloc(9345, 1, fake, 9345, 0, fake, 9345, null, null) == -103
+    assert lib.chol_trisolve_noalloc(18689, 1, fake, 18689, 1, fake, 18689, null, null) == -103
+    assert lib.chol_trisolve_noalloc(-1, 1, fake, 1, 0, fake, 1, null, null) == -1
+    assert lib.chol_trisolve_noalloc(8, 1, fake, 7, 0, fake, 8, null, null) == -4
+    from paper_1812_02056_amd import binding
+    assert "static scratch" in binding.status_string(-103)
