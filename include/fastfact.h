@@ -77,6 +77,13 @@ enum {
                                       min(1536, n/4) columns are factored in
                                       order on `stream`.  Both schedules give
                                       bitwise identical factors. */
+    FF_FLAG_ESCALATE = 1u << 3,     /* chol_solve only: when the factor in the
+                                      requested precision fails (info > 0) or
+                                      its refinement ends neither converged nor
+                                      at a backward error <= tol, factor A again
+                                      in the next precision (bfloat16 ->
+                                      binary32 -> binary64) and refine with
+                                      that; see chol_solve. */
     FF_FLAG_FIXED_STEP = 1u << 2    /* every block exactly s columns wide (the
                                       step of Sec. 2 Algorithms 1 and 2
                                       verbatim).  Without it, the first block
@@ -139,16 +146,21 @@ int lu_nopiv_factor(int64_t n, int64_t s, void *A, int64_t lda, int dtype, unsig
 
 /* Outcome of chol_solve (host struct). */
 typedef struct {
-    int32_t info;          /* factorisation info (0 = ok), as d_info above */
-    int32_t iters;         /* refinement iterations performed */
+    int32_t info;          /* info of the factorisation that produced X (0 = ok), as d_info above */
+    int32_t iters;         /* refinement iterations performed with that factor */
     int32_t converged;     /* 1 if the correction test was met */
-    int32_t dtype_used;    /* update precision of the factor that was used */
+    int32_t dtype_used;    /* update precision of the factor that produced X */
     double last_correction;/* ||dX||_inf / ||X||_inf of the last iteration */
     double backward_err;   /* max_j ||b_j - A x_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf) */
+    int32_t escalated_to;  /* -1, or (with FF_FLAG_ESCALATE) the ff_dtype escalated to (== dtype_used) */
+    int32_t escalations;   /* refactorisations after the first */
+    int32_t total_iters;   /* refinement iterations over all factors tried */
+    int32_t first_info;    /* info of the factorisation in the requested precision */
 } ff_solve_info;
 
 /*
- * Solve A X = B for SPD A with mixed-precision iterative refinement.
+ * Solve A X = B for SPD A (solving linear systems being the use of the
+ * factorisation, Introduction) with mixed-precision iterative refinement.
  *   A64   n x n binary64 SPD matrix (lower triangle read, never written)
  *   W     n x n working factor in `dtype` storage (double* for FF_F64, float*
  *         otherwise), leading dimension ldw.  If w_is_factored == 0 the call
@@ -161,14 +173,24 @@ typedef struct {
  *         all columns); also on stagnation (the correction shrank by less
  *         than half) or after max_iter iterations.  max_iter = 0 returns the
  *         plain triangular-solve result.
- *   ws    device workspace, >= ff_solve_workspace_size(n, s, nrhs, dtype)
+ *   flags FF_FLAG_* of the factorisations, plus FF_FLAG_ESCALATE: a result
+ *         is accepted when the correction test was met, or when refinement
+ *         stopped with backward error <= tol (the accuracy the conditioning
+ *         allows); otherwise, or when the factorisation failed, A64 is
+ *         factored again in the next precision (bfloat16 -> binary32, in W;
+ *         binary32 -> binary64, in the workspace) and refined again.  out
+ *         then describes the last attempt; escalated_to, escalations,
+ *         total_iters and first_info record the way there.
+ *   ws    device workspace, >= ff_solve_workspace_size(n, s, nrhs, dtype,
+ *         flags) (with FF_FLAG_ESCALATE and float storage it includes an n x n
+ *         binary64 factor)
  *   out   host pointer, filled on return.
  * The residual B - A X and the update X += dX are binary64; the triangular
  * solves with W run in W's storage precision.  This call SYNCHRONISES `stream`
  * (the stop test runs on the host) and returns 0 even if refinement did not
  * converge (out->converged = 0) or the factorisation failed (out->info > 0).
  */
-size_t ff_solve_workspace_size(int64_t n, int64_t s, int64_t nrhs, int dtype);
+size_t ff_solve_workspace_size(int64_t n, int64_t s, int64_t nrhs, int dtype, unsigned flags);
 int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double *A64, int64_t lda,
                void *W, int64_t ldw, int dtype, unsigned flags, int w_is_factored,
                const double *B, int64_t ldb, double *X, int64_t ldx,

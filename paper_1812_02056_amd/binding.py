@@ -24,6 +24,7 @@ F64, F32, BF16 = 0, 1, 2
 FLAG_STRASSEN1 = 1
 FLAG_NO_LOOKAHEAD = 2
 FLAG_FIXED_STEP = 4
+FLAG_ESCALATE = 8
 ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_SCRATCH = -100, -101, -102, -103
 
 _DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
@@ -60,7 +61,8 @@ class KernelProfile(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("info", ctypes.c_int32), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("dtype_used", ctypes.c_int32), ("last_correction", ctypes.c_double),
-                ("backward_err", ctypes.c_double)]
+                ("backward_err", ctypes.c_double), ("escalated_to", ctypes.c_int32),
+                ("escalations", ctypes.c_int32), ("total_iters", ctypes.c_int32), ("first_info", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,7 +98,7 @@ def load():
     lib.ff_lu_workspace_size.restype = sz
     lib.lu_nopiv_factor.argtypes = [i64, i64, vp, i64, i32, u32, vp, sz, vp, vp]
     lib.lu_nopiv_factor.restype = i32
-    lib.ff_solve_workspace_size.argtypes = [i64, i64, i64, i32]
+    lib.ff_solve_workspace_size.argtypes = [i64, i64, i64, i32, u32]
     lib.ff_solve_workspace_size.restype = sz
     lib.chol_solve.argtypes = [i64, i64, i64, vp, i64, vp, i64, i32, u32, i32, vp, i64, vp, i64,
                                dbl, i32, vp, sz, vp, ctypes.POINTER(SolveInfo)]
@@ -249,19 +251,22 @@ def lu_nopiv_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_loo
     return info
 
 
-def solve_workspace_size(n: int, s: int, nrhs: int, dtype="f64") -> int:
-    return int(load().ff_solve_workspace_size(n, s, nrhs, _dt(dtype)))
+def solve_workspace_size(n: int, s: int, nrhs: int, dtype="f64", escalate=False) -> int:
+    return int(load().ff_solve_workspace_size(n, s, nrhs, _dt(dtype), FLAG_ESCALATE if escalate else 0))
 
 
 def chol_solve(A64: torch.Tensor, B: torch.Tensor, s: int, dtype="f32", W: torch.Tensor | None = None,
                w_is_factored=False, X: torch.Tensor | None = None, tol=1e-13, max_iter=50, strassen=False,
-               stream=None, ws: torch.Tensor | None = None):
-    """Solve A64 X = B with a factor W in `dtype` and binary64 refinement.
+               stream=None, ws: torch.Tensor | None = None, escalate=False, no_lookahead=False):
+    """Solve A64 X = B with a factor W in `dtype` and binary64 refinement
+    (escalate: refactor in higher precision when that fails, FF_FLAG_ESCALATE).
     Returns (X, W, info dict).  Synchronises the stream."""
     lib = load()
     dt = _dt(dtype)
     n = int(A64.shape[0])
     nrhs = int(B.shape[1])
+    flags = ((FLAG_STRASSEN1 if strassen else 0) | (FLAG_ESCALATE if escalate else 0)
+             | (FLAG_NO_LOOKAHEAD if no_lookahead else 0))
     if W is None:
         if w_is_factored:
             raise ValueError("w_is_factored requires W")
@@ -269,12 +274,11 @@ def chol_solve(A64: torch.Tensor, B: torch.Tensor, s: int, dtype="f32", W: torch
     if X is None:
         X = colmajor_empty(n, nrhs, torch.float64, A64.device)
     if ws is None:
-        ws = _workspace(int(lib.ff_solve_workspace_size(n, s, nrhs, dt)), A64.device)
+        ws = _workspace(int(lib.ff_solve_workspace_size(n, s, nrhs, dt, flags)), A64.device)
     out = SolveInfo()
-    rc = lib.chol_solve(n, s, nrhs, _ptr(A64), _ld(A64, "A64"), _ptr(W), _ld(W, "W"), dt,
-                        FLAG_STRASSEN1 if strassen else 0, 1 if w_is_factored else 0,
-                        _ptr(B), _ld(B, "B"), _ptr(X), _ld(X, "X"), float(tol), int(max_iter),
-                        _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream), ctypes.byref(out))
+    rc = lib.chol_solve(n, s, nrhs, _ptr(A64), _ld(A64, "A64"), _ptr(W), _ld(W, "W"), dt, flags,
+                        1 if w_is_factored else 0, _ptr(B), _ld(B, "B"), _ptr(X), _ld(X, "X"), float(tol),
+                        int(max_iter), _ptr(ws), 0 if ws is None else ws.numel(), _stream(stream), ctypes.byref(out))
     _check(rc, "chol_solve")
     return X, W, out.as_dict()
 

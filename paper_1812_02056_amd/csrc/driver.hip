@@ -873,10 +873,14 @@ int lu_nopiv_factor(int64_t n, int64_t s, void* A, int64_t lda, int dtype, unsig
     return lu_blocked((int)n, si, static_cast<double*>(A), lda, flags, d_info, 0, st);
 }
 
-size_t ff_solve_workspace_size(int64_t n, int64_t s, int64_t nrhs, int dtype) {
+size_t ff_solve_workspace_size(int64_t n, int64_t s, int64_t nrhs, int dtype, unsigned flags) {
     if (n <= 0 || nrhs <= 0 || s < 1) return 0;
     if (dtype == FF_F64) return carve_solve<double>(nullptr, n, s, nrhs, dtype).bytes;
-    return carve_solve<float>(nullptr, n, s, nrhs, dtype).bytes;
+    size_t bytes = carve_solve<float>(nullptr, n, s, nrhs, dtype).bytes;
+    if (flags & FF_FLAG_ESCALATE)
+        bytes += align_up((size_t)n * (size_t)n * sizeof(double)) +
+                 carve_solve<double>(nullptr, n, s, nrhs, FF_F64).bytes;
+    return bytes;
 }
 
 int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t lda, void* W, int64_t ldw, int dtype,
@@ -890,7 +894,8 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t ld
     if (n > 0 && W == nullptr) return -6;
     if (ldw < std::max<int64_t>(1, n)) return -7;
     if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -8;
-    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP)) return -9;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP | FF_FLAG_ESCALATE))
+        return -9;
     if (n > 0 && nrhs > 0 && B == nullptr) return -11;
     if (ldb < std::max<int64_t>(1, n)) return -12;
     if (n > 0 && nrhs > 0 && X == nullptr) return -13;
@@ -901,16 +906,51 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t ld
     if ((flags & FF_FLAG_STRASSEN1) && dtype != FF_F64) return FF_ERR_UNSUPPORTED;
     memset(out, 0, sizeof(*out));
     out->dtype_used = dtype;
+    out->escalated_to = -1;
     if (n == 0 || nrhs == 0) return 0;
-    const size_t need = ff_solve_workspace_size(n, s, nrhs, dtype);
+    const size_t need = ff_solve_workspace_size(n, s, nrhs, dtype, flags);
     if (ws == nullptr || ws_bytes < need) return FF_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int si = (int)std::min<int64_t>(s, n);
+    const unsigned fflags = flags & ~(unsigned)FF_FLAG_ESCALATE;   // what the factorisations see
+    int rc;
     if (dtype == FF_F64)
-        return solve_impl<double>((int)n, si, (int)nrhs, A64, lda, static_cast<double*>(W), ldw, dtype, flags,
-                                  w_is_factored, B, ldb, X, ldx, tol, max_iter, ws, st, out);
-    return solve_impl<float>((int)n, si, (int)nrhs, A64, lda, static_cast<float*>(W), ldw, dtype, flags,
-                             w_is_factored, B, ldb, X, ldx, tol, max_iter, ws, st, out);
+        rc = solve_impl<double>((int)n, si, (int)nrhs, A64, lda, static_cast<double*>(W), ldw, dtype, fflags,
+                                w_is_factored, B, ldb, X, ldx, tol, max_iter, ws, st, out);
+    else
+        rc = solve_impl<float>((int)n, si, (int)nrhs, A64, lda, static_cast<float*>(W), ldw, dtype, fflags,
+                               w_is_factored, B, ldb, X, ldx, tol, max_iter, ws, st, out);
+    out->first_info = out->info;
+    out->total_iters = out->iters;
+    out->escalated_to = -1;
+    if (rc != 0 || !(flags & FF_FLAG_ESCALATE) || dtype == FF_F64) return rc;
+    auto accepted = [&](const ff_solve_info& o) { return o.info == 0 && (o.converged || o.backward_err <= tol); };
+    auto take = [&](const ff_solve_info& o, int to) {
+        const int first = out->first_info, total = out->total_iters + o.iters, esc = out->escalations + 1;
+        *out = o;
+        out->first_info = first;
+        out->total_iters = total;
+        out->escalations = esc;
+        out->escalated_to = to;
+    };
+    if (accepted(*out)) return 0;
+    ff_solve_info o{};
+    if (dtype == FF_BF16) {
+        rc = solve_impl<float>((int)n, si, (int)nrhs, A64, lda, static_cast<float*>(W), ldw, FF_F32, fflags, 0, B, ldb,
+                               X, ldx, tol, max_iter, ws, st, &o);
+        if (rc != 0) return rc;
+        take(o, FF_F32);
+        if (accepted(*out)) return 0;
+    }
+    Carver cv(static_cast<char*>(ws) + carve_solve<float>(nullptr, n, s, nrhs, dtype).bytes);
+    double* W64 = cv.take<double>((size_t)n * (size_t)n);
+    void* ws64 = cv.base + cv.off;
+    o = ff_solve_info{};
+    rc = solve_impl<double>((int)n, si, (int)nrhs, A64, lda, W64, n, FF_F64, fflags, 0, B, ldb, X, ldx, tol, max_iter,
+                            ws64, st, &o);
+    if (rc != 0) return rc;
+    take(o, FF_F64);
+    return 0;
 }
 
 size_t ff_trisolve_workspace_size(int64_t n, int dtype) {

@@ -1,7 +1,13 @@
 """Full-size GPU checks at n = 16384, in the configuration bench.py times (binary64,
-lookahead schedule, the benchmark's step sizes).  The oracle cannot run at this
-size inside a test, so the checks are ones whose expected values do not come from
-the library:
+lookahead schedule, the benchmark's step sizes):
+
+* the benchmark matrices against the CPU oracle, element by element: Cholesky of
+  A = G G^T / n + I (kappa ~ 5) at the paper's step s = 168 and at the benchmark's
+  s = 768 with ||tril(L - L_oracle)||_F / ||tril(L)||_F <= 1e-11; LU without
+  pivoting of the strictly diagonally dominant U(-1, 1) matrix at s = 168 against
+  the oracle's Doolittle factors at the same bound, backward error <= 1e-13
+  (the oracle runs on all host cores: about half a minute for Cholesky and a
+  minute for LU);
 
 * integer families: A = L0 L0^T (or L0 U0) formed by torch's binary64 GEMM, exact
   for these entries; the factor must equal L0 (U0) bit for bit, as at small sizes,
@@ -15,6 +21,7 @@ the library:
 import numpy as np
 import pytest
 
+import oracle
 from paper_1812_02056_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -148,3 +155,48 @@ def test_fullsize_refined_solve_integer_solution(dtype, s):
     assert info["backward_err"] <= 1e-15
     del A, B, X, W
     torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def benchmark_chol_oracle():
+    A0 = wl.spd_scaled_device(N, seed=0, device=DEV)     # the benchmark's matrix (symmetric, row-major)
+    Lo, info = oracle.chol(A0.cpu().numpy())
+    assert info == 0
+    return A0, Lo
+
+
+@pytest.mark.parametrize("s", [168, 768])
+def test_fullsize_chol_benchmark_matrix_matches_oracle(benchmark_chol_oracle, s):
+    A0, Lo = benchmark_chol_oracle
+    Acm = A0.clone().t()
+    assert ff.chol_factor(Acm, s, dtype="f64", sync=True) == 0
+    L = torch.tril(Acm).cpu().numpy()
+    del Acm
+    torch.cuda.empty_cache()
+    rel = oracle.rel_lower(L, Lo)
+    print(f"n={N} s={s}: rel_L = {rel:.2e}")
+    assert rel <= 1e-11
+
+
+def test_fullsize_lu_matches_oracle():
+    s = 168
+    T = wl.diag_dominant_device(N, seed=0, device=DEV)   # T[j, i] = A[i, j]: column-major storage of A
+    A_host = T.t().cpu().numpy()
+    LUo, info = oracle.lu(A_host)
+    assert info == 0
+    Acm = T.clone().t()
+    assert ff.lu_nopiv_factor(Acm, s, sync=True) == 0
+    LU = Acm.cpu().numpy()
+    d = LU - LUo
+    rel = float(np.linalg.norm(d) / np.linalg.norm(LUo))
+    del d
+    # backward error with torch's binary64 GEMM on the device (independent of the library's kernels)
+    Ld = torch.tril(Acm, -1)
+    Ld.diagonal().fill_(1.0)
+    Ud = torch.triu(Acm)
+    bwd = float(torch.linalg.norm(T.t() - Ld @ Ud) / torch.linalg.norm(T))
+    print(f"LU n={N} s={s}: rel = {rel:.2e} bwd = {bwd:.2e}")
+    del T, Acm, Ld, Ud
+    torch.cuda.empty_cache()
+    assert rel <= 1e-11
+    assert bwd <= 1e-13

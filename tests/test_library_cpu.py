@@ -72,8 +72,12 @@ def test_workspace_sizes(lib):
     assert lib.ff_chol_workspace_size(100, 27, 1, 0) >= 27 * 27 * 8
     assert lib.ff_chol_workspace_size(10, 27, 2, 0) >= 10 * 10 * 8
     assert lib.ff_trisolve_workspace_size(130, 0) >= 3 * 64 * 64 * 8
-    assert lib.ff_solve_workspace_size(1000, 64, 4, 1) > lib.ff_solve_workspace_size(1000, 64, 1, 1)
-    assert lib.ff_solve_workspace_size(0, 64, 4, 1) == 0
+    assert lib.ff_solve_workspace_size(1000, 64, 4, 1, 0) > lib.ff_solve_workspace_size(1000, 64, 1, 1, 0)
+    assert lib.ff_solve_workspace_size(0, 64, 4, 1, 0) == 0
+    # escalation to binary64 needs an n x n binary64 factor in the workspace
+    assert (lib.ff_solve_workspace_size(1000, 64, 1, 2, 8) - lib.ff_solve_workspace_size(1000, 64, 1, 2, 0)
+            >= 1000 * 1000 * 8)
+    assert lib.ff_solve_workspace_size(1000, 64, 1, 0, 8) == lib.ff_solve_workspace_size(1000, 64, 1, 0, 0)
 
 
 def _header_without_comments():
@@ -85,7 +89,7 @@ def test_flag_constants_match_the_header():
     from paper_1812_02056_amd import binding
     text = _header_without_comments()
     flags = dict(re.findall(r"\b(FF_FLAG_[A-Z0-9_]+)\s*=\s*1u\s*<<\s*(\d+)", text))
-    assert set(flags) == {"FF_FLAG_STRASSEN1", "FF_FLAG_NO_LOOKAHEAD", "FF_FLAG_FIXED_STEP"}
+    assert set(flags) == {"FF_FLAG_STRASSEN1", "FF_FLAG_NO_LOOKAHEAD", "FF_FLAG_FIXED_STEP", "FF_FLAG_ESCALATE"}
     for name, shift in flags.items():
         assert getattr(binding, name[3:]) == 1 << int(shift), name
 
@@ -113,3 +117,12 @@ def test_noalloc_rejects_sizes_beyond_its_scratch(lib):
     assert lib.chol_trisolve_noalloc(8, 1, fake, 7, 0, fake, 8, null, null) == -4
     from paper_1812_02056_amd import binding
     assert "static scratch" in binding.status_string(-103)
+
+
+def test_solve_info_layout_matches_the_header():
+    from paper_1812_02056_amd import binding
+    text = _header_without_comments()
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*ff_solve_info;", text).group(1)
+    fields = re.findall(r"(int32_t|double)\s+(\w+);", body)
+    ctype = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
+    assert [(n, ctype[t]) for t, n in fields] == list(binding.SolveInfo._fields_)
