@@ -254,21 +254,24 @@ int ff_update_gemm(int64_t m, int64_t w, void *C, int64_t ldc, const void *X, in
 
 /*
  * Measurement aid (not part of the method): while enabled, every trailing
- * update launched by chol_factor is bracketed by a pair of HIP events recorded
- * on the stream it runs on, and tallied by the kernel shape the launch used.
- * Events are created per launch, so leave it off outside timing runs.
+ * update launched by chol_factor on the caller's stream is bracketed by a pair
+ * of HIP events recorded on that stream, and tallied by the kernel that ran:
+ * for binary64 by kernel shape, FF_UPD_SHAPE_64 (64 x 64 tiles),
+ * FF_UPD_SHAPE_128 (128 x 128 tiles, two workgroups per CU) and
+ * FF_UPD_SHAPE_256x128 (256 x 128 tiles, one workgroup per CU: the lookahead
+ * update); FF_UPD_SHAPE_F32 and FF_UPD_SHAPE_BF16 collect the binary32 and the
+ * bfloat16-operand updates of every shape.  Events are created per launch, so
+ * leave it off outside timing runs.
  *   ff_update_profile_enable(1) clears the tallies and starts recording;
  *   ff_update_profile_enable(0) stops recording (tallies are kept).
- *   ff_update_profile_read waits for the recorded events and fills out[shape]
- *   for shape FF_UPD_SHAPE_64 (64 x 64 tiles), FF_UPD_SHAPE_128 (128 x 128
- *   tiles, two workgroups per CU) and FF_UPD_SHAPE_256x128 (256 x 128 tiles, one
- *   workgroup per CU: the lookahead update); flops are the algorithmic
- *   2 K x (entries written) of each launch, bytes its algorithmic HBM traffic
- *   (each entry written read and written once, the M x K panel rows of the
- *   region read once).  Host-synchronous; the tallies are process-wide.
- *   Returns 0 or FF_ERR_HIP.
+ *   ff_update_profile_read waits for the recorded events and fills out[shape];
+ *   flops are the algorithmic 2 K x (entries written) of each launch, bytes
+ *   its algorithmic HBM traffic (each entry written read and written once, the
+ *   M x K panel rows of the region read once, at the storage element size).
+ *   Host-synchronous; the tallies are process-wide.  Returns 0 or FF_ERR_HIP.
  */
-enum { FF_UPD_SHAPE_64 = 0, FF_UPD_SHAPE_128 = 1, FF_UPD_SHAPE_256x128 = 2, FF_UPD_NSHAPES = 3 };
+enum { FF_UPD_SHAPE_64 = 0, FF_UPD_SHAPE_128 = 1, FF_UPD_SHAPE_256x128 = 2, FF_UPD_SHAPE_F32 = 3,
+       FF_UPD_SHAPE_BF16 = 4, FF_UPD_NSHAPES = 5 };
 typedef struct {
     int64_t launches;
     double total_ms;

@@ -40,7 +40,7 @@ EXPORTED = (
     "ff_server_get_stats",
 )
 
-UPD_SHAPES = ("64x64", "128x128", "256x128")   # FF_UPD_SHAPE_* order
+UPD_SHAPES = ("64x64", "128x128", "256x128", "f32", "bf16")   # FF_UPD_SHAPE_* order
 
 
 class ServerResult(ctypes.Structure):
@@ -336,11 +336,11 @@ def update_profile_enable(enable: bool = True):
 def update_profile_read() -> dict:
     """Per kernel shape: launches, total_ms, total_flops, total_bytes (algorithmic)
     since the last enable (synchronises)."""
-    out = (KernelProfile * 3)()
+    out = (KernelProfile * len(UPD_SHAPES))()
     _check(load().ff_update_profile_read(out), "ff_update_profile_read")
     return {UPD_SHAPES[i]: {"launches": int(out[i].launches), "total_ms": float(out[i].total_ms),
                             "total_flops": float(out[i].total_flops), "total_bytes": float(out[i].total_bytes)}
-            for i in range(3)}
+            for i in range(len(UPD_SHAPES))}
 
 
 class Server:

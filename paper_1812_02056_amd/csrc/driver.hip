@@ -131,7 +131,10 @@ struct UpdTimer {
     double flops = 0, bytes = 0;
     int shape = 0;
     hipStream_t st = nullptr;
-    UpdTimer(int M, int N, int K, int shift, int reserve, hipStream_t s, double f0 = 0.0, double f1 = 1.0) : st(s) {
+    // shape_of < 0: the binary64 kernel shape launch_update picks; else that tally
+    // (FF_UPD_SHAPE_F32 / FF_UPD_SHAPE_BF16).  elem: bytes per stored element.
+    UpdTimer(int M, int N, int K, int shift, int reserve, hipStream_t s, double f0 = 0.0, double f1 = 1.0,
+             int shape_of = -1, int elem = 8) : st(s) {
         // the tail part of a split update runs concurrently on another stream and
         // is not recorded (the profile covers the launches on the caller's stream)
         if (f0 > 0.0) return;
@@ -150,8 +153,8 @@ struct UpdTimer {
         flops = 2.0 * (double)K * entries;
         // C entries read and written once, the region's panel rows (its columns
         // are rows of the same panel) read once
-        bytes = 8.0 * (2.0 * entries + (double)M * (double)K);
-        shape = update_shape(M, N, reserve);
+        bytes = (double)elem * (2.0 * entries + (double)M * (double)K);
+        shape = shape_of >= 0 ? shape_of : update_shape(M, N, reserve);
         (void)hipEventRecord(e0, st);
     }
     void stop() {
@@ -248,11 +251,14 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
                                      reserve, max_cus, f0, f1));
         tm.stop();
     } else {
+        UpdTimer tm(M, N, w, shift, reserve, st, f0, f1, dtype == FF_BF16 ? FF_UPD_SHAPE_BF16 : FF_UPD_SHAPE_F32,
+                    (int)sizeof(float));
         if (dtype == FF_BF16)
             FF_TRY(launch_update_bf16(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, shift, info, st, reserve));
         else
             FF_TRY(launch_update<float>(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, true, shift, info, st,
                                         reserve, max_cus, f0, f1));
+        tm.stop();
     }
     return 0;
 }
