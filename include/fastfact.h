@@ -282,37 +282,54 @@ int ff_update_profile_enable(int enable);
 int ff_update_profile_read(ff_kernel_profile out[FF_UPD_NSHAPES]);
 
 /*
- * Serving: many independent SPD systems A_i X_i = B_i (binary64), each factored
- * by Algorithm 1 (Sec. 2) with step s = min(n, 192) (the widest diagonal block
- * one workgroup factors) and solved with the factor.  A server keeps every admitted factorisation in
- * flight: each ff_server_step advances all of them by one block of s columns
- * with three grouped launches (the diagonal blocks of every matrix, then their
- * panel solves, then their trailing updates), and starts the solves of those
- * that finished.  Factors live in the caller's device arena; a finished factor
- * stays resident under its nonzero key, so a later request with the same key
- * (and n) is solved without refactoring (a cache hit).  Requests are admitted
- * in arrival order while the arena has room for the factor (n*n doubles) and
- * the solve workspace, evicting least recently used resident factors that no
- * request is using.  A request whose factorisation fails reports info > 0
- * (1-based column, as chol_factor) and its X is unspecified.
+ * Serving: many independent SPD systems A_i X_i = B_i (binary64 A, B, X), each
+ * factored by Algorithm 1 (Sec. 2) with step s = min(n, 192) (the widest
+ * diagonal block one workgroup factors) and solved with the factor.  A server
+ * keeps every admitted factorisation in flight: each ff_server_step advances
+ * all of them by one block of s columns with three grouped launches (the
+ * diagonal blocks of every matrix, then their panel solves, then their trailing
+ * updates), and starts the solves of those that finished.  Factors live in the
+ * caller's device arena; a finished factor stays resident under its nonzero
+ * key, so a later request with the same key (and n) is solved without
+ * refactoring (a cache hit).  Requests are admitted in arrival order while the
+ * arena has room for the factor and the solve workspace, evicting least
+ * recently used resident factors that no request is using.
+ *
+ * Precision (dtype at creation):
+ *   FF_F64  binary64 factors (8 n^2 bytes), one forward and one back solve;
+ *   FF_F32  binary32 factors (4 n^2 bytes; diagonal blocks factored in
+ *           binary64, panel solves and updates in binary32) and binary64
+ *           iterative refinement against the request's A: an iteration is
+ *           enqueued per scheduler iteration after the previous one's
+ *           correction ||dX||_inf / ||X||_inf has reached the host; it stops at
+ *           <= 1e-12, on stagnation (the correction shrank by less than half)
+ *           or after 30 iterations.  The request's A must stay valid until it
+ *           is returned (it is read by every iteration, also on a cache hit).
+ *   FF_BF16 is not served (FF_ERR_UNSUPPORTED).
  *
  *   ff_server_create: arena = device buffer of arena_bytes (the HBM budget),
  *     owned by the caller and untouched by anything else while the server
  *     lives; stream = HIP stream for all server work.  Returns NULL on error
- *     (*status < 0).  The server allocates its own small job tables.
+ *     (*status < 0).  The server allocates its own small job tables and pinned
+ *     host slots.
  *   ff_server_submit: A (lda >= n), B and X (n x nrhs, ldb, ldx >= n) are
  *     device buffers that must stay valid, and B / A unmodified, until the
  *     request is returned by ff_server_poll; key = 0 means never cache.
  *     The arrival time is stamped when submit is called.  Returns 0,
  *     -(argument index) or FF_ERR_WORKSPACE if the request can never fit.
  *   ff_server_step: one scheduler iteration (admission, one block step of
- *     every active factorisation, solves).  Enqueues only, except that it waits
- *     for the step 4 iterations back before reusing its job table.  Returns the
- *     number of requests not yet finished (>= 0), or an error (FF_ERR_WORKSPACE
- *     if the oldest queued request cannot be admitted although nothing runs).
- *   ff_server_poll: up to max_out finished requests (their solve has completed
- *     on the device): id, info, cache_hit, latency_ms (device time from the
- *     submit stamp to the end of the solve).  Non-blocking.
+ *     every active factorisation, solves and refinement decisions).  Enqueues
+ *     only, except that it waits for the step 4 iterations back before reusing
+ *     its job table.  Returns the number of requests not yet finished (>= 0),
+ *     or an error (FF_ERR_WORKSPACE if the oldest queued request cannot be
+ *     admitted although nothing runs).
+ *   ff_server_poll: up to max_out finished requests (their work has completed
+ *     on the device): id, info (as chol_factor's; FF_ERR_HIP if a bounded wait
+ *     of the triangular solves expired), cache_hit, latency_ms (device time
+ *     from the submit stamp to the end of the solve), iters and converged (the
+ *     refinement of FF_F32 servers; 0 for FF_F64).  A request whose
+ *     factorisation failed reports info > 0 and its X is unspecified.
+ *     Non-blocking.
  * A server is not thread safe; use one per host thread.
  */
 typedef struct ff_server ff_server;
@@ -321,12 +338,14 @@ typedef struct {
     int32_t info;
     int32_t cache_hit;
     double latency_ms;
+    int32_t iters;
+    int32_t converged;
 } ff_server_result;
 typedef struct {
     int64_t submitted, completed, steps, grouped_launches, cache_hits, evictions;
     int64_t arena_free, resident_factors, queued, active;
 } ff_server_stats;
-ff_server *ff_server_create(void *arena, size_t arena_bytes, void *stream, int *status);
+ff_server *ff_server_create(void *arena, size_t arena_bytes, int dtype, void *stream, int *status);
 int ff_server_destroy(ff_server *srv);
 int ff_server_submit(ff_server *srv, uint64_t key, int64_t n, const double *A, int64_t lda, const double *B,
                      int64_t nrhs, int64_t ldb, double *X, int64_t ldx, int64_t *req_id);

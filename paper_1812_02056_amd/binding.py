@@ -45,7 +45,7 @@ UPD_SHAPES = ("64x64", "128x128", "256x128", "f32", "bf16")   # FF_UPD_SHAPE_* o
 
 class ServerResult(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("info", ctypes.c_int32), ("cache_hit", ctypes.c_int32),
-                ("latency_ms", ctypes.c_double)]
+                ("latency_ms", ctypes.c_double), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -117,7 +117,7 @@ def load():
     lib.ff_update_profile_enable.restype = i32
     lib.ff_update_profile_read.argtypes = [ctypes.POINTER(KernelProfile)]
     lib.ff_update_profile_read.restype = i32
-    lib.ff_server_create.argtypes = [vp, sz, vp, ctypes.POINTER(i32)]
+    lib.ff_server_create.argtypes = [vp, sz, i32, vp, ctypes.POINTER(i32)]
     lib.ff_server_create.restype = vp
     lib.ff_server_destroy.argtypes = [vp]
     lib.ff_server_destroy.restype = i32
@@ -344,20 +344,22 @@ def update_profile_read() -> dict:
 
 
 class Server:
-    """Continuous-batching solver (ff_server_*): many independent binary64 SPD
-    systems, every admitted factorisation advanced one block per step() with
-    grouped launches; finished factors stay resident under their key.
+    """Continuous-batching solver (ff_server_*): many independent SPD systems
+    (binary64 A, B, X), every admitted factorisation advanced one block per
+    step() with grouped launches; finished factors stay resident under their
+    key.  dtype "f64": binary64 factors; "f32": binary32 factors with binary64
+    refinement.
 
     arena: a device tensor whose storage is the HBM budget (kept alive here).
     Tensors passed to submit() are kept alive until their request is polled."""
 
-    def __init__(self, arena: torch.Tensor, stream=None):
+    def __init__(self, arena: torch.Tensor, stream=None, dtype="f64"):
         self._lib = load()
         self.arena = arena
         self.stream = stream if stream is not None else torch.cuda.current_stream(arena.device)
         st = ctypes.c_int(0)
-        h = self._lib.ff_server_create(_ptr(arena), arena.numel() * arena.element_size(), _stream(self.stream),
-                                       ctypes.byref(st))
+        h = self._lib.ff_server_create(_ptr(arena), arena.numel() * arena.element_size(), _dt(dtype),
+                                       _stream(self.stream), ctypes.byref(st))
         if not h:
             raise FastFactError(f"ff_server_create failed: {st.value} ({status_string(st.value)})")
         self._h = ctypes.c_void_p(h)
@@ -392,7 +394,8 @@ class Server:
         for i in range(k.value):
             r = out[i]
             self._keep.pop(r.id, None)
-            res.append({"id": r.id, "info": r.info, "cache_hit": bool(r.cache_hit), "latency_ms": r.latency_ms})
+            res.append({"id": r.id, "info": r.info, "cache_hit": bool(r.cache_hit), "latency_ms": r.latency_ms,
+                        "iters": r.iters, "converged": bool(r.converged)})
         return res
 
     def stats(self) -> dict:

@@ -55,38 +55,43 @@ hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc,
                                            const double* Y, int64_t ldy, const int* info, hipStream_t st,
                                            int reserve_cus = 0);
 
-// Job tables of the grouped (many-matrix) kernels, device resident.
-//   GroupDiag: factor the w x w block at a (binary64, w <= LDS_DIAG_MAX).
+// Job tables of the grouped (many-matrix) kernels, device resident.  Matrix
+// pointers are untyped: the launch's storage type S (double or float) gives
+// their element type.
+//   GroupDiag: factor the w x w block at a (binary64 arithmetic, w <= LDS_DIAG_MAX).
 //   GroupTrsm: solve the m x w panel x against the factored block t (both with
 //              leading dimension ld); workgroups [wg_begin, wg_begin + nwg).
 //   GroupUpd:  c -= p p^T on the lower triangle of the m x m square c, p m x w;
 //              lower-triangle 128 x 128 tiles [tiles_begin, tiles_begin + tiles).
 struct GroupDiag {
-    double* a;
+    void* a;
     int64_t ld;
     int w;
     int col_base;
     int* info;
 };
 struct GroupTrsm {
-    double* x;
-    const double* t;
+    void* x;
+    const void* t;
     int64_t ld;
     int m, w;
     int wg_begin, nwg;
     const int* info;
 };
 struct GroupUpd {
-    double* c;
-    const double* p;
+    void* c;
+    const void* p;
     int64_t ld;
     int m, w;
     int tiles_begin;
     const int* info;
 };
+template <typename S>
 hipError_t launch_potrf_grouped(int njobs, const GroupDiag* d_jobs, hipStream_t st);
+template <typename S>
 hipError_t launch_trsm_grouped(int njobs, int total_wg, const GroupTrsm* d_jobs, hipStream_t st);
 int trsm_rows_per_wg();
+template <typename S>
 hipError_t launch_update_grouped(int njobs, int total_tiles, const GroupUpd* d_jobs, hipStream_t st);
 int grouped_update_tile();
 

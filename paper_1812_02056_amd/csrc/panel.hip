@@ -624,13 +624,15 @@ void trsm_reg_kernel(int m, int w, T* x, int64_t xi, int64_t xj, const T* __rest
 // ---------------------------------------------------------------------------
 // Grouped forms for many independent factorisations at once (serving): one
 // launch covers the diagonal blocks, or the panel solves, of every job.
+template <typename S>
 __global__ __launch_bounds__(PT)
 void potrf_grouped_kernel(const GroupDiag* __restrict__ jobs)
 {
     const GroupDiag jb = jobs[blockIdx.x];
-    potrf_block<double>(jb.w, jb.a, jb.ld, jb.info, jb.col_base);
+    potrf_block<S>(jb.w, static_cast<S*>(jb.a), jb.ld, jb.info, jb.col_base);
 }
 
+template <typename S>
 __global__ __launch_bounds__(TRSM_NT)
 void trsm_grouped_kernel(const GroupTrsm* __restrict__ jobs, int njobs)
 {
@@ -642,7 +644,8 @@ void trsm_grouped_kernel(const GroupTrsm* __restrict__ jobs, int njobs)
         else hi = mid - 1;
     }
     const GroupTrsm jb = jobs[lo];
-    trsm_block<double, true>(jb.m, jb.w, jb.x, 1, jb.ld, jb.t, jb.ld, 1, 0, jb.info, blockIdx.x - jb.wg_begin, jb.nwg);
+    trsm_block<S, true>(jb.m, jb.w, static_cast<S*>(jb.x), 1, jb.ld, static_cast<const S*>(jb.t), jb.ld, 1, 0, jb.info,
+                        blockIdx.x - jb.wg_begin, jb.nwg);
 }
 
 }  // namespace
@@ -693,17 +696,24 @@ hipError_t launch_trsm(int m, int w, T* x, int64_t xi, int64_t xj, const T* t, i
     return hipGetLastError();
 }
 
+template <typename S>
 hipError_t launch_potrf_grouped(int njobs, const GroupDiag* d_jobs, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(potrf_grouped_kernel, dim3(njobs), dim3(PT), 0, st, d_jobs);
+    hipLaunchKernelGGL((potrf_grouped_kernel<S>), dim3(njobs), dim3(PT), 0, st, d_jobs);
     return hipGetLastError();
 }
 
+template <typename S>
 hipError_t launch_trsm_grouped(int njobs, int total_wg, const GroupTrsm* d_jobs, hipStream_t st) {
     if (njobs <= 0 || total_wg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(trsm_grouped_kernel, dim3(total_wg), dim3(TRSM_NT), 0, st, d_jobs, njobs);
+    hipLaunchKernelGGL((trsm_grouped_kernel<S>), dim3(total_wg), dim3(TRSM_NT), 0, st, d_jobs, njobs);
     return hipGetLastError();
 }
+
+template hipError_t launch_potrf_grouped<double>(int, const GroupDiag*, hipStream_t);
+template hipError_t launch_potrf_grouped<float>(int, const GroupDiag*, hipStream_t);
+template hipError_t launch_trsm_grouped<double>(int, int, const GroupTrsm*, hipStream_t);
+template hipError_t launch_trsm_grouped<float>(int, int, const GroupTrsm*, hipStream_t);
 
 int trsm_rows_per_wg() { return TRSM_NT / 4; }
 

@@ -1,117 +1,298 @@
 // serve.hip -- continuous batching of many independent SPD solves.
 //
 // Each request is Algorithm 1 of arXiv 1812.02056 (Sec. 2) on its own matrix,
-// followed by the two triangular solves.  The server keeps every admitted
-// factorisation in flight at once: one scheduler iteration (ff_server_step)
-// advances each of them by one block of s columns with three grouped launches
-// (diagonal factorisations, panel solves, trailing updates of all active
-// matrices), and starts the solves of the factorisations that finished.
-// Factors live in a caller-provided device arena (the HBM budget); a finished
-// factor stays resident under its key, so a later request for the same matrix
-// skips the factorisation.  Admission is first come, first served, by arena
-// space, evicting least recently used resident factors that no request holds.
+// followed by the two triangular solves (solving linear systems being the
+// use of the factorisation, Introduction).  The scheduling (arena, resident
+// factors, admission, the stage of every request) is serve_core.hpp; this file
+// is its device side: one scheduler iteration advances every admitted
+// factorisation by one block with three grouped launches (diagonal blocks,
+// panel solves, trailing updates of all active matrices) and runs the solves.
+//
+// Two precisions:
+//   FF_F64  factors in binary64, one forward and one backward solve;
+//   FF_F32  factors stored in binary32 (diagonal blocks factored in binary64,
+//           panel solves and updates in binary32), solves refined in binary64
+//           against the request's A: each iteration computes R = B - A X,
+//           solves with the factor, adds the correction and copies
+//           ||dX||_inf / ||X||_inf to the host, where the scheduler decides on
+//           the next iteration at a later scheduler iteration, without waiting.
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
-#include <cmath>
-#include <list>
-#include <map>
 #include <new>
 #include <vector>
 
 #include "fastfact.h"
 #include "internal.hpp"
+#include "serve_core.hpp"
 
 namespace ff {
 namespace {
 
-constexpr size_t ALIGN = 256;
-constexpr int MAX_ACTIVE = 512;      // admitted requests (job-table capacity)
+using ffserve::align_up;
+
+constexpr int MAX_ACTIVE = 512;      // admitted requests (job-table capacity, host slots)
 constexpr int MAX_FACTORS = 8192;    // live factors (info words)
 constexpr int RING = 4;              // job-table slots in flight
+constexpr size_t TAB_BYTES = MAX_ACTIVE * (sizeof(GroupDiag) + sizeof(GroupTrsm) + sizeof(GroupUpd)) + 3 * 256;
 
-inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
-
-// First-fit allocator over [0, size) with coalescing on free.
-struct Arena {
-    size_t size = 0;
-    std::map<size_t, size_t> free_;   // offset -> length
-    void init(size_t n) {
-        size = n;
-        free_.clear();
-        if (n) free_[0] = n;
-    }
-    bool alloc(size_t n, size_t& off) {
-        n = align_up(n ? n : 1);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                off = it->first;
-                const size_t rest = it->second - n;
-                free_.erase(it);
-                if (rest) free_[off + n] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t n) {
-        n = align_up(n ? n : 1);
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
+// Pinned host slot of an admitted request: the last refinement check and the
+// triangular solves' error word.
+struct HostSlot {
+    double norms[2];     // max |dX|, max |X|
+    int err;
+    int pad;
 };
 
-struct Factor {            // a factor buffer in the arena
-    uint64_t key;
-    int n;
-    size_t off, bytes;
-    int users = 0;         // requests that read or write it
-    bool ready = false;    // factorisation finished (enqueued)
-    bool dead = false;     // failed or unkeyed: freed when the last user is done
-    int info_slot = -1;
+struct Handles {
+    hipEvent_t t_arrive = nullptr, t_done = nullptr, t_check = nullptr;
 };
 
-enum State { QUEUED, FACTOR, WAIT_FACTOR, SOLVE, DONE };
-
-struct Request {
-    int64_t id;
-    uint64_t key;
-    int n, nrhs;
-    const double* A;
-    int64_t lda;
-    const double* B;
-    int64_t ldb;
-    double* X;
-    int64_t ldx;
-    State st = QUEUED;
-    Factor* f = nullptr;
-    bool owner = false;    // this request computes f
-    int s = 0, c0 = 0;
-    size_t ws_off = 0, ws_bytes = 0;
-    hipEvent_t t_arrive = nullptr, t_done = nullptr;
-    bool hit = false;
+// Workspace of a request's solve, carved from its arena block.
+struct SolveWs {
+    int* ctl;            // triangular-solve control words (ctl[0]: error word)
+    void* fac;
+    void* pub;
+    double* R;           // n x nrhs residual (binary32 mode)
+    float* D;            // n x nrhs correction in the factor's precision
+    double* rpart;       // residual partial sums
+    double* norms;       // 2 doubles
+    size_t bytes;
 };
 
-// Step of a served factorisation: LDS_DIAG_MAX columns, the widest diagonal block
-// one workgroup factors (the paper's n^0.5286 is 30-117 over n = 256..8192; with
-// the wider step each matrix takes fewer scheduler iterations, which measured
-// 914 vs 825 solves/s in closed loop and p50 / p99 10 / 71 ms vs 20 / 86 ms at
-// load 0.8 on the serving benchmark).
-int default_step(int n) {
-    return std::max(1, std::min(n, LDS_DIAG_MAX));
+SolveWs carve(char* base, int n, int nrhs, int dtype) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes ? bytes : 1);
+        return p;
+    };
+    const size_t es = dtype == FF_F64 ? sizeof(double) : sizeof(float);
+    SolveWs w{};
+    w.ctl = reinterpret_cast<int*>(take(TRI_CTL * sizeof(int)));
+    w.fac = take(trisolve_fac_elems(n) * es);
+    w.pub = take(trisolve_pub_elems(n) * es);
+    if (dtype != FF_F64) {
+        w.R = reinterpret_cast<double*>(take((size_t)n * nrhs * sizeof(double)));
+        w.D = reinterpret_cast<float*>(take((size_t)n * nrhs * sizeof(float)));
+        w.rpart = reinterpret_cast<double*>(take(residual_part_doubles(n) * sizeof(double)));
+        w.norms = reinterpret_cast<double*>(take(4 * sizeof(double)));
+    }
+    w.bytes = off;
+    return w;
 }
+
+class HipExecutor : public ffserve::Executor {
+public:
+    hipStream_t st = nullptr;      // all server work
+    hipStream_t clock = nullptr;   // idle stream: arrival stamps
+    char* base = nullptr;
+    int dtype = FF_F64;
+    int* d_info = nullptr;
+    int* h_info = nullptr;
+    HostSlot* h_slot = nullptr;
+    void* h_tab[RING] = {};
+    void* d_tab[RING] = {};
+    hipEvent_t tab_ev[RING] = {};
+
+    int init(void* arena, void* stream, int dt) {
+        st = static_cast<hipStream_t>(stream);
+        base = static_cast<char*>(arena);
+        dtype = dt;
+        if (hipStreamCreateWithFlags(&clock, hipStreamNonBlocking) != hipSuccess ||
+            hipMalloc(&d_info, MAX_FACTORS * sizeof(int)) != hipSuccess ||
+            hipHostMalloc(&h_info, MAX_FACTORS * sizeof(int)) != hipSuccess ||
+            hipHostMalloc(&h_slot, MAX_ACTIVE * sizeof(HostSlot)) != hipSuccess)
+            return FF_ERR_HIP;
+        for (int i = 0; i < RING; ++i)
+            if (hipHostMalloc(&h_tab[i], TAB_BYTES) != hipSuccess || hipMalloc(&d_tab[i], TAB_BYTES) != hipSuccess ||
+                hipEventCreateWithFlags(&tab_ev[i], hipEventDisableTiming) != hipSuccess)
+                return FF_ERR_HIP;
+        memset(h_slot, 0, MAX_ACTIVE * sizeof(HostSlot));
+        return 0;
+    }
+    ~HipExecutor() override {
+        if (st) (void)hipStreamSynchronize(st);
+        for (int i = 0; i < RING; ++i) {
+            if (h_tab[i]) (void)hipHostFree(h_tab[i]);
+            if (d_tab[i]) (void)hipFree(d_tab[i]);
+            if (tab_ev[i]) (void)hipEventDestroy(tab_ev[i]);
+        }
+        if (d_info) (void)hipFree(d_info);
+        if (h_info) (void)hipHostFree(h_info);
+        if (h_slot) (void)hipHostFree(h_slot);
+        if (clock) (void)hipStreamDestroy(clock);
+    }
+
+    size_t es() const { return dtype == FF_F64 ? sizeof(double) : sizeof(float); }
+    size_t factor_bytes(int n) const override { return (size_t)n * (size_t)n * es(); }
+    size_t solve_bytes(int n, int nrhs) const override { return carve(nullptr, n, nrhs, dtype).bytes; }
+    char* factor_ptr(const ffserve::Factor* f) const { return base + f->off; }
+
+    int arrive(ffserve::Request* r) override {
+        Handles* h = new (std::nothrow) Handles();
+        if (!h) return FF_ERR_HIP;
+        r->dev = h;
+        if (hipEventCreate(&h->t_arrive) != hipSuccess || hipEventCreate(&h->t_done) != hipSuccess ||
+            hipEventCreateWithFlags(&h->t_check, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(h->t_arrive, clock) != hipSuccess)
+            return FF_ERR_HIP;
+        return 0;
+    }
+
+    int start_factor(ffserve::Request* r) override {
+        const ffserve::Factor* f = r->f;
+        if (dtype == FF_F64) {
+            // the factor starts as a copy of A (lower triangle read)
+            if (hipMemcpy2DAsync(factor_ptr(f), (size_t)r->n * sizeof(double), r->A, (size_t)r->lda * sizeof(double),
+                                 (size_t)r->n * sizeof(double), r->n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return FF_ERR_HIP;
+        } else if (launch_copy_lower_from_f64<float>(r->n, r->A, r->lda, reinterpret_cast<float*>(factor_ptr(f)), r->n,
+                                                     st) != hipSuccess) {
+            return FF_ERR_HIP;
+        }
+        return launch_set_int(d_info + f->info_slot, 0, st) == hipSuccess ? 0 : FF_ERR_HIP;
+    }
+
+    template <typename S>
+    int step_typed(const std::vector<ffserve::Request*>& rs, int slot) {
+        char* h = static_cast<char*>(h_tab[slot]);
+        char* d = static_cast<char*>(d_tab[slot]);
+        const size_t o1 = align_up(MAX_ACTIVE * sizeof(GroupDiag));
+        const size_t o2 = o1 + align_up(MAX_ACTIVE * sizeof(GroupTrsm));
+        GroupDiag* hd = reinterpret_cast<GroupDiag*>(h);
+        GroupTrsm* ht = reinterpret_cast<GroupTrsm*>(h + o1);
+        GroupUpd* hu = reinterpret_cast<GroupUpd*>(h + o2);
+        int nd = 0, nt = 0, nu = 0, wg = 0, tiles = 0;
+        const int rows_wg = trsm_rows_per_wg(), ut = grouped_update_tile();
+        for (ffserve::Request* r : rs) {
+            const int n = r->n, c0 = r->c0, w = std::min(r->s, n - c0), m = n - c0 - w;
+            S* L = reinterpret_cast<S*>(factor_ptr(r->f));
+            int* info = d_info + r->f->info_slot;
+            S* A11 = L + c0 + (int64_t)c0 * n;
+            hd[nd++] = GroupDiag{A11, n, w, c0, info};
+            if (m > 0) {
+                S* A21 = L + (c0 + w) + (int64_t)c0 * n;
+                const int nwg = std::min((m + rows_wg - 1) / rows_wg, 64);
+                ht[nt++] = GroupTrsm{A21, A11, n, m, w, wg, nwg, info};
+                wg += nwg;
+                const int nb = (m + ut - 1) / ut;
+                hu[nu++] = GroupUpd{L + (c0 + w) + (int64_t)(c0 + w) * n, A21, n, m, w, tiles, info};
+                tiles += nb * (nb + 1) / 2;
+            }
+        }
+        if (nd == 0) return 0;
+        if (hipMemcpyAsync(d, h, TAB_BYTES, hipMemcpyHostToDevice, st) != hipSuccess) return FF_ERR_HIP;
+        if (launch_potrf_grouped<S>(nd, reinterpret_cast<const GroupDiag*>(d), st) != hipSuccess ||
+            launch_trsm_grouped<S>(nt, wg, reinterpret_cast<const GroupTrsm*>(d + o1), st) != hipSuccess ||
+            launch_update_grouped<S>(nu, tiles, reinterpret_cast<const GroupUpd*>(d + o2), st) != hipSuccess)
+            return FF_ERR_HIP;
+        return 0;
+    }
+    int step(const std::vector<ffserve::Request*>& rs, int slot) override {
+        return dtype == FF_F64 ? step_typed<double>(rs, slot) : step_typed<float>(rs, slot);
+    }
+
+    int factor_done(ffserve::Request* r) override {
+        const int k = r->f->info_slot;
+        return hipMemcpyAsync(h_info + k, d_info + k, sizeof(int), hipMemcpyDeviceToHost, st) == hipSuccess ? 0
+                                                                                                          : FF_ERR_HIP;
+    }
+
+    SolveWs ws_of(const ffserve::Request* r) const { return carve(base + r->ws_off, r->n, r->nrhs, dtype); }
+
+    int solve(ffserve::Request* r) override {
+        const int n = r->n, nrhs = r->nrhs;
+        if (dtype == FF_F64) {
+            const double* L = reinterpret_cast<const double*>(factor_ptr(r->f));
+            if (hipMemcpy2DAsync(r->X, (size_t)r->ldx * sizeof(double), r->B, (size_t)r->ldb * sizeof(double),
+                                 (size_t)n * sizeof(double), nrhs, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return FF_ERR_HIP;
+            return chol_trisolve(n, nrhs, L, n, FF_F64, r->X, r->ldx, base + r->ws_off, r->ws_bytes, st);
+        }
+        const SolveWs w = ws_of(r);
+        const float* W = reinterpret_cast<const float*>(factor_ptr(r->f));
+        const TriWs<float> tri{w.ctl, static_cast<float*>(w.fac), static_cast<float*>(w.pub)};
+        if (launch_set_int(w.ctl, 0, st) != hipSuccess ||
+            launch_convert_from_f64<float>(n, nrhs, r->B, r->ldb, w.D, n, st) != hipSuccess ||
+            trisolve_impl<float>(n, nrhs, W, n, w.D, n, tri, true, st) != hipSuccess ||
+            launch_widen<float>(n, nrhs, w.D, n, r->X, r->ldx, st) != hipSuccess)
+            return FF_ERR_HIP;
+        return refine(r);
+    }
+
+    // One binary64 refinement iteration, then its correction norms to the host.
+    int refine(ffserve::Request* r) override {
+        const int n = r->n, nrhs = r->nrhs;
+        const SolveWs w = ws_of(r);
+        const float* W = reinterpret_cast<const float*>(factor_ptr(r->f));
+        const TriWs<float> tri{w.ctl, static_cast<float*>(w.fac), static_cast<float*>(w.pub)};
+        Handles* h = static_cast<Handles*>(r->dev);
+        if (launch_residual_f64(n, nrhs, r->A, r->lda, r->X, r->ldx, r->B, r->ldb, w.R, n, nullptr, w.rpart, st) !=
+                hipSuccess ||
+            launch_convert_from_f64<float>(n, nrhs, w.R, n, w.D, n, st) != hipSuccess ||
+            trisolve_impl<float>(n, nrhs, W, n, w.D, n, tri, false, st) != hipSuccess ||
+            launch_axpy_max<float>(n, nrhs, w.D, n, r->X, r->ldx, w.norms, st) != hipSuccess ||
+            hipMemcpyAsync(h_slot[r->slot].norms, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipEventRecord(h->t_check, st) != hipSuccess)
+            return FF_ERR_HIP;
+        return 0;
+    }
+
+    int refine_poll(ffserve::Request* r, bool* ready, double* corr) override {
+        Handles* h = static_cast<Handles*>(r->dev);
+        const hipError_t e = hipEventQuery(h->t_check);
+        if (e == hipErrorNotReady) {
+            *ready = false;
+            return 0;
+        }
+        if (e != hipSuccess) return FF_ERR_HIP;
+        const HostSlot& hs = h_slot[r->slot];
+        *ready = true;
+        *corr = hs.norms[1] > 0.0 ? hs.norms[0] / hs.norms[1] : hs.norms[0];
+        return 0;
+    }
+
+    int finish(ffserve::Request* r) override {
+        Handles* h = static_cast<Handles*>(r->dev);
+        const int* err = dtype == FF_F64 ? reinterpret_cast<const int*>(base + r->ws_off) : ws_of(r).ctl;
+        if (hipMemcpyAsync(&h_slot[r->slot].err, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipEventRecord(h->t_done, st) != hipSuccess)
+            return FF_ERR_HIP;
+        return 0;
+    }
+
+    bool finished(ffserve::Request* r) override {
+        return hipEventQuery(static_cast<Handles*>(r->dev)->t_done) == hipSuccess;
+    }
+
+    int info(const ffserve::Factor* f, const ffserve::Request* r) override {
+        if (h_slot[r->slot].err != 0) return FF_ERR_HIP;
+        return h_info[f->info_slot];
+    }
+
+    double latency_ms(ffserve::Request* r) override {
+        Handles* h = static_cast<Handles*>(r->dev);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, h->t_arrive, h->t_done);
+        return (double)ms;
+    }
+
+    void release(ffserve::Request* r) override {
+        Handles* h = static_cast<Handles*>(r->dev);
+        if (!h) return;
+        if (h->t_arrive) (void)hipEventDestroy(h->t_arrive);
+        if (h->t_done) (void)hipEventDestroy(h->t_done);
+        if (h->t_check) (void)hipEventDestroy(h->t_check);
+        delete h;
+        r->dev = nullptr;
+    }
+
+    int slot_wait(int slot) override { return hipEventSynchronize(tab_ev[slot]) == hipSuccess ? 0 : FF_ERR_HIP; }
+    int slot_done(int slot) override { return hipEventRecord(tab_ev[slot], st) == hipSuccess ? 0 : FF_ERR_HIP; }
+};
 
 }  // namespace
 }  // namespace ff
@@ -119,161 +300,33 @@ int default_step(int n) {
 using namespace ff;
 
 struct ff_server {
-    hipStream_t st = nullptr;      // all server work
-    hipStream_t clock = nullptr;   // idle stream: arrival stamps
-    char* base = nullptr;
-    Arena arena;
-    std::list<Request*> queue;     // not yet admitted
-    std::vector<Request*> active;
-    std::list<Factor*> resident;   // ready keyed factors, front = most recently used
-    std::map<uint64_t, Factor*> by_key;
-    std::vector<Factor*> factors;  // every live factor
-    int64_t next_id = 1;
-    // info words: device and a pinned host mirror
-    int* d_info = nullptr;
-    int* h_info = nullptr;
-    std::vector<int> free_info;
-    // job tables: pinned host + device, RING slots
-    void* h_tab[RING] = {};
-    void* d_tab[RING] = {};
-    hipEvent_t tab_ev[RING] = {};
-    int tab_used[RING] = {};
-    int64_t steps = 0;
-    ff_server_stats stats{};
+    HipExecutor ex;
+    ffserve::Scheduler* sched = nullptr;
 };
-
-namespace {
-
-constexpr size_t TAB_BYTES = MAX_ACTIVE * (sizeof(GroupDiag) + sizeof(GroupTrsm) + sizeof(GroupUpd)) + 3 * ALIGN;
-
-void drop_factor(ff_server* s, Factor* f) {
-    s->arena.release(f->off, f->bytes);
-    if (f->info_slot >= 0) s->free_info.push_back(f->info_slot);
-    if (f->key) {
-        auto it = s->by_key.find(f->key);
-        if (it != s->by_key.end() && it->second == f) s->by_key.erase(it);
-    }
-    s->resident.remove(f);
-    s->factors.erase(std::remove(s->factors.begin(), s->factors.end(), f), s->factors.end());
-    delete f;
-}
-
-// Drop the least recently used resident factor no request is using.
-bool evict_one(ff_server* s) {
-    Factor* victim = nullptr;
-    for (auto it = s->resident.rbegin(); it != s->resident.rend(); ++it)
-        if ((*it)->users == 0) { victim = *it; break; }
-    if (!victim) return false;
-    drop_factor(s, victim);
-    s->stats.evictions++;
-    return true;
-}
-
-// Space for n bytes, evicting unused resident factors, oldest first.
-bool make_room(ff_server* s, size_t bytes, size_t& off) {
-    while (!s->arena.alloc(bytes, off))
-        if (!evict_one(s)) return false;
-    return true;
-}
-
-// Admit queued requests in arrival order while space allows.
-int admit(ff_server* s) {
-    while (!s->queue.empty() && (int)s->active.size() < MAX_ACTIVE) {
-        Request* r = s->queue.front();
-        const size_t ws = ff_trisolve_workspace_size(r->n, FF_F64);
-        Factor* f = nullptr;
-        bool owner = false;
-        auto it = r->key ? s->by_key.find(r->key) : s->by_key.end();
-        if (it != s->by_key.end() && it->second->n == r->n) {
-            f = it->second;
-        } else {
-            if (s->free_info.empty() && !evict_one(s)) break;
-            f = new (std::nothrow) Factor{r->key, r->n, 0, (size_t)r->n * r->n * sizeof(double)};
-            if (!f) return FF_ERR_HIP;
-            owner = true;
-        }
-        size_t ws_off = 0, f_off = 0;
-        f->users++;                       // keep it from being evicted below
-        if (owner && !make_room(s, f->bytes, f_off)) { f->users--; delete f; break; }
-        if (owner) {
-            f->off = f_off;
-            s->factors.push_back(f);
-        }
-        if (!make_room(s, ws, ws_off)) {
-            f->users--;
-            if (owner) {
-                s->arena.release(f->off, f->bytes);
-                s->factors.pop_back();
-                delete f;
-            }
-            break;
-        }
-        s->queue.pop_front();
-        r->f = f;
-        r->owner = owner;
-        r->ws_off = ws_off;
-        r->ws_bytes = ws;
-        if (owner) {
-            f->info_slot = s->free_info.back();
-            s->free_info.pop_back();
-            if (f->key) s->by_key[f->key] = f;
-            // the factor starts as a copy of A (lower triangle read), info = 0
-            double* L = reinterpret_cast<double*>(s->base + f->off);
-            if (hipMemcpy2DAsync(L, (size_t)r->n * sizeof(double), r->A, (size_t)r->lda * sizeof(double),
-                                 (size_t)r->n * sizeof(double), r->n, hipMemcpyDeviceToDevice, s->st) != hipSuccess ||
-                launch_set_int(s->d_info + f->info_slot, 0, s->st) != hipSuccess)
-                return FF_ERR_HIP;
-            r->st = FACTOR;
-            r->s = default_step(r->n);
-            r->c0 = 0;
-        } else {
-            r->hit = true;
-            r->st = f->ready ? SOLVE : WAIT_FACTOR;
-            if (f->ready) {
-                s->resident.remove(f);
-                s->resident.push_front(f);
-            }
-            s->stats.cache_hits++;
-        }
-        s->active.push_back(r);
-    }
-    return 0;
-}
-
-int launch_solve(ff_server* s, Request* r) {
-    const double* L = reinterpret_cast<const double*>(s->base + r->f->off);
-    if (hipMemcpy2DAsync(r->X, (size_t)r->ldx * sizeof(double), r->B, (size_t)r->ldb * sizeof(double),
-                         (size_t)r->n * sizeof(double), r->nrhs, hipMemcpyDeviceToDevice, s->st) != hipSuccess)
-        return FF_ERR_HIP;
-    const int rc = chol_trisolve(r->n, r->nrhs, L, r->n, FF_F64, r->X, r->ldx, s->base + r->ws_off, r->ws_bytes, s->st);
-    if (rc) return rc;
-    if (hipEventRecord(r->t_done, s->st) != hipSuccess) return FF_ERR_HIP;
-    r->st = DONE;
-    return 0;
-}
-
-}  // namespace
 
 extern "C" {
 
-ff_server* ff_server_create(void* arena, size_t arena_bytes, void* stream, int* status) {
+ff_server* ff_server_create(void* arena, size_t arena_bytes, int dtype, void* stream, int* status) {
     int rc = 0;
-    ff_server* s = new (std::nothrow) ff_server();
-    if (!s) rc = FF_ERR_HIP;
-    if (!rc && arena_bytes > 0 && arena == nullptr) rc = -1;
+    if (arena_bytes > 0 && arena == nullptr) rc = -1;
+    if (!rc && dtype != FF_F64 && dtype != FF_F32) rc = dtype == FF_BF16 ? FF_ERR_UNSUPPORTED : -3;
+    ff_server* s = nullptr;
     if (!rc) {
-        s->st = static_cast<hipStream_t>(stream);
-        s->base = static_cast<char*>(arena);
-        s->arena.init(arena_bytes);
-        if (hipStreamCreateWithFlags(&s->clock, hipStreamNonBlocking) != hipSuccess ||
-            hipMalloc(&s->d_info, MAX_FACTORS * sizeof(int)) != hipSuccess ||
-            hipHostMalloc(&s->h_info, MAX_FACTORS * sizeof(int)) != hipSuccess)
-            rc = FF_ERR_HIP;
-        for (int i = 0; !rc && i < RING; ++i)
-            if (hipHostMalloc(&s->h_tab[i], TAB_BYTES) != hipSuccess || hipMalloc(&s->d_tab[i], TAB_BYTES) != hipSuccess ||
-                hipEventCreateWithFlags(&s->tab_ev[i], hipEventDisableTiming) != hipSuccess)
-                rc = FF_ERR_HIP;
-        for (int i = MAX_FACTORS - 1; i >= 0; --i) s->free_info.push_back(i);
+        s = new (std::nothrow) ff_server();
+        if (!s) rc = FF_ERR_HIP;
+    }
+    if (!rc) rc = s->ex.init(arena, stream, dtype);
+    if (!rc) {
+        ffserve::Config cfg;
+        cfg.max_active = MAX_ACTIVE;
+        cfg.max_factors = MAX_FACTORS;
+        cfg.ring = RING;
+        cfg.step_cols = LDS_DIAG_MAX;
+        cfg.refine = dtype != FF_F64;
+        cfg.tol = 1e-12;
+        cfg.max_iter = 30;
+        s->sched = new (std::nothrow) ffserve::Scheduler(&s->ex, arena_bytes, cfg);
+        if (!s->sched) rc = FF_ERR_HIP;
     }
     if (status) *status = rc;
     if (rc && s) {
@@ -285,18 +338,8 @@ ff_server* ff_server_create(void* arena, size_t arena_bytes, void* stream, int* 
 
 int ff_server_destroy(ff_server* s) {
     if (!s) return 0;
-    if (s->st) (void)hipStreamSynchronize(s->st);
-    for (Request* r : s->active) { (void)hipEventDestroy(r->t_arrive); (void)hipEventDestroy(r->t_done); delete r; }
-    for (Request* r : s->queue) { (void)hipEventDestroy(r->t_arrive); (void)hipEventDestroy(r->t_done); delete r; }
-    for (Factor* f : s->factors) delete f;
-    for (int i = 0; i < RING; ++i) {
-        if (s->h_tab[i]) (void)hipHostFree(s->h_tab[i]);
-        if (s->d_tab[i]) (void)hipFree(s->d_tab[i]);
-        if (s->tab_ev[i]) (void)hipEventDestroy(s->tab_ev[i]);
-    }
-    if (s->d_info) (void)hipFree(s->d_info);
-    if (s->h_info) (void)hipHostFree(s->h_info);
-    if (s->clock) (void)hipStreamDestroy(s->clock);
+    if (s->ex.st) (void)hipStreamSynchronize(s->ex.st);
+    delete s->sched;
     delete s;
     return 0;
 }
@@ -308,146 +351,44 @@ int ff_server_submit(ff_server* s, uint64_t key, int64_t n, const double* A, int
     if (!A) return -4;
     if (lda < n) return -5;
     if (!B) return -6;
-    if (nrhs < 1) return -7;
+    if (nrhs < 1 || nrhs > 65536) return -7;
     if (ldb < n) return -8;
     if (!X) return -9;
     if (ldx < n) return -10;
-    const size_t need = align_up((size_t)n * n * sizeof(double)) + align_up(ff_trisolve_workspace_size(n, FF_F64));
-    if (need > s->arena.size) return FF_ERR_WORKSPACE;
-    Request* r = new (std::nothrow) Request();
-    if (!r) return FF_ERR_HIP;
-    *r = Request{s->next_id++, key, (int)n, (int)nrhs, A, lda, B, ldb, X, ldx};
-    if (hipEventCreate(&r->t_arrive) != hipSuccess || hipEventCreate(&r->t_done) != hipSuccess ||
-        hipEventRecord(r->t_arrive, s->clock) != hipSuccess) {
-        delete r;
-        return FF_ERR_HIP;
-    }
-    s->queue.push_back(r);
-    s->stats.submitted++;
-    if (req_id) *req_id = r->id;
-    return 0;
+    return s->sched->submit(key, (int)n, A, lda, B, (int)nrhs, ldb, X, ldx, req_id);
 }
 
 int ff_server_step(ff_server* s) {
     if (!s) return -1;
-    // a job-table slot is reused only after the step that last used it has run
-    const int slot = (int)(s->steps % RING);
-    if (s->tab_used[slot] && hipEventSynchronize(s->tab_ev[slot]) != hipSuccess) return FF_ERR_HIP;
-    int rc = admit(s);
-    if (rc) return rc;
-    // nothing running and the oldest request still not admitted: it cannot be
-    // (fragmented arena with every factor in use cannot happen when nothing is
-    // active, so this is a broken invariant, reported instead of spinning)
-    if (s->active.empty() && !s->queue.empty()) return FF_ERR_WORKSPACE;
-
-    // requests waiting on a factor another request computes
-    for (Request* r : s->active)
-        if (r->st == WAIT_FACTOR && r->f->ready) r->st = SOLVE;
-
-    // one block step of every active factorisation, three grouped launches
-    char* h = static_cast<char*>(s->h_tab[slot]);
-    char* d = static_cast<char*>(s->d_tab[slot]);
-    GroupDiag* hd = reinterpret_cast<GroupDiag*>(h);
-    GroupTrsm* ht = reinterpret_cast<GroupTrsm*>(h + align_up(MAX_ACTIVE * sizeof(GroupDiag)));
-    GroupUpd* hu = reinterpret_cast<GroupUpd*>(h + align_up(MAX_ACTIVE * sizeof(GroupDiag)) +
-                                               align_up(MAX_ACTIVE * sizeof(GroupTrsm)));
-    int nd = 0, nt = 0, nu = 0, wg = 0, tiles = 0;
-    const int rows_wg = trsm_rows_per_wg(), ut = grouped_update_tile();
-    std::vector<Request*> stepped;
-    for (Request* r : s->active) {
-        if (r->st != FACTOR) continue;
-        const int n = r->n, c0 = r->c0, w = std::min(r->s, n - c0), m = n - c0 - w;
-        double* L = reinterpret_cast<double*>(s->base + r->f->off);
-        int* info = s->d_info + r->f->info_slot;
-        double* A11 = L + c0 + (int64_t)c0 * n;
-        hd[nd++] = GroupDiag{A11, n, w, c0, info};
-        if (m > 0) {
-            double* A21 = L + (c0 + w) + (int64_t)c0 * n;
-            const int nwg = std::min((m + rows_wg - 1) / rows_wg, 64);
-            ht[nt++] = GroupTrsm{A21, A11, n, m, w, wg, nwg, info};
-            wg += nwg;
-            const int nb = (m + ut - 1) / ut;
-            hu[nu++] = GroupUpd{L + (c0 + w) + (int64_t)(c0 + w) * n, A21, n, m, w, tiles, info};
-            tiles += nb * (nb + 1) / 2;
-        }
-        stepped.push_back(r);
-    }
-    if (nd > 0) {
-        if (hipMemcpyAsync(d, h, TAB_BYTES, hipMemcpyHostToDevice, s->st) != hipSuccess) return FF_ERR_HIP;
-        const GroupDiag* dd = reinterpret_cast<const GroupDiag*>(d);
-        const GroupTrsm* dt = reinterpret_cast<const GroupTrsm*>(d + align_up(MAX_ACTIVE * sizeof(GroupDiag)));
-        const GroupUpd* du = reinterpret_cast<const GroupUpd*>(d + align_up(MAX_ACTIVE * sizeof(GroupDiag)) +
-                                                               align_up(MAX_ACTIVE * sizeof(GroupTrsm)));
-        if (launch_potrf_grouped(nd, dd, s->st) != hipSuccess || launch_trsm_grouped(nt, wg, dt, s->st) != hipSuccess ||
-            launch_update_grouped(nu, tiles, du, s->st) != hipSuccess)
-            return FF_ERR_HIP;
-        s->stats.grouped_launches += 3;
-    }
-    for (Request* r : stepped) {
-        r->c0 += std::min(r->s, r->n - r->c0);
-        if (r->c0 >= r->n) {
-            // factor finished: its info word goes to the host mirror, then the solve
-            if (hipMemcpyAsync(s->h_info + r->f->info_slot, s->d_info + r->f->info_slot, sizeof(int),
-                               hipMemcpyDeviceToHost, s->st) != hipSuccess)
-                return FF_ERR_HIP;
-            r->f->ready = true;
-            if (r->f->key) s->resident.push_front(r->f);
-            else r->f->dead = true;
-            r->st = SOLVE;
-        }
-    }
-    for (Request* r : s->active)
-        if (r->st == SOLVE && (rc = launch_solve(s, r)) != 0) return rc;
-    if (hipEventRecord(s->tab_ev[slot], s->st) != hipSuccess) return FF_ERR_HIP;
-    s->tab_used[slot] = 1;
-    s->steps++;
-    s->stats.steps = s->steps;
-    int inflight = 0;
-    for (Request* r : s->active) inflight += r->st != DONE;
-    return inflight + (int)s->queue.size();
+    return s->sched->step();
 }
 
 int ff_server_poll(ff_server* s, ff_server_result* out, int max_out, int* n_out) {
     if (!s) return -1;
     if (max_out < 0 || (max_out > 0 && !out)) return -2;
+    std::vector<ffserve::Result> res((size_t)max_out);
     int k = 0;
-    for (size_t i = 0; i < s->active.size() && k < max_out;) {
-        Request* r = s->active[i];
-        if (r->st != DONE || hipEventQuery(r->t_done) != hipSuccess) { ++i; continue; }
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, r->t_arrive, r->t_done);
-        Factor* f = r->f;
-        const int info = s->h_info[f->info_slot];
-        out[k++] = ff_server_result{r->id, info, r->hit ? 1 : 0, (double)ms};
-        s->arena.release(r->ws_off, r->ws_bytes);
-        f->users--;
-        if (info != 0 && !f->dead) {
-            // a failed factor is never served again
-            f->dead = true;
-            s->resident.remove(f);
-            auto it = s->by_key.find(f->key);
-            if (it != s->by_key.end() && it->second == f) s->by_key.erase(it);
-        }
-        if (f->dead && f->users == 0) drop_factor(s, f);
-        (void)hipEventDestroy(r->t_arrive);
-        (void)hipEventDestroy(r->t_done);
-        delete r;
-        s->active.erase(s->active.begin() + i);
-        s->stats.completed++;
-    }
+    const int rc = s->sched->poll(res.data(), max_out, &k);
+    for (int i = 0; i < k; ++i)
+        out[i] = ff_server_result{res[i].id, res[i].info, res[i].cache_hit, res[i].latency_ms, res[i].iters,
+                                  res[i].converged};
     if (n_out) *n_out = k;
-    return 0;
+    return rc;
 }
 
 int ff_server_get_stats(ff_server* s, ff_server_stats* out) {
     if (!s || !out) return -1;
-    *out = s->stats;
-    size_t fr = 0;
-    for (auto& kv : s->arena.free_) fr += kv.second;
-    out->arena_free = (int64_t)fr;
-    out->resident_factors = (int64_t)s->resident.size();
-    out->queued = (int64_t)s->queue.size();
-    out->active = (int64_t)s->active.size();
+    const ffserve::Stats& st = s->sched->stats();
+    out->submitted = st.submitted;
+    out->completed = st.completed;
+    out->steps = st.steps;
+    out->grouped_launches = st.grouped_launches;
+    out->cache_hits = st.cache_hits;
+    out->evictions = st.evictions;
+    out->arena_free = (int64_t)s->sched->arena_free();
+    out->resident_factors = (int64_t)s->sched->resident_count();
+    out->queued = (int64_t)s->sched->queued_count();
+    out->active = (int64_t)s->sched->active_count();
     return 0;
 }
 

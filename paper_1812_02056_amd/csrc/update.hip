@@ -312,12 +312,13 @@ void update_wide_tail_kernel(int M, int N, int K, T* __restrict__ C, int64_t ldc
 // Grouped trailing updates (many independent matrices, serving): the lower
 // 128 x 128 tiles of every job form one flat queue; a workgroup finds its job by
 // binary search over the tile offsets and runs the same tile body.
+template <typename S>
 __global__ __launch_bounds__(256, 2)
 void update_grouped_kernel(const GroupUpd* __restrict__ jobs, int njobs, int ntiles)
 {
-    typedef wide_cfg<double, 64, 2> CF;
-    __shared__ double As[2][CF::BK][CF::TM];
-    __shared__ double Bs[2][CF::BK][CF::TN];
+    typedef wide_cfg<S, 64, 2> CF;
+    __shared__ S As[2][CF::BK][CF::TM];
+    __shared__ S Bs[2][CF::BK][CF::TN];
     for (int slot = blockIdx.x; slot < ntiles; slot += gridDim.x) {
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
@@ -329,7 +330,8 @@ void update_grouped_kernel(const GroupUpd* __restrict__ jobs, int njobs, int nti
         if (jb.info && *jb.info != 0) continue;
         const int t = slot - jb.tiles_begin;
         const int bi = tri_row(t), bj = t - bi * (bi + 1) / 2;
-        wide_tile<double, 64, 2, true, true>(jb.m, jb.m, jb.w, jb.c, jb.ld, jb.p, jb.ld, jb.p, jb.ld, 0, bi, bj, As, Bs);
+        wide_tile<S, 64, 2, true, true>(jb.m, jb.m, jb.w, static_cast<S*>(jb.c), jb.ld, static_cast<const S*>(jb.p),
+                                        jb.ld, static_cast<const S*>(jb.p), jb.ld, 0, bi, bj, As, Bs);
     }
 }
 
@@ -578,13 +580,16 @@ hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int
 
 int grouped_update_tile() { return 128; }
 
+template <typename S>
 hipError_t launch_update_grouped(int njobs, int total_tiles, const GroupUpd* d_jobs, hipStream_t st) {
     if (njobs <= 0 || total_tiles <= 0) return hipSuccess;
     int nwg = 2 * update_workers(0);
     if (nwg > total_tiles) nwg = total_tiles;
-    hipLaunchKernelGGL(update_grouped_kernel, dim3(nwg), dim3(256), 0, st, d_jobs, njobs, total_tiles);
+    hipLaunchKernelGGL((update_grouped_kernel<S>), dim3(nwg), dim3(256), 0, st, d_jobs, njobs, total_tiles);
     return hipGetLastError();
 }
+template hipError_t launch_update_grouped<double>(int, int, const GroupUpd*, hipStream_t);
+template hipError_t launch_update_grouped<float>(int, int, const GroupUpd*, hipStream_t);
 
 hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const float* X, int64_t ldx,
                               const float* Y, int64_t ldy, bool lower, int shift, const int* info, hipStream_t st,

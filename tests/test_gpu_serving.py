@@ -5,9 +5,12 @@ Each request must give exactly the result of the single-matrix path with the
 same step size: the grouped launches run the same per-block kernels (diagonal
 factorisation, panel solve) and the same per-tile update body with the same
 accumulation order, so the factor and the solution are bitwise equal to
-chol_factor + chol_trisolve on the request alone.  Against the oracle the
-tolerances are those of the binary64 path (fwd_x <= 1e-12 at kappa ~ 5, bitwise
-on the integer family).
+chol_factor + chol_trisolve on the request alone (binary64 server), or to
+chol_solve with a binary32 factor, refinement tolerance 1e-12 and at most 30
+iterations (binary32 server: the same refinement kernels and the same stop
+rule, so also the same iteration count).  Against the oracle the tolerances are
+those of the binary64 path (fwd_x <= 1e-12 at kappa ~ 5, bitwise on the integer
+family).
 """
 import numpy as np
 import pytest
@@ -46,6 +49,14 @@ def alone(A, B):
     return host(X), info
 
 
+def alone_f32(A, B):
+    """The single-matrix binary32 + refinement path with the server's step and stop rule."""
+    n = A.shape[0]
+    X, _, info = ff.chol_solve(dev(A), dev(B), min(n, 192), dtype="f32", tol=1e-12, max_iter=30)
+    torch.cuda.synchronize()
+    return host(X), info
+
+
 def drain(srv, limit=100000):
     out = {}
     for _ in range(limit):
@@ -69,10 +80,11 @@ def arena(nbytes):
     return torch.empty(nbytes // 8 + 1, dtype=torch.float64, device=DEV)
 
 
-def test_server_mix_matches_single_path_bitwise():
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_server_mix_matches_single_path_bitwise(dtype):
     sizes = [64, 300, 513, 129, 1000, 256, 777]
     reqs = []
-    srv = ff.Server(arena(1 << 30))
+    srv = ff.Server(arena(1 << 30), dtype=dtype)
     for i, n in enumerate(sizes):
         A = wl.spd_scaled(n, seed=100 + i)
         B = wl.rhs(n, 1 + i % 5, seed=200 + i)
@@ -85,8 +97,14 @@ def test_server_mix_matches_single_path_bitwise():
     for rid, A, B, Xd in reqs:
         assert done[rid]["info"] == 0
         assert not done[rid]["cache_hit"]
-        Xa, info = alone(A, B)
-        assert info == 0
+        if dtype == "f64":
+            Xa, info = alone(A, B)
+            assert info == 0
+        else:
+            Xa, sinfo = alone_f32(A, B)
+            assert sinfo["info"] == 0
+            assert done[rid]["iters"] == sinfo["iters"] and done[rid]["converged"] == bool(sinfo["converged"])
+            assert done[rid]["converged"]
         assert np.array_equal(host(Xd), Xa), rid
         Lo, _ = oracle.chol(A)
         assert oracle.fwd_x(host(Xd), oracle.chol_solve(Lo, B)) <= 1e-12
@@ -95,11 +113,12 @@ def test_server_mix_matches_single_path_bitwise():
     srv.close()
 
 
-def test_server_repeat_key_is_a_cache_hit():
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_server_repeat_key_is_a_cache_hit(dtype):
     n = 640
     A = wl.spd_scaled(n, seed=7)
     Ad = dev(A)
-    srv = ff.Server(arena(1 << 28))
+    srv = ff.Server(arena(1 << 28), dtype=dtype)
     B1, B2 = wl.rhs(n, 3, seed=8), wl.rhs(n, 2, seed=9)
     B1d = dev(B1)
     X1 = torch.zeros_like(B1d)
@@ -114,9 +133,34 @@ def test_server_repeat_key_is_a_cache_hit():
     assert d1[r1]["info"] == 0 and not d1[r1]["cache_hit"]
     assert d2[r2]["info"] == 0 and d2[r2]["cache_hit"]
     assert srv.stats()["grouped_launches"] == steps_before      # no block step ran for the hit
-    Xa, _ = alone(A, B2)
+    Xa, _ = alone(A, B2) if dtype == "f64" else alone_f32(A, B2)
     assert np.array_equal(host(X2), Xa)
     srv.close()
+
+
+def test_server_f32_mixed_sizes_and_conditioning_against_oracle():
+    # binary32 factors refined in binary64: every result within the binary64 tolerance
+    srv = ff.Server(arena(1 << 30), dtype="f32")
+    cases = []
+    for i, (n, lam) in enumerate(((333, 1.0), (700, 1e-2), (1024, 1e-3), (95, 1.0))):
+        A = wl.spd_scaled(n, seed=80 + i, lam=lam)
+        B = wl.rhs(n, 1 + i, seed=90 + i)
+        Bd = dev(B)
+        Xd = torch.zeros_like(Bd)
+        cases.append((srv.submit(dev(A), Bd, Xd, key=300 + i), A, B, Xd))
+    done = drain(srv)
+    for rid, A, B, Xd in cases:
+        assert done[rid]["info"] == 0 and done[rid]["iters"] >= 1
+        Lo, _ = oracle.chol(A)
+        Xo = oracle.chol_solve(Lo, B)
+        assert oracle.bwd_x(A, host(Xd), B) <= 1e-15
+        assert oracle.fwd_x(host(Xd), Xo) <= 1e-12
+    srv.close()
+
+
+def test_server_bf16_is_not_served():
+    with pytest.raises(ff.FastFactError):
+        ff.Server(arena(1 << 20), dtype="bf16")
 
 
 def test_server_non_spd_reports_info_and_spares_the_others():
