@@ -58,6 +58,10 @@ def _load():
         lib.oracle_syrk_update.restype = None
         lib.oracle_gemm_update.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64]
         lib.oracle_gemm_update.restype = None
+        lib.oracle_qr_alg3.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int)]
+        lib.oracle_qr_alg3.restype = i64
+        lib.oracle_qr_project.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64]
+        lib.oracle_qr_project.restype = None
         lib.oracle_round_f32.argtypes = [ctypes.c_double]
         lib.oracle_round_f32.restype = ctypes.c_double
         lib.oracle_round_bf16.argtypes = [ctypes.c_double]
@@ -159,6 +163,35 @@ def gemm_update(C, X, Y):
     m, w = X.shape
     _load().oracle_gemm_update(m, w, _p(C), max(m, 1), _p(X), max(m, 1), _p(Y), max(w, 1))
     return C
+
+
+def qr_alg3(A, s: int):
+    """Algorithm 3 (Sec. 2) with step s on an m x n matrix (m >= n).
+    Returns (Q, R, block_projections, info); R = Q^T A in full."""
+    A = _colmajor(A)
+    m, n = A.shape
+    if m < n:
+        raise ValueError("qr_alg3 needs m >= n")
+    Q = np.zeros((m, n), order="F")
+    R = np.zeros((n, n), order="F")
+    info = ctypes.c_int(0)
+    k = _load().oracle_qr_alg3(m, n, int(s), _p(A), max(1, m), _p(Q), max(1, m), _p(R), max(1, n),
+                               ctypes.byref(info))
+    if k < 0:
+        raise MemoryError("oracle_qr_alg3")
+    return Q, R, int(k), int(info.value)
+
+
+def qr_project(Bq, Bm):
+    """One block projection of Algorithm 3 (Sec. 2): C = Bq^T Bm, Bm - Bq C.
+    Returns (Bm_new, C)."""
+    Bq = _colmajor(Bq)
+    Bm = _colmajor(Bm)
+    m, w = Bq.shape
+    k = Bm.shape[1]
+    C = np.zeros((w, k), order="F")
+    _load().oracle_qr_project(m, w, k, _p(Bq), max(1, m), _p(Bm), max(1, m), _p(C), max(1, w))
+    return Bm, C
 
 
 def round_f32(x):

@@ -7,7 +7,7 @@
  * threads; each row's arithmetic is unchanged, so the results are bitwise the
  * same for any thread count.
  *
- * Paper: C. Camarero, arXiv 1812.02056 (Sec. 2: Algorithms 1 and 2 and the
+ * Paper: C. Camarero, arXiv 1812.02056 (Sec. 2: Algorithms 1, 2 and 3 and the
  * discussion of their special cases s = 1 and s = n).
  */
 #include "oracle.h"
@@ -316,6 +316,104 @@ void oracle_gemm_update(int64_t m, int64_t w, double *C, int64_t ldc,
             for (int64_t k = 0; k < w; ++k) t += X[IDX(i, k, ldx)] * Y[IDX(k, j, ldy)];
             C[IDX(i, j, ldc)] -= t;
         }
+}
+
+/*
+ * The block projection of Algorithm 3 (Sec. 2): with the finished columns
+ * Bq = Q[:, z..c-1] (w of them) and the columns still to come Bm = M[:, c..n],
+ *     C = Bq^T Bm          (w x k; each entry a sum over the m rows, ascending)
+ *     S = Bq C, Bm -= S    (each entry of S a sum over the w columns, ascending)
+ * Columns of Bm are independent, so they are spread over threads.
+ */
+void oracle_qr_project(int64_t m, int64_t w, int64_t k, const double *Bq, int64_t ldq,
+                       double *Bm, int64_t ldm, double *C, int64_t ldc)
+{
+#pragma omp parallel
+    {
+        double *cj = (double *)malloc((size_t)(w > 0 ? w : 1) * sizeof(double));
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t j = 0; j < k; ++j) {
+            double *bm = Bm + (size_t)j * (size_t)ldm;
+            for (int64_t t = 0; t < w; ++t) {
+                const double *q = Bq + (size_t)t * (size_t)ldq;
+                double d = 0.0;
+                for (int64_t i = 0; i < m; ++i) d += q[i] * bm[i];
+                cj[t] = d;
+            }
+            for (int64_t i = 0; i < m; ++i) {
+                double sv = 0.0;
+                for (int64_t t = 0; t < w; ++t) sv += Bq[IDX(i, t, ldq)] * cj[t];
+                bm[i] -= sv;
+            }
+            if (C)
+                for (int64_t t = 0; t < w; ++t) C[IDX(t, j, ldc)] = cj[t];
+        }
+        free(cj);
+    }
+}
+
+/*
+ * Algorithm 3 of Sec. 2 with step s.  M starts as a copy of A and Q as zeros;
+ * z is the first column of the current block.  For c = 0, 1, ..., n-1:
+ *   - when c = z + s: project the block Q[:, z..c-1] out of M[:, c..n-1]
+ *     (oracle_qr_project) and set z = c;
+ *   - v = M[:, c]; for j = z..c-1 in order: v -= q_j (q_j^T v), the product
+ *     taken with the vector as updated so far;
+ *   - v /= ||v|| (the norm a sum of squares in row order, then sqrt; each entry
+ *     divided by it) and Q[:, c] = v.
+ * Then R = Q^T A in full.  With s = 1 every column is projected out as soon as
+ * it is finished, and with s >= n no block projection happens; the two are the
+ * right- and left-looking orderings of modified Gram-Schmidt and perform the
+ * same operations on every column.
+ */
+int64_t oracle_qr_alg3(int64_t m, int64_t n, int64_t s, const double *A, int64_t lda,
+                       double *Q, int64_t ldq, double *R, int64_t ldr, int *info)
+{
+    *info = 0;
+    if (n <= 0) return 0;
+    double *M = (double *)malloc((size_t)m * (size_t)n * sizeof(double));
+    if (!M) return -1;
+    for (int64_t j = 0; j < n; ++j)
+        memcpy(M + (size_t)j * (size_t)m, A + (size_t)j * (size_t)lda, (size_t)m * sizeof(double));
+    for (int64_t j = 0; j < n; ++j)
+        memset(Q + (size_t)j * (size_t)ldq, 0, (size_t)m * sizeof(double));
+    int64_t z = 0, projections = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        if (c == z + s) {
+            oracle_qr_project(m, c - z, n - c, Q + (size_t)z * (size_t)ldq, ldq,
+                              M + (size_t)c * (size_t)m, m, NULL, 0);
+            ++projections;
+            z = c;
+        }
+        double *v = M + (size_t)c * (size_t)m;
+        for (int64_t j = z; j < c; ++j) {
+            const double *u = Q + (size_t)j * (size_t)ldq;
+            double d = 0.0;
+            for (int64_t i = 0; i < m; ++i) d += u[i] * v[i];
+            for (int64_t i = 0; i < m; ++i) v[i] -= u[i] * d;
+        }
+        double ss = 0.0;
+        for (int64_t i = 0; i < m; ++i) ss += v[i] * v[i];
+        const double nrm = sqrt(ss);
+        if (!(nrm > 0.0)) {
+            *info = (int)(c + 1);
+            free(M);
+            return projections;
+        }
+        double *qc = Q + (size_t)c * (size_t)ldq;
+        for (int64_t i = 0; i < m; ++i) qc[i] = v[i] / nrm;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+            const double *qi = Q + (size_t)i * (size_t)ldq;
+            const double *aj = A + (size_t)j * (size_t)lda;
+            double d = 0.0;
+            for (int64_t k = 0; k < m; ++k) d += qi[k] * aj[k];
+            R[IDX(i, j, ldr)] = d;
+        }
+    free(M);
+    return projections;
 }
 
 double oracle_round_f32(double x) { return (double)(float)x; }

@@ -71,6 +71,21 @@ void oracle_gemm_update(int64_t m, int64_t w, double *C, int64_t ldc,
 /* Round a binary64 value to the nearest binary32 value (ties to even), and
  * to the nearest bfloat16 value (8-bit significand; ties to even) of its
  * binary32 rounding, both returned as binary64. */
+/* QR by Gram-Schmidt with deferred block projections (Sec. 2, Algorithm 3),
+ * for an m x n matrix A with m >= n >= 0.  Writes the m x n Q (orthonormal
+ * columns) and the full n x n product R = Q^T A (its strict lower triangle is
+ * rounding noise; the algorithm states R upper triangular).  *info = 0, or the
+ * 1-based column c whose norm after the projections is not > 0 (zero or NaN);
+ * the routine then stops: columns >= c of Q are zero and R is not written.
+ * Returns the number of block projections, floor((n-1)/s) when info = 0. */
+int64_t oracle_qr_alg3(int64_t m, int64_t n, int64_t s, const double *A, int64_t lda,
+                       double *Q, int64_t ldq, double *R, int64_t ldr, int *info);
+
+/* One block projection of Algorithm 3 (Sec. 2) on its own: C = Bq^T Bm
+ * (w x k, Bq m x w, Bm m x k), then Bm -= Bq C.  C may be NULL. */
+void oracle_qr_project(int64_t m, int64_t w, int64_t k, const double *Bq, int64_t ldq,
+                       double *Bm, int64_t ldm, double *C, int64_t ldc);
+
 double oracle_round_f32(double x);
 double oracle_round_bf16(double x);
 

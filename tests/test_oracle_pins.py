@@ -414,3 +414,121 @@ def test_generators_deterministic_and_structured():
     L0, A = wl.chol_int_family(50, seed=3)
     assert np.array_equal(A, L0 @ L0.T)
     assert wl.default_s(512) == 27 and wl.default_s(16384) == 169
+
+
+# --------------------------------------------------------------------------- QR (Algorithm 3)
+def _frac(d, key):
+    return np.array(d[key + "_num"], dtype=np.float64) / d[key + "_den"]
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 10])
+def test_golden_qr_hand_examples(golden, s):
+    for key in ("qr_2x2", "qr_3x2"):
+        d = golden[key]
+        A = np.array(d["A"], dtype=np.float64)
+        Q, R, _, info = oracle.qr_alg3(A, s)
+        assert info == 0, key
+        np.testing.assert_allclose(Q, _frac(d, "Q"), rtol=0, atol=1e-15, err_msg=key)   # a few ulps
+        np.testing.assert_allclose(R, _frac(d, "R"), rtol=0, atol=4e-15, err_msg=key)
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 9])
+def test_golden_qr_orthogonal_columns_exact(golden, s):
+    d = golden["qr_hadamard4"]
+    Q, R, k, info = oracle.qr_alg3(np.array(d["A"], dtype=np.float64), s)
+    assert info == 0 and k == 3 // s
+    assert np.array_equal(Q, _frac(d, "Q"))
+    assert np.array_equal(R, _frac(d, "R"))
+
+
+@pytest.mark.parametrize("s", [1, 2, 5])
+def test_golden_qr_zero_column(golden, s):
+    d = golden["qr_zero_column"]
+    Q, _, _, info = oracle.qr_alg3(np.array(d["A"], dtype=np.float64), s)
+    assert info == d["info"]
+    assert np.all(Q[:, d["info"] - 1:] == 0.0)
+
+
+def test_qr_nan_column_info():
+    A = wl.spd_scaled(40, seed=5)
+    A[7, 12] = np.nan
+    _, _, _, info = oracle.qr_alg3(A, 8)
+    assert info == 13
+
+
+def _lapack_qr_positive(A):
+    """LAPACK's Householder QR with the signs chosen so that diag(R) > 0: for a
+    matrix of full column rank this factorisation is unique."""
+    Ql, Rl = np.linalg.qr(A)
+    sg = np.sign(np.diag(Rl))
+    return Ql * sg, Rl * sg[:, None]
+
+
+@pytest.mark.parametrize("shape,s", [((160, 160), 1), ((160, 160), 7), ((200, 150), 32), ((200, 150), 150),
+                                     ((257, 129), 64)])
+def test_qr_matches_lapack(shape, s):
+    m, n = shape
+    A = np.random.default_rng(11).standard_normal((m, n))
+    kappa = np.linalg.cond(A)
+    Q, R, k, info = oracle.qr_alg3(A, s)
+    Ql, Rl = _lapack_qr_positive(A)
+    assert info == 0 and k == (n - 1) // s
+    tol = 64 * n * kappa * np.finfo(float).eps
+    assert np.max(np.abs(Q - Ql)) <= tol
+    assert np.max(np.abs(np.triu(R) - Rl)) <= tol * np.max(np.abs(Rl))
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 96])
+def test_qr_s1_and_s_n_are_the_same_gram_schmidt_bitwise(n):
+    """Sec. 2: s = 1 and s = n are the two classical special cases; for QR both are
+    modified Gram-Schmidt (right- and left-looking) and do the same operations."""
+    A = np.random.default_rng(12).standard_normal((n + 5, n))
+    Q1, R1, k1, _ = oracle.qr_alg3(A, 1)
+    Qn, Rn, kn, _ = oracle.qr_alg3(A, n)
+    Qb, Rb, kb, _ = oracle.qr_alg3(A, n + 40)
+    assert k1 == n - 1 and kn == 0 and kb == 0
+    assert np.array_equal(Q1, Qn) and np.array_equal(R1, Rn)
+    assert np.array_equal(Qn, Qb) and np.array_equal(Rn, Rb)
+
+
+def test_qr_in_block_projection_uses_the_updated_vector():
+    """Modified (not classical) Gram-Schmidt inside a block: on nearly dependent
+    columns MGS keeps orthogonality at about kappa * eps while classical GS loses
+    it as kappa^2 * eps; the oracle with s >= n must show the MGS level."""
+    rng = np.random.default_rng(13)
+    U, _ = np.linalg.qr(rng.standard_normal((120, 40)))
+    V, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    A = U @ np.diag(np.logspace(0, -7, 40)) @ V.T       # kappa = 1e7
+    Q, _, _, info = oracle.qr_alg3(A, 40)
+    assert info == 0
+    loss = np.max(np.abs(Q.T @ Q - np.eye(40)))
+    # classical GS on this matrix loses orthogonality completely (order one)
+    Qc = np.zeros_like(A)
+    for c in range(40):
+        v = A[:, c] - Qc[:, :c] @ (Qc[:, :c].T @ A[:, c])
+        Qc[:, c] = v / np.linalg.norm(v)
+    loss_cgs = np.max(np.abs(Qc.T @ Qc - np.eye(40)))
+    assert loss <= 1e-7 and loss_cgs > 1e-4
+
+
+@pytest.mark.parametrize("s", [1, 16, 50, 300])
+def test_qr_invariants_on_the_workload_matrix(s):
+    n = 300
+    A = wl.spd_scaled(n, seed=14)
+    Q, R, k, info = oracle.qr_alg3(A, s)
+    eps = np.finfo(float).eps
+    assert info == 0 and k == (n - 1) // s
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 8 * n * eps
+    assert np.max(np.abs(A - Q @ np.triu(R))) <= 8 * n * eps * np.max(np.abs(A))
+    assert np.max(np.abs(np.tril(R, -1))) <= 8 * n * eps * np.max(np.abs(A))
+    assert np.all(np.diag(R) > 0)
+
+
+def test_qr_project_integer_exact():
+    """C = Bq^T Bm and Bm - Bq C on values where every product and sum is exact."""
+    H = np.array([[1, 1, 1, 1], [1, -1, 1, -1], [1, 1, -1, -1], [1, -1, -1, 1]], dtype=np.float64)
+    Bq = np.kron(H, np.ones((2, 1)))[:, :3] / 4.0                      # 8 x 3, orthonormal-free scaling
+    Bm = np.random.default_rng(15).integers(-8, 9, size=(8, 5)).astype(np.float64)
+    Mn, C = oracle.qr_project(Bq, Bm.copy())
+    assert np.array_equal(C, Bq.T @ Bm)
+    assert np.array_equal(Mn, Bm - Bq @ (Bq.T @ Bm))
