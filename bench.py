@@ -63,7 +63,7 @@ def parse():
     p.add_argument("--leg", choices=("lowprec", "trisolve"), default=None,
                    help="only one leg, for profiling: the binary32 / bfloat16 factorisations, or the triangular solves")
     p.add_argument("--serving-only", action="store_true", help="only the serving leg (many independent solves)")
-    p.add_argument("--serving-requests", type=int, default=2000)
+    p.add_argument("--serving-requests", type=int, default=10000)
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy 3 times (reference kernel for HBM counter scaling)")
     return p.parse_args()
@@ -118,8 +118,7 @@ def main():
     if args.serving_only:
         from paper_1812_02056_amd import workloads as wl
         res = run_serving(ff, torch, wl, dev, nreq=args.serving_requests)
-        log(f"[bench] serving: {res}")
-        print(json.dumps({"serving_f64": res}), flush=True)
+        print(json.dumps({"serving": res}), flush=True)
         return
     n = args.n
     svals = [int(x) for x in args.s.split(",")]
@@ -363,79 +362,126 @@ def run_extras(ff, torch, wl, dev, n, A0):
 
     # --- serving: continuous batching of many independent solves
     try:
-        out["serving_f64"] = run_serving(ff, torch, wl, dev)
-        log(f"[bench] serving: {out['serving_f64']}")
+        out["serving"] = run_serving(ff, torch, wl, dev)
     except Exception as e:
-        out["serving_f64"] = {"error": str(e)}
+        out["serving"] = {"error": str(e)}
     torch.cuda.empty_cache()
     return out
 
 
-def run_serving(ff, torch, wl, dev, nreq=2000, seed=0, pool=48, window=128, rho=0.8):
-    """Continuous batching of many independent binary64 SPD solves (the serving
-    workload): sizes n = round(exp(U(ln 256, ln 8192))), nrhs ~ U{1..8}; with
-    probability 0.3 a request repeats the matrix of one of the last 64 distinct
-    ones (same key: the resident factor serves it).  Matrices come from a pool of
-    pre-generated A = G G^T/n + I (a new request gets a new key, so it is factored
-    even when its pool matrix was used before).  Closed loop (a window of
-    outstanding requests) gives the saturation rate X_max; an open loop with
-    exponential arrivals at rho * X_max gives the latency percentiles (device time
-    from the submit stamp to the end of the solve, plus any lateness of the host
-    loop behind the nominal arrival)."""
+def run_serving(ff, torch, wl, dev, nreq=10000, seed=0, window=128, rhos=(0.5, 0.8, 0.95), arena_gb=200,
+                modes=("f64", "f32"), seq_requests=2000):
+    """Continuous batching of many independent SPD solves (the serving workload):
+    nreq requests, n = round(exp(U(ln 256, ln 8192))), nrhs ~ U{1..8}; with
+    probability 0.3 a request repeats the matrix (and key) of one of the last 64
+    distinct ones, served from its resident factor.  Every distinct matrix is
+    A = G G^T / n + I from its own seed (10^6 + its index), generated just before
+    its first submission on a producer stream, up to 8 requests ahead (the
+    product in bfloat16 GEMM, rounded, then scaled and shifted in binary64 and
+    mirrored; SPD since the rounding moves eigenvalues by about 2e-3 and
+    lambda_min >= 1); its GPU time is reported separately.  A request is
+    submitted, and its arrival stamped, once its A is resident.
+    Per precision mode (binary64; binary32 factors with binary64 refinement): a
+    closed loop (window of outstanding requests) gives the saturation rate X_max,
+    open loops with exponential arrivals at rho * X_max give latency percentiles
+    (device time from the submit stamp to the end of the solve, plus any lateness
+    of the host loop behind the nominal arrival).  HBM budget: a 200 GB arena."""
+    import collections
     import math
     import numpy as np
     rng = np.random.default_rng(seed)
-    sizes = [int(round(math.exp(rng.uniform(math.log(256), math.log(8192))))) for _ in range(pool)]
-    mats = [wl.spd_scaled_device(n, seed=10**6 + i, device=dev) for i, n in enumerate(sizes)]
-    torch.cuda.synchronize()
+    reqs, distinct = [], []
+    for i in range(nreq):
+        if distinct and rng.uniform() < 0.3:
+            key, j, n = distinct[int(rng.integers(max(0, len(distinct) - 64), len(distinct)))]
+        else:
+            j = len(distinct)
+            n = int(round(math.exp(rng.uniform(math.log(256), math.log(8192)))))
+            key = j + 1
+            distinct.append((key, j, n))
+        reqs.append((key, j, n, int(rng.integers(1, 9))))
+    prod = torch.cuda.Stream(device=dev)
+    gen = {"matrices": 0, "gpu_ms": 0.0}
+    cache = collections.OrderedDict()        # the last 64 distinct matrices (repeats only reach those)
+    pending = collections.OrderedDict()      # matrices being generated: j -> (A, start, end event)
+    LOOKAHEAD = 8
 
-    def workload():
-        reqs, distinct = [], []
-        for i in range(nreq):
-            if distinct and rng.uniform() < 0.3:
-                key, j = distinct[int(rng.integers(0, min(64, len(distinct)))) - min(64, len(distinct))]
-            else:
-                key, j = i + 1, int(rng.integers(0, pool))
-                distinct.append((key, j))
-            reqs.append((key, j, int(rng.integers(1, 9))))
-        return reqs
+    def enqueue(j, n):
+        # generate the matrix of distinct index j on the producer stream (no host wait)
+        if j in cache or j in pending:
+            return
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(prod):
+            e0.record(prod)
+            g = torch.Generator(device=dev)
+            g.manual_seed(10 ** 6 + j)
+            G = torch.randn(n, n, dtype=torch.bfloat16, device=dev, generator=g)
+            A = torch.mm(G, G.t().contiguous()).to(torch.float64)
+            del G
+            A.div_(float(n))
+            A.diagonal().add_(1.0)
+            A = torch.tril(A) + torch.tril(A, -1).t()
+            e1.record(prod)
+        pending[j] = (A, e0, e1)
 
-    def run(reqs, arrivals=None):
-        arena = torch.empty(64 << 27, dtype=torch.float64, device=dev)     # 64 GiB budget
-        srv = ff.Server(arena)
+    def matrix(j, n):
+        A = cache.get(j)
+        if A is not None:
+            return A
+        enqueue(j, n)
+        A, e0, e1 = pending.pop(j)
+        e1.synchronize()                 # resident before its request arrives
+        gen["matrices"] += 1
+        gen["gpu_ms"] += e0.elapsed_time(e1)
+        cache[j] = A
+        if len(cache) > 64:
+            cache.popitem(last=False)
+        return A
+
+    def prefetch(rq, start):
+        for key, j, n, nrhs in rq[start:start + LOOKAHEAD]:
+            enqueue(j, n)
+
+    def run(mode, rq, arrivals=None):
+        arena = torch.empty(int(arena_gb * 1e9) // 8, dtype=torch.float64, device=dev)
+        srv = ff.Server(arena, dtype=mode)
         flops = 0.0
-        lat, hits, out = [], 0, {}
+        lat, hits, iters, conv, sizes = [], 0, [], 0, {}
         nominal = {}
+        g0 = gen["gpu_ms"]
         t0 = time.perf_counter()
         nxt, done = 0, 0
         last_done, last_t, last_log = 0, 0.0, 0.0
-        while done < len(reqs):
+        while done < len(rq):
             now = time.perf_counter() - t0
             if done != last_done:
                 last_done, last_t = done, now
             elif now - last_t > 60.0 and nxt > done:
-                raise RuntimeError(f"serving made no progress for 60 s ({done}/{len(reqs)} done)")
+                raise RuntimeError(f"serving made no progress for 60 s ({done}/{len(rq)} done)")
             if now - last_log > 10.0:
-                log(f"[bench] serving: {done}/{len(reqs)} done after {now:.1f} s")
+                log(f"[bench] serving {mode}: {done}/{len(rq)} done after {now:.1f} s")
                 last_log = now
-            while nxt < len(reqs) and (nxt - done) < window and (arrivals is None or arrivals[nxt] <= now):
-                key, j, nrhs = reqs[nxt]
-                A = mats[j].t()
-                n = A.shape[0]
+            while nxt < len(rq) and (nxt - done) < window and (arrivals is None or arrivals[nxt] <= now):
+                key, j, n, nrhs = rq[nxt]
+                A = matrix(j, n).t()
+                prefetch(rq, nxt + 1)
                 B = torch.randn(nrhs, n, dtype=torch.float64, device=dev).t()
                 X = torch.empty_like(B)
                 rid = srv.submit(A, B, X, key=key)
-                nominal[rid] = (now - arrivals[nxt]) * 1e3 if arrivals is not None else 0.0
-                out[rid] = n
+                t_sub = time.perf_counter() - t0
+                nominal[rid] = (t_sub - arrivals[nxt]) * 1e3 if arrivals is not None else 0.0
+                sizes[rid] = n
                 nxt += 1
             srv.step()
             for r in srv.poll():
                 done += 1
                 hits += r["cache_hit"]
+                iters.append(r["iters"])
+                conv += r["converged"]
                 if r["info"] != 0:
                     raise RuntimeError(f"serving request failed: info={r['info']}")
                 if not r["cache_hit"]:
-                    flops += out[r["id"]] ** 3 / 3.0
+                    flops += sizes[r["id"]] ** 3 / 3.0
                 lat.append(r["latency_ms"] + nominal[r["id"]])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -444,48 +490,66 @@ def run_serving(ff, torch, wl, dev, nreq=2000, seed=0, pool=48, window=128, rho=
         del arena
         torch.cuda.empty_cache()
         lat = np.array(lat)
-        return {"requests": len(reqs), "wall_s": round(wall, 3), "solves_per_s": round(len(reqs) / wall, 1),
-                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "cache_hit_rate": round(hits / len(reqs), 3), "factor_tflops": round(flops / wall / 1e12, 3),
-                "steps": st["steps"], "grouped_launches": st["grouped_launches"], "evictions": st["evictions"]}
+        out = {"requests": len(rq), "wall_s": round(wall, 3), "solves_per_s": round(len(rq) / wall, 1),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "cache_hit_rate": round(hits / len(rq), 3), "factor_tflops": round(flops / wall / 1e12, 3),
+               "generation_gpu_ms_in_run": round(gen["gpu_ms"] - g0, 1),
+               "steps": st["steps"], "grouped_launches": st["grouped_launches"], "evictions": st["evictions"]}
+        if mode != "f64":
+            out["mean_refinement_iters"] = round(float(np.mean(iters)), 2)
+            out["converged_fraction"] = round(conv / len(rq), 4)
+        return out
 
-    def sequential(reqs):
+    def sequential(rq):
         # the same requests one at a time through chol_factor + chol_trisolve
-        # (resident factors reused for repeats, as the server does)
-        cache = {}
+        # (binary64, resident factors reused for repeats)
+        facs = {}
+        for key, j, n, nrhs in rq:
+            if key not in facs:
+                matrix(j, n)                 # generated before the clock starts
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for key, j, nrhs in reqs:
-            A = mats[j].t()
-            n = A.shape[0]
-            if key not in cache:
-                L = A.clone(memory_format=torch.preserve_format)
-                ff.chol_factor(L, min(wl.default_s(n), 192))
-                cache[key] = L
+        for key, j, n, nrhs in rq:
+            if key not in facs:
+                L = matrix(j, n).t().clone(memory_format=torch.preserve_format)
+                ff.chol_factor(L, min(n, 192))
+                facs[key] = L
+                if len(facs) > 64:
+                    facs.pop(next(iter(facs)))
             X = torch.randn(nrhs, n, dtype=torch.float64, device=dev).t()
-            ff.chol_trisolve(cache[key], X)
+            ff.chol_trisolve(facs[key], X)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        del cache
+        del facs
         torch.cuda.empty_cache()
-        return {"requests": len(reqs), "wall_s": round(wall, 3), "solves_per_s": round(len(reqs) / wall, 1)}
+        return {"requests": len(rq), "wall_s": round(wall, 3), "solves_per_s": round(len(rq) / wall, 1)}
 
-    reqs = workload()
-    log(f"[bench] serving: pool of {pool} matrices ready, {nreq} requests")
-    run(reqs[:100])                                  # warm-up (kernels, allocator)
-    closed = run(reqs)
-    log(f"[bench] serving closed loop: {closed}")
-    seq = sequential(reqs)
-    log(f"[bench] one request at a time: {seq}")
-    xmax = closed["solves_per_s"]
-    gaps = rng.exponential(1.0 / (rho * xmax), size=len(reqs))
-    arrivals = np.cumsum(gaps)
-    opened = run(reqs, arrivals)
-    del mats
+    log(f"[bench] serving: {nreq} requests, {len(distinct)} distinct matrices")
+    res = {"workload": f"{nreq} requests, n log-uniform [256, 8192], nrhs U{{1..8}}, 30% repeats of the last 64 "
+                       f"distinct matrices, per-request seeds (A = G G^T/n + I generated on a producer stream), "
+                       f"arena {arena_gb} GB, window {window} in closed loop"}
+    for mode in modes:
+        run(mode, reqs[:200])                                 # warm-up (kernels, allocator)
+        closed = run(mode, reqs)
+        log(f"[bench] serving {mode} closed loop: {closed}")
+        xmax = closed["solves_per_s"]
+        entry = {"closed_loop": closed}
+        for rho in rhos:
+            arr = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / (rho * xmax), size=len(reqs)))
+            entry[f"open_loop_rho{rho}"] = run(mode, reqs, arr)
+            log(f"[bench] serving {mode} rho={rho}: {entry[f'open_loop_rho{rho}']}")
+        res[mode] = entry
+    if seq_requests:
+        res["one_at_a_time_f64"] = sequential(reqs[:seq_requests])
+        log(f"[bench] one request at a time: {res['one_at_a_time_f64']}")
+    res["generation"] = {"matrices": gen["matrices"], "gpu_ms": round(gen["gpu_ms"], 1),
+                         "note": "producer stream, bfloat16 GEMM, up to 8 requests ahead of submission; "
+                                 "runs beside the server (its interference is part of every rate), "
+                                 "never inside a latency (arrival is stamped once A is resident)"}
+    cache.clear()
+    pending.clear()
     torch.cuda.empty_cache()
-    return {"workload": f"{nreq} requests, n log-uniform [256, 8192], nrhs U{{1..8}}, 30% repeats, "
-                        f"pool of {pool} matrices, binary64, arena 64 GiB",
-            "closed_loop": closed, f"open_loop_rho{rho}": opened, "one_at_a_time": seq}
+    return res
 
 
 MIXED_STEP = {16384: {"f64": 768, "f32": 640, "bf16": 768}, 32768: {"f64": 768, "f32": 768, "bf16": 768}}
