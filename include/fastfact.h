@@ -84,6 +84,12 @@ enum {
                                       in the next precision (bfloat16 ->
                                       binary32 -> binary64) and refine with
                                       that; see chol_solve. */
+    FF_FLAG_GMRES_IR = 1u << 4,     /* chol_solve only: each refinement step
+                                      solves its correction equation A d = r
+                                      by GMRES in binary64, preconditioned on
+                                      the left by the factor (M = W W^T in W's
+                                      precision), instead of by one pair of
+                                      triangular solves; see chol_solve. */
     FF_FLAG_FIXED_STEP = 1u << 2    /* every block exactly s columns wide (the
                                       step of Sec. 2 Algorithms 1 and 2
                                       verbatim).  Without it, the first block
@@ -156,6 +162,8 @@ typedef struct {
     int32_t escalations;   /* refactorisations after the first */
     int32_t total_iters;   /* refinement iterations over all factors tried */
     int32_t first_info;    /* info of the factorisation in the requested precision */
+    int32_t krylov_iters;  /* with FF_FLAG_GMRES_IR: GMRES steps over all columns and factors */
+    int32_t reserved;      /* 0 */
 } ff_solve_info;
 
 /*
@@ -181,6 +189,12 @@ typedef struct {
  *         binary32 -> binary64, in the workspace) and refined again.  out
  *         then describes the last attempt; escalated_to, escalations,
  *         total_iters and first_info record the way there.
+ *         FF_FLAG_GMRES_IR refines each column on its own: a step computes
+ *         r = b - A x in binary64 and runs one GMRES cycle (at most 30
+ *         steps, stopping when the preconditioned residual has fallen by
+ *         1e-8) on M^-1 A d = M^-1 r, Gram-Schmidt applied twice, then x += d;
+ *         iters is then the most steps any column took, the stop rules are
+ *         those above applied per column, and converged needs every column.
  *   ws    device workspace, >= ff_solve_workspace_size(n, s, nrhs, dtype,
  *         flags) (with FF_FLAG_ESCALATE and float storage it includes an n x n
  *         binary64 factor)

@@ -25,6 +25,7 @@ FLAG_STRASSEN1 = 1
 FLAG_NO_LOOKAHEAD = 2
 FLAG_FIXED_STEP = 4
 FLAG_ESCALATE = 8
+FLAG_GMRES_IR = 16
 ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_SCRATCH = -100, -101, -102, -103
 
 _DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
@@ -62,7 +63,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("info", ctypes.c_int32), ("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("dtype_used", ctypes.c_int32), ("last_correction", ctypes.c_double),
                 ("backward_err", ctypes.c_double), ("escalated_to", ctypes.c_int32),
-                ("escalations", ctypes.c_int32), ("total_iters", ctypes.c_int32), ("first_info", ctypes.c_int32)]
+                ("escalations", ctypes.c_int32), ("total_iters", ctypes.c_int32), ("first_info", ctypes.c_int32),
+                ("krylov_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -251,22 +253,25 @@ def lu_nopiv_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_loo
     return info
 
 
-def solve_workspace_size(n: int, s: int, nrhs: int, dtype="f64", escalate=False) -> int:
-    return int(load().ff_solve_workspace_size(n, s, nrhs, _dt(dtype), FLAG_ESCALATE if escalate else 0))
+def solve_workspace_size(n: int, s: int, nrhs: int, dtype="f64", escalate=False, gmres=False) -> int:
+    flags = (FLAG_ESCALATE if escalate else 0) | (FLAG_GMRES_IR if gmres else 0)
+    return int(load().ff_solve_workspace_size(n, s, nrhs, _dt(dtype), flags))
 
 
 def chol_solve(A64: torch.Tensor, B: torch.Tensor, s: int, dtype="f32", W: torch.Tensor | None = None,
                w_is_factored=False, X: torch.Tensor | None = None, tol=1e-13, max_iter=50, strassen=False,
-               stream=None, ws: torch.Tensor | None = None, escalate=False, no_lookahead=False):
+               stream=None, ws: torch.Tensor | None = None, escalate=False, no_lookahead=False, gmres=False):
     """Solve A64 X = B with a factor W in `dtype` and binary64 refinement
-    (escalate: refactor in higher precision when that fails, FF_FLAG_ESCALATE).
+    (escalate: refactor in higher precision when that fails, FF_FLAG_ESCALATE;
+    gmres: correction equations solved by factor-preconditioned GMRES,
+    FF_FLAG_GMRES_IR).
     Returns (X, W, info dict).  Synchronises the stream."""
     lib = load()
     dt = _dt(dtype)
     n = int(A64.shape[0])
     nrhs = int(B.shape[1])
     flags = ((FLAG_STRASSEN1 if strassen else 0) | (FLAG_ESCALATE if escalate else 0)
-             | (FLAG_NO_LOOKAHEAD if no_lookahead else 0))
+             | (FLAG_NO_LOOKAHEAD if no_lookahead else 0) | (FLAG_GMRES_IR if gmres else 0))
     if W is None:
         if w_is_factored:
             raise ValueError("w_is_factored requires W")

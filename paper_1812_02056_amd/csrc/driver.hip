@@ -660,6 +660,12 @@ int check_common(int64_t n, int64_t s, const void* A, int64_t lda, int dtype, un
     return 0;
 }
 
+// GMRES-IR: restart length (the basis has GM_RESTART + 1 columns, at most the
+// 32 the multi-dot kernels take) and the inner tolerance on the preconditioned
+// residual relative to its starting norm.
+constexpr int GM_RESTART = 30;
+constexpr double GM_INNER_TOL = 1e-8;
+
 template <typename S>
 struct SolveWs {
     TriWs<S> tri;
@@ -670,6 +676,12 @@ struct SolveWs {
     S* D;
     double* rowsum;
     double* norms;
+    // GMRES-IR: Krylov basis (n x GM_RESTART + 1), two vectors, partial sums, scalars
+    double* V;
+    double* t;
+    double* d;
+    double* mpart;
+    double* scal;
     size_t bytes;
 };
 
@@ -696,8 +708,111 @@ SolveWs<S> carve_solve(void* base, int64_t n, int64_t s, int64_t nrhs, int dtype
     w.D = cv.take<S>((size_t)n * (size_t)nrhs);
     w.rowsum = cv.take<double>((size_t)n);
     w.norms = cv.take<double>(3 + 3 * (size_t)nrhs);
+    w.V = cv.take<double>((size_t)n * (GM_RESTART + 1));
+    w.t = cv.take<double>((size_t)n);
+    w.d = cv.take<double>((size_t)n);
+    w.mpart = cv.take<double>(multidot_part_doubles((int)n));
+    w.scal = cv.take<double>(4 * 32);
     w.bytes = cv.off;
     return w;
+}
+
+// Correction of one column by left-preconditioned GMRES in binary64: solve
+// M^-1 A d = M^-1 r with M = W W^T (the factor in its storage precision, applied
+// by the two triangular solves), then x += d.  On return norms[0..1] hold
+// max|d|, max|x| (device) and *k_used the Krylov steps taken.  Classical
+// Gram-Schmidt applied twice orthogonalises each new vector; the Hessenberg
+// matrix, its Givens rotations and the small triangular solve live on the host.
+template <typename S>
+int gmres_correct(int n, const double* A64, int64_t lda, const S* W, int64_t ldw, const double* b, double* x,
+                  const SolveWs<S>& w, hipStream_t st, int* k_used) {
+    const int m = GM_RESTART;
+    double* V = w.V;
+    double* zero_rhs = w.d;                       // n zeros: the matvec is a residual with b = 0
+    FF_TRY(launch_fill_double(n, zero_rhs, 0.0, st));
+    auto precond = [&](const double* in, double* out) -> hipError_t {
+        // out = W^-T W^-1 in, in the factor's precision
+        hipError_t e = launch_convert_from_f64<S>(n, 1, in, n, w.D, n, st);
+        if (e == hipSuccess) e = trisolve_impl<S>(n, 1, W, ldw, w.D, n, w.tri, false, st);
+        if (e == hipSuccess) e = launch_widen<S>(n, 1, w.D, n, out, n, st);
+        return e;
+    };
+    // r = b - A x, z = M^-1 r into V[:, 0], beta^2 = z.z
+    FF_TRY(launch_residual_f64(n, 1, A64, lda, x, n, b, n, w.R, n, nullptr, w.rpart, st));
+    FF_TRY(precond(w.R, V));
+    double* sq = w.scal;                          // device scalars: [0] squared norm, [32..] h1, [64..] h2, [96..] y
+    double* h1 = w.scal + 32;
+    double* h2 = w.scal + 64;
+    double* ydev = w.scal + 96;
+    FF_TRY(launch_multidot(n, 1, V, n, V, w.mpart, sq, st));
+    double beta2 = 0.0;
+    FF_TRY(hipMemcpyAsync(&beta2, sq, sizeof(double), hipMemcpyDeviceToHost, st));
+    FF_TRY(hipStreamSynchronize(st));
+    *k_used = 0;
+    if (!(beta2 > 0.0)) {                         // nothing to correct (or an unusable value)
+        FF_TRY(launch_axpy_max<double>(n, 1, zero_rhs, n, x, n, w.norms, st));
+        return 0;
+    }
+    const double beta = std::sqrt(beta2);
+    FF_TRY(launch_normalize(n, V, sq, V, st));
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (; k < m; ++k) {
+        double* vk = V + (int64_t)k * n;
+        double* vn = V + (int64_t)(k + 1) * n;
+        // t = -A v_k (a residual with b = 0), vn = M^-1 (-A v_k), then negated
+        FF_TRY(launch_residual_f64(n, 1, A64, lda, vk, n, zero_rhs, n, w.t, n, nullptr, w.rpart, st));
+        FF_TRY(precond(w.t, vn));
+        FF_TRY(launch_negate(n, vn, vn, st));
+        FF_TRY(launch_multidot(n, k + 1, V, n, vn, w.mpart, h1, st));
+        FF_TRY(launch_gemv_add(n, k + 1, V, n, h1, -1.0, vn, st));
+        FF_TRY(launch_multidot(n, k + 1, V, n, vn, w.mpart, h2, st));
+        FF_TRY(launch_gemv_add(n, k + 1, V, n, h2, -1.0, vn, st));
+        FF_TRY(launch_multidot(n, 1, vn, n, vn, w.mpart, sq, st));
+        double hh[2 * 32 + 1];
+        FF_TRY(hipMemcpyAsync(hh, h1, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
+        FF_TRY(hipMemcpyAsync(hh + 32, h2, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
+        FF_TRY(hipMemcpyAsync(hh + 64, sq, sizeof(double), hipMemcpyDeviceToHost, st));
+        FF_TRY(hipStreamSynchronize(st));
+        double* col = &H[(size_t)k * (m + 1)];    // column k of H, rows 0..k+1
+        for (int i = 0; i <= k; ++i) col[i] = hh[i] + hh[32 + i];
+        const double hn = std::sqrt(std::max(hh[64], 0.0));
+        col[k + 1] = hn;
+        if (hn > 0.0) FF_TRY(launch_normalize(n, vn, sq, vn, st));
+        // apply the earlier rotations, then a new one that zeroes col[k + 1]
+        for (int i = 0; i < k; ++i) {
+            const double a = col[i], c = col[i + 1];
+            col[i] = cs[i] * a + sn[i] * c;
+            col[i + 1] = -sn[i] * a + cs[i] * c;
+        }
+        const double rr = std::hypot(col[k], col[k + 1]);
+        cs[k] = rr > 0.0 ? col[k] / rr : 1.0;
+        sn[k] = rr > 0.0 ? col[k + 1] / rr : 0.0;
+        col[k] = rr;
+        col[k + 1] = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        if (std::fabs(g[k + 1]) <= GM_INNER_TOL * beta || !(hn > 0.0) || !(rr > 0.0)) {
+            ++k;
+            break;
+        }
+    }
+    *k_used = k;
+    // y = R^-1 g (upper triangular k x k), d = V y, x += d with the max norms
+    std::vector<double> y(k, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+        double v = g[i];
+        for (int j = i + 1; j < k; ++j) v -= H[(size_t)j * (m + 1) + i] * y[j];
+        const double dii = H[(size_t)i * (m + 1) + i];
+        y[i] = dii != 0.0 ? v / dii : 0.0;
+    }
+    FF_TRY(hipMemcpyAsync(ydev, y.data(), (size_t)k * sizeof(double), hipMemcpyHostToDevice, st));
+    FF_TRY(launch_fill_double(n, w.t, 0.0, st));
+    FF_TRY(launch_gemv_add(n, k, V, n, ydev, 1.0, w.t, st));
+    FF_TRY(launch_axpy_max<double>(n, 1, w.t, n, x, n, w.norms, st));
+    FF_TRY(hipStreamSynchronize(st));             // y's host copy is done before y goes
+    return 0;
 }
 
 template <typename S>
@@ -712,11 +827,12 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
     out->dtype_used = dtype;
     out->last_correction = 0.0;
     out->backward_err = 0.0;
+    out->krylov_iters = 0;
     if (!w_is_factored) {
         FF_TRY(launch_copy_lower_from_f64<S>(n, A64, lda, W, ldw, st));
         FF_TRY(launch_set_int(w.d_info, 0, st));
-        int rc = chol_blocked<S>(n, s, W, ldw, dtype, flags, w.diag64, w.d_info, 0, st,
-                                 !(flags & FF_FLAG_NO_LOOKAHEAD));
+        int rc = chol_blocked<S>(n, s, W, ldw, dtype, flags & ~(unsigned)FF_FLAG_GMRES_IR, w.diag64, w.d_info, 0,
+                                 st, !(flags & FF_FLAG_NO_LOOKAHEAD));
         if (rc) return rc;
         int info = 0;
         FF_TRY(hipMemcpyAsync(&info, w.d_info, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -733,7 +849,33 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
     double prev = -1.0;
     double host[2];
     int bad_wait = 0;
-    for (int it = 1; it <= max_iter; ++it) {
+    if (flags & FF_FLAG_GMRES_IR) {
+        // each column: outer refinement steps whose correction equation is solved
+        // by preconditioned GMRES; iters reports the most outer steps of a column
+        int all_conv = 1, max_it = 0;
+        for (int c = 0; c < nrhs; ++c) {
+            double pc = -1.0;
+            int conv = 0, it = 0;
+            for (it = 1; it <= max_iter; ++it) {
+                int k = 0;
+                int rc = gmres_correct<S>(n, A64, lda, W, ldw, B + (int64_t)c * ldb, X + (int64_t)c * ldx, w, st, &k);
+                if (rc) return rc;
+                out->krylov_iters += k;
+                FF_TRY(hipMemcpyAsync(host, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+                FF_TRY(hipStreamSynchronize(st));
+                const double corr = (host[1] > 0.0) ? host[0] / host[1] : host[0];
+                out->last_correction = std::max(out->last_correction, corr);
+                if (corr <= tol) { conv = 1; break; }
+                if (!(corr == corr) || (pc >= 0.0 && corr > 0.5 * pc)) break;
+                pc = corr;
+            }
+            all_conv &= conv;
+            max_it = std::max(max_it, std::min(it, max_iter));
+        }
+        out->iters = max_it;
+        out->converged = all_conv;
+    }
+    for (int it = 1; it <= max_iter && !(flags & FF_FLAG_GMRES_IR); ++it) {
         FF_TRY(launch_residual_f64(n, nrhs, A64, lda, X, ldx, B, ldb, w.R, n, nullptr, w.rpart, st));
         FF_TRY(launch_convert_from_f64<S>(n, nrhs, w.R, n, w.D, n, st));
         FF_TRY(trisolve_impl<S>(n, nrhs, W, ldw, w.D, n, w.tri, false, st));
@@ -900,7 +1042,8 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t ld
     if (n > 0 && W == nullptr) return -6;
     if (ldw < std::max<int64_t>(1, n)) return -7;
     if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -8;
-    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP | FF_FLAG_ESCALATE))
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP | FF_FLAG_ESCALATE |
+                             FF_FLAG_GMRES_IR))
         return -9;
     if (n > 0 && nrhs > 0 && B == nullptr) return -11;
     if (ldb < std::max<int64_t>(1, n)) return -12;
@@ -933,11 +1076,13 @@ int chol_solve(int64_t n, int64_t s, int64_t nrhs, const double* A64, int64_t ld
     auto accepted = [&](const ff_solve_info& o) { return o.info == 0 && (o.converged || o.backward_err <= tol); };
     auto take = [&](const ff_solve_info& o, int to) {
         const int first = out->first_info, total = out->total_iters + o.iters, esc = out->escalations + 1;
+        const int kry = out->krylov_iters + o.krylov_iters;
         *out = o;
         out->first_info = first;
         out->total_iters = total;
         out->escalations = esc;
         out->escalated_to = to;
+        out->krylov_iters = kry;
     };
     if (accepted(*out)) return 0;
     ff_solve_info o{};

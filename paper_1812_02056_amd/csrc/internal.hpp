@@ -162,4 +162,16 @@ hipError_t launch_norms(int n, int nrhs, const double* rowsum, const double* X, 
                         int64_t ldd, const double* R, int64_t ldr, const double* B, int64_t ldb, double* out,
                         hipStream_t st);
 
+// GMRES pieces (solve.hip): Krylov basis V n x k (k <= 32) column-major binary64.
+// out[i] = V[:, i] . w (part: multidot_part_doubles(n) doubles of scratch);
+// w += alpha V h; y = x / sqrt(*sq); y = -x.
+size_t multidot_part_doubles(int n);
+hipError_t launch_multidot(int n, int k, const double* V, int64_t ldv, const double* w, double* part, double* out,
+                           hipStream_t st);
+hipError_t launch_gemv_add(int n, int k, const double* V, int64_t ldv, const double* h, double alpha, double* w,
+                           hipStream_t st);
+hipError_t launch_normalize(int n, const double* x, const double* sq, double* y, hipStream_t st);
+hipError_t launch_negate(int n, const double* x, double* y, hipStream_t st);
+hipError_t launch_fill_double(int n, double* y, double v, hipStream_t st);
+
 }  // namespace ff

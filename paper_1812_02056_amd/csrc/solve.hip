@@ -728,6 +728,72 @@ void axpy_max_kernel(int n, const S* __restrict__ D, int64_t ldd, double* __rest
     }
 }
 
+// ---------------------------------------------------------------- GMRES pieces
+// Krylov basis V: n x (k) column-major binary64, ld = ldv.  Sums are taken in a
+// fixed order (per-workgroup partials over row chunks, then the partials in
+// workgroup order), so results do not depend on scheduling.
+constexpr int KV_MAX = 32;          // basis vectors one launch handles
+constexpr int KV_WG = 256;          // threads per workgroup
+constexpr int KV_ROWS = 2048;       // rows per workgroup
+
+// part[g * KV_MAX + i] = sum over the rows of workgroup g of V[:, i] w.
+__global__ __launch_bounds__(KV_WG)
+void multidot_part_kernel(int n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ w,
+                          double* __restrict__ part) {
+    __shared__ double red[KV_WG];
+    const int r0 = blockIdx.x * KV_ROWS;
+    const int r1 = min(n, r0 + KV_ROWS);
+    for (int i = 0; i < k; ++i) {
+        double acc = 0.0;
+        for (int r = r0 + threadIdx.x; r < r1; r += KV_WG) acc += V[r + (int64_t)i * ldv] * w[r];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = KV_WG / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x * KV_MAX + i] = red[0];
+        __syncthreads();
+    }
+}
+
+// out[i] = sum_g part[g * KV_MAX + i] (g ascending), i < k.
+__global__ void multidot_reduce_kernel(int k, int ngroups, const double* __restrict__ part, double* __restrict__ out) {
+    const int i = threadIdx.x;
+    if (i >= k) return;
+    double s = 0.0;
+    for (int g = 0; g < ngroups; ++g) s += part[g * KV_MAX + i];
+    out[i] = s;
+}
+
+// w += alpha * V h (h: k values on the device).
+__global__ void gemv_add_kernel(int n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
+                                double alpha, double* __restrict__ w) {
+    __shared__ double hs[KV_MAX];
+    if (threadIdx.x < k) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += V[r + (int64_t)i * ldv] * hs[i];
+        w[r] += alpha * s;
+    }
+}
+
+// y = x / sqrt(*sq), sq a device scalar (a squared norm); y may alias x.
+__global__ void normalize_kernel(int n, const double* x, const double* __restrict__ sq, double* y) {
+    const double inv = 1.0 / sqrt(*sq);
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) y[r] = x[r] * inv;
+}
+
+__global__ void fill_double_kernel(int n, double* __restrict__ y, double v) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) y[r] = v;
+}
+
+// y = -x (y may alias x).
+__global__ void negate_kernel(int n, const double* x, double* y) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) y[r] = -x[r];
+}
+
 }  // namespace
 
 template <typename S>
@@ -851,5 +917,45 @@ template hipError_t launch_widen<double>(int, int, const double*, int64_t, doubl
 template hipError_t launch_widen<float>(int, int, const float*, int64_t, double*, int64_t, hipStream_t);
 template hipError_t launch_axpy_max<double>(int, int, const double*, int64_t, double*, int64_t, double*, hipStream_t);
 template hipError_t launch_axpy_max<float>(int, int, const float*, int64_t, double*, int64_t, double*, hipStream_t);
+
+size_t multidot_part_doubles(int n) { return (size_t)((n + KV_ROWS - 1) / KV_ROWS) * KV_MAX; }
+
+hipError_t launch_multidot(int n, int k, const double* V, int64_t ldv, const double* w, double* part, double* out,
+                           hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    if (k > KV_MAX) return hipErrorInvalidValue;
+    const int ng = (n + KV_ROWS - 1) / KV_ROWS;
+    if (ng > 0)
+        hipLaunchKernelGGL(multidot_part_kernel, dim3(ng), dim3(KV_WG), 0, st, n, k, V, ldv, w, part);
+    hipLaunchKernelGGL(multidot_reduce_kernel, dim3(1), dim3(KV_MAX), 0, st, k, ng, part, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_add(int n, int k, const double* V, int64_t ldv, const double* h, double alpha, double* w,
+                           hipStream_t st) {
+    if (k <= 0 || n <= 0) return hipSuccess;
+    if (k > KV_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemv_add_kernel, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, n, k, V, ldv, h,
+                       alpha, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(int n, const double* x, const double* sq, double* y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normalize_kernel, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, n, x, sq, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_double(int n, double* y, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_double_kernel, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, n, y, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_negate(int n, const double* x, double* y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(negate_kernel, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, n, x, y);
+    return hipGetLastError();
+}
 
 }  // namespace ff

@@ -89,7 +89,8 @@ def test_flag_constants_match_the_header():
     from paper_1812_02056_amd import binding
     text = _header_without_comments()
     flags = dict(re.findall(r"\b(FF_FLAG_[A-Z0-9_]+)\s*=\s*1u\s*<<\s*(\d+)", text))
-    assert set(flags) == {"FF_FLAG_STRASSEN1", "FF_FLAG_NO_LOOKAHEAD", "FF_FLAG_FIXED_STEP", "FF_FLAG_ESCALATE"}
+    assert set(flags) == {"FF_FLAG_STRASSEN1", "FF_FLAG_NO_LOOKAHEAD", "FF_FLAG_FIXED_STEP", "FF_FLAG_ESCALATE",
+                          "FF_FLAG_GMRES_IR"}
     for name, shift in flags.items():
         assert getattr(binding, name[3:]) == 1 << int(shift), name
 
