@@ -150,6 +150,42 @@ size_t ff_lu_workspace_size(int64_t n, int64_t s, int dtype, unsigned flags);
 int lu_nopiv_factor(int64_t n, int64_t s, void *A, int64_t lda, int dtype, unsigned flags,
                     void *ws, size_t ws_bytes, int32_t *d_info, void *stream);
 
+/*
+ * QR factorisation A = Q R by Gram-Schmidt with deferred block projections
+ * (Sec. 2 Algorithm 3 with step s), for an m x n matrix with m >= n.  A is read
+ * only; Q (m x n, orthonormal columns) and R (n x n upper triangular with a
+ * positive diagonal; its strict lower triangle is written as zero) are outputs
+ * and must not overlap A or each other.  Per block of ws = min(s, n,
+ * ff_qr_step-limit) columns: modified Gram-Schmidt inside the block (every
+ * column projected against the block's earlier columns one at a time, then
+ * divided by its norm), then C = B_Q^T M[:, c..] and M[:, c..] -= B_Q C for the
+ * block's columns B_Q and the columns M[:, c..] after it; finally R = Q^T A.
+ * The working matrix M of the algorithm lives in Q.  Only FF_F64.
+ *   m, n   m >= n >= 0; m is limited to 128 rows per compute unit (256 rows per
+ *          compute unit with blocks of at most 71 columns), else FF_ERR_UNSUPPORTED
+ *   s      step, >= 1; the block width actually used is ff_qr_step(m, n, s)
+ *          (at most 142 columns for m <= 128 * compute units: the block lives in
+ *          the LDS of the workgroups that run its Gram-Schmidt)
+ *   A      device double*, lda >= max(1, m)
+ *   Q      device double*, ldq >= max(1, m)
+ *   R      device double*, ldr >= max(1, n)
+ *   flags  must be 0
+ *   ws     device workspace, >= ff_qr_workspace_size(m, n, s, dtype, flags)
+ *   d_info device int32: 0, or the 1-based column whose norm after its
+ *          projections is not > 0 (zero or NaN; Q and R are then incomplete), or
+ *          -1 if a wait between the co-resident workgroups of the Gram-Schmidt
+ *          kernel expired (the device was shared with other work that kept
+ *          compute units busy; Q and R are then invalid)
+ *   stream hipStream_t; the call is asynchronous.
+ * The Gram-Schmidt kernel keeps one workgroup per compute unit resident and
+ * synchronises them through device memory; it must not share the device with
+ * work that holds compute units indefinitely.
+ */
+size_t ff_qr_workspace_size(int64_t m, int64_t n, int64_t s, int dtype, unsigned flags);
+int ff_qr_step(int64_t m, int64_t n, int64_t s);
+int qr_factor(int64_t m, int64_t n, int64_t s, const void *A, int64_t lda, void *Q, int64_t ldq, void *R,
+              int64_t ldr, int dtype, unsigned flags, void *ws, size_t ws_bytes, int32_t *d_info, void *stream);
+
 /* Outcome of chol_solve (host struct). */
 typedef struct {
     int32_t info;          /* info of the factorisation that produced X (0 = ok), as d_info above */

@@ -34,7 +34,8 @@ _STORAGE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
 # Every symbol include/fastfact.h declares.
 EXPORTED = (
     "ff_status_string", "ff_version", "ff_chol_workspace_size", "chol_factor",
-    "ff_lu_workspace_size", "lu_nopiv_factor", "ff_solve_workspace_size", "chol_solve",
+    "ff_lu_workspace_size", "lu_nopiv_factor", "ff_qr_workspace_size", "ff_qr_step", "qr_factor",
+    "ff_solve_workspace_size", "chol_solve",
     "ff_trisolve_workspace_size", "chol_trisolve", "chol_trisolve_noalloc", "ff_update_syrk", "ff_update_gemm",
     "ff_update_profile_enable", "ff_update_profile_read",
     "ff_server_create", "ff_server_destroy", "ff_server_submit", "ff_server_step", "ff_server_poll",
@@ -100,6 +101,12 @@ def load():
     lib.ff_lu_workspace_size.restype = sz
     lib.lu_nopiv_factor.argtypes = [i64, i64, vp, i64, i32, u32, vp, sz, vp, vp]
     lib.lu_nopiv_factor.restype = i32
+    lib.ff_qr_workspace_size.argtypes = [i64, i64, i64, i32, u32]
+    lib.ff_qr_workspace_size.restype = sz
+    lib.ff_qr_step.argtypes = [i64, i64, i64]
+    lib.ff_qr_step.restype = i32
+    lib.qr_factor.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, u32, vp, sz, vp, vp]
+    lib.qr_factor.restype = i32
     lib.ff_solve_workspace_size.argtypes = [i64, i64, i64, i32, u32]
     lib.ff_solve_workspace_size.restype = sz
     lib.chol_solve.argtypes = [i64, i64, i64, vp, i64, vp, i64, i32, u32, i32, vp, i64, vp, i64,
@@ -251,6 +258,41 @@ def lu_nopiv_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_loo
         (stream or torch.cuda.current_stream()).synchronize()
         return int(info.item())
     return info
+
+
+def qr_workspace_size(m: int, n: int, s: int, dtype="f64") -> int:
+    return int(load().ff_qr_workspace_size(m, n, s, _dt(dtype), 0))
+
+
+def qr_step(m: int, n: int, s: int) -> int:
+    """The block width qr_factor uses for step s (bounded by the Gram-Schmidt
+    kernel's LDS-resident block)."""
+    return int(load().ff_qr_step(m, n, s))
+
+
+def qr_factor(A: torch.Tensor, s: int, Q: torch.Tensor | None = None, R: torch.Tensor | None = None,
+              dtype="f64", stream=None, ws: torch.Tensor | None = None, info: torch.Tensor | None = None,
+              sync=False):
+    """A = Q R (A m x n column-major, m >= n, read only).  Returns (Q, R, info);
+    info is an int when sync, else the device tensor."""
+    lib = load()
+    dt = _dt(dtype)
+    m, n = int(A.shape[0]), int(A.shape[1])
+    if Q is None:
+        Q = colmajor_empty(m, n, A.dtype, A.device)
+    if R is None:
+        R = colmajor_empty(n, n, A.dtype, A.device)
+    if ws is None:
+        ws = _workspace(int(lib.ff_qr_workspace_size(m, n, s, dt, 0)), A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    rc = lib.qr_factor(m, n, s, _ptr(A), _ld(A, "A"), _ptr(Q), _ld(Q, "Q"), _ptr(R), _ld(R, "R"), dt, 0,
+                       _ptr(ws), 0 if ws is None else ws.numel(), _ptr(info), _stream(stream))
+    _check(rc, "qr_factor")
+    if sync:
+        (stream or torch.cuda.current_stream()).synchronize()
+        return Q, R, int(info.item())
+    return Q, R, info
 
 
 def solve_workspace_size(n: int, s: int, nrhs: int, dtype="f64", escalate=False, gmres=False) -> int:

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfastfact.so")
-SOURCES = ["update.hip", "strassen.hip", "panel.hip", "solve.hip", "driver.hip", "serve.hip"]
+SOURCES = ["update.hip", "strassen.hip", "panel.hip", "solve.hip", "qr.hip", "driver.hip", "serve.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

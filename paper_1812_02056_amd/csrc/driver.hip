@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "fastfact.h"
+#include "grid.hpp"
 #include "internal.hpp"
 
 // Device scratch of the allocation-free entry point (see noalloc_scratch).
@@ -954,6 +955,61 @@ int noalloc_scratch(void** out) {
     *out = noalloc_scratch_ptr[dev];
     return 0;
 }
+
+// ---------------------------------------------------------------- QR (Algorithm 3)
+// Workspace of qr_factor: the grid-count word, the panel's published shares,
+// the block product C = B_Q^T M[:, c..] and the split-K partial products.
+struct QrWs {
+    int* ctl;
+    double* part;
+    double* C;
+    double* tp;
+    size_t bytes;
+};
+
+int qr_step(int64_t m, int64_t n, int64_t s) {
+    return (int)std::min<int64_t>(std::min<int64_t>(s, n), qr_panel_max_width(m));
+}
+
+QrWs carve_qr(void* base, int64_t m, int64_t n, int64_t s) {
+    Carver cv(base);
+    QrWs w;
+    const int ws = qr_step(m, n, s);
+    size_t tp = tn_gemm_part_elems((int)n, (int)n, (int)m, true);
+    for (int64_t z = 0; z < n; z += ws) {
+        const int wb = (int)std::min<int64_t>(ws, n - z);
+        const int64_t N = n - z - wb;
+        if (N > 0) tp = std::max(tp, tn_gemm_part_elems(wb, (int)N, (int)m, false));
+    }
+    w.ctl = cv.take<int>(64);
+    w.part = cv.take<double>(qr_panel_part_elems(m, ws));
+    w.C = cv.take<double>((size_t)ws * (size_t)n);
+    w.tp = cv.take<double>(tp);
+    w.bytes = cv.off;
+    return w;
+}
+
+// Algorithm 3 with step ws: Q := A (Q holds M), then per block the in-block
+// Gram-Schmidt, the block product C = B_Q^T M[:, c..] and M[:, c..] -= B_Q C;
+// finally R = Q^T A.  Every kernel does nothing once *d_info != 0.
+int qr_blocked(int m, int n, int ws, const double* A, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
+               const QrWs& w, int* d_info, hipStream_t st) {
+    FF_TRY(hipMemcpy2DAsync(Q, (size_t)ldq * sizeof(double), A, (size_t)lda * sizeof(double),
+                            (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st));
+    for (int z = 0; z < n; z += ws) {
+        const int wb = std::min(ws, n - z);
+        double* Bq = Q + (int64_t)z * ldq;
+        FF_TRY(launch_qr_panel(m, wb, z, Bq, ldq, w.part, w.ctl, d_info, st));
+        const int N = n - z - wb;
+        if (N <= 0) break;
+        double* Bm = Q + (int64_t)(z + wb) * ldq;
+        FF_TRY(launch_tn_gemm(wb, N, m, Bq, ldq, Bm, ldq, w.C, wb, false, w.tp, d_info, st));
+        FF_TRY(launch_update<double>(m, N, wb, Bm, ldq, Bq, ldq, w.C, wb, false, false, 0, d_info, st, 0, 0, 0.0,
+                                     1.0));
+    }
+    FF_TRY(launch_tn_gemm(n, n, m, Q, ldq, A, lda, R, ldr, true, w.tp, d_info, st));
+    return 0;
+}
 }  // namespace
 }  // namespace ff
 
@@ -1019,6 +1075,45 @@ int lu_nopiv_factor(int64_t n, int64_t s, void* A, int64_t lda, int dtype, unsig
     if (n == 0) return 0;
     const int si = (int)std::min<int64_t>(s, n);
     return lu_blocked((int)n, si, static_cast<double*>(A), lda, flags, d_info, 0, st);
+}
+
+size_t ff_qr_workspace_size(int64_t m, int64_t n, int64_t s, int dtype, unsigned flags) {
+    (void)dtype; (void)flags;
+    if (n <= 0 || m < n || s < 1 || qr_panel_rows(m) == 0) return 0;
+    return carve_qr(nullptr, m, n, s).bytes;
+}
+
+int qr_factor(int64_t m, int64_t n, int64_t s, const void* A, int64_t lda, void* Q, int64_t ldq, void* R, int64_t ldr,
+              int dtype, unsigned flags, void* ws, size_t ws_bytes, int32_t* d_info, void* stream) {
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return -2;
+    if (m < n || m > (int64_t)INT32_MAX / 2) return -1;
+    if (s < 1) return -3;
+    if (n > 0 && A == nullptr) return -4;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (n > 0 && Q == nullptr) return -6;
+    if (ldq < std::max<int64_t>(1, m)) return -7;
+    if (n > 0 && R == nullptr) return -8;
+    if (ldr < std::max<int64_t>(1, n)) return -9;
+    if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -10;
+    if (flags != 0) return -11;
+    if (d_info == nullptr) return -14;
+    if (dtype != FF_F64) return FF_ERR_UNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (launch_set_int(d_info, 0, st) != hipSuccess) return FF_ERR_HIP;
+    if (n == 0) return 0;
+    if (qr_panel_rows(m) == 0 || !tn_gemm_fits(m, ldq, std::max(ldq, lda)) || !ld_fits(ldq, sizeof(double)) ||
+        !ld_fits(ldr, sizeof(double)))
+        return FF_ERR_UNSUPPORTED;
+    const size_t need = ff_qr_workspace_size(m, n, s, dtype, flags);
+    if (ws == nullptr || ws_bytes < need) return FF_ERR_WORKSPACE;
+    const QrWs w = carve_qr(ws, m, n, s);
+    return qr_blocked((int)m, (int)n, qr_step(m, n, s), static_cast<const double*>(A), lda, static_cast<double*>(Q),
+                      ldq, static_cast<double*>(R), ldr, w, d_info, st);
+}
+
+int ff_qr_step(int64_t m, int64_t n, int64_t s) {
+    if (n <= 0 || m < n || s < 1) return 0;
+    return qr_step(m, n, s);
 }
 
 size_t ff_solve_workspace_size(int64_t n, int64_t s, int64_t nrhs, int dtype, unsigned flags) {

@@ -1,0 +1,446 @@
+// qr.hip -- QR factorisation by Gram-Schmidt with deferred block projections.
+//
+// Sec. 2 of arXiv 1812.02056, Algorithm 3.  M starts as a copy of A; here M lives
+// in the output Q (column c of M is not read again once column c of Q exists).
+// Per block of w columns:
+//   (1) in-block modified Gram-Schmidt: each column is projected against the
+//       block's earlier columns one at a time, every product taken with the
+//       vector as updated so far, and divided by its norm;
+//   (2) block projection of the finished block B_Q out of the later columns:
+//       C = B_Q^T M[:, c..], then M[:, c..] -= B_Q C.
+// Finally R = Q^T A (its upper triangle; the strict lower triangle is zero).
+//
+// Kernels:
+//   qr_panel_kernel  (1) on P co-resident workgroups, each holding RR rows of the
+//                    block in LDS.  MGS runs right-looking: in round j column j
+//                    is normalised and projected out of the block's later
+//                    columns.  Every column still receives the same projections
+//                    in the same order as in the left-looking form.  A round
+//                    needs one grid-wide sum (the norm of v_j and the products
+//                    v_j . v_c), taken in a fixed order so that every workgroup
+//                    holds bitwise the same values.
+//   tn_gemm_kernel   D = X^T Y with both operands K-major (the product of (2)
+//                    and R = Q^T A), v_mfma_f64_16x16x4f64 on 128 x 128 tiles,
+//                    split over K into partial products that tn_reduce_kernel
+//                    sums in a fixed order.
+// The subtraction of (2) is the LU trailing-update kernel (update.hip).
+#include <algorithm>
+
+#include "common.hpp"
+#include "fastfact.h"
+#include "grid.hpp"
+#include "internal.hpp"
+
+namespace ff {
+
+namespace {
+
+// ---------------------------------------------------------------- products
+constexpr int TG_T = 128;          // output tile edge
+constexpr int TG_BK = 16;          // K depth of one LDS stage
+constexpr int TG_P = TG_T + 4;     // LDS row pitch: the staging writes of a wave
+                                   // (8 columns x 8 K pairs) then cover every bank pair once
+constexpr int TG_NT = 256;         // 2 x 2 waves, each a 64 x 64 part of the tile
+
+__device__ __forceinline__ void load2(rsrc_t r, int off, double& a, double& b) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    u2 lo, hi;
+    lo.x = v.x; lo.y = v.y;
+    hi.x = v.z; hi.y = v.w;
+    a = __builtin_bit_cast(double, lo);
+    b = __builtin_bit_cast(double, hi);
+}
+
+// D(i, j) = sum over k in this workgroup's K range of X(k, i) Y(k, j), for
+// i < M, j < N, where X(k, i) = X[k + i*ldx] and Y(k, j) = Y[k + j*ldy].
+// Workgroup b takes K part q = b % ks of tile b / ks and writes it to
+// D + q * dstride (ks = 1: D itself).  UPPER: tiles are the upper triangle of the
+// tile grid (column-major triangle order) and only entries with i <= j are
+// written.
+template <bool UPPER>
+__global__ __launch_bounds__(TG_NT, 2)
+void tn_gemm_kernel(int M, int N, int K, int kchunk, int ks, int tiles_m, const double* __restrict__ X,
+                    int64_t ldx, const double* __restrict__ Y, int64_t ldy, double* __restrict__ D, int64_t ldd,
+                    int64_t dstride, const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    __shared__ double As[2][TG_BK][TG_P];   // As[k][i] = X(k0 + k, row0 + i)
+    __shared__ double Bs[2][TG_BK][TG_P];   // Bs[k][j] = Y(k0 + k, col0 + j)
+    const int b = blockIdx.x;
+    const int q = b % ks, tile = b / ks;
+    int bi, bj;
+    if (UPPER) {
+        bj = tri_row(tile);
+        bi = tile - bj * (bj + 1) / 2;
+    } else {
+        bi = tile % tiles_m;
+        bj = tile / tiles_m;
+    }
+    const int kb = q * kchunk;
+    const int kc = min(K, kb + kchunk) - kb;
+    const int row0 = bi * TG_T, col0 = bj * TG_T;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave & 1, wc = wave >> 1;
+
+    // Staging: 8 lanes read one 128-byte run (16 K values) of a column; a
+    // thread owns K pair kp and columns sc + 32 u, u = 0..3.
+    const int kp = 2 * (tid & 7), sc = tid >> 3;
+    const rsrc_t rx = make_rsrc(X + kb + (int64_t)row0 * ldx);
+    const rsrc_t ry = make_rsrc(Y + kb + (int64_t)col0 * ldy);
+    int ox[4], oy[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = sc + 32 * u;
+        ox[u] = row0 + c < M ? (kp + c * (int)ldx) * 8 : BUF_OOB;
+        oy[u] = col0 + c < N ? (kp + c * (int)ldy) * 8 : BUF_OOB;
+    }
+    double xa[4][2], ya[4][2];
+    const int nk = (kc + TG_BK - 1) / TG_BK;
+    auto load = [&](int kt) {
+        const int k0 = kt * TG_BK;
+        if (k0 + TG_BK <= kc) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                load2(rx, ox[u] == BUF_OOB ? BUF_OOB : ox[u] + k0 * 8, xa[u][0], xa[u][1]);
+                load2(ry, oy[u] == BUF_OOB ? BUF_OOB : oy[u] + k0 * 8, ya[u][0], ya[u][1]);
+            }
+        } else {
+            // last, partial stage: K values at or past kc read as zero
+            const bool v0 = k0 + kp < kc, v1 = k0 + kp + 1 < kc;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xa[u][0] = buf_load<double>(rx, v0 && ox[u] != BUF_OOB ? ox[u] + k0 * 8 : BUF_OOB);
+                xa[u][1] = buf_load<double>(rx, v1 && ox[u] != BUF_OOB ? ox[u] + k0 * 8 + 8 : BUF_OOB);
+                ya[u][0] = buf_load<double>(ry, v0 && oy[u] != BUF_OOB ? oy[u] + k0 * 8 : BUF_OOB);
+                ya[u][1] = buf_load<double>(ry, v1 && oy[u] != BUF_OOB ? oy[u] + k0 * 8 + 8 : BUF_OOB);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            As[buf][kp][sc + 32 * u] = xa[u][0];
+            As[buf][kp + 1][sc + 32 * u] = xa[u][1];
+            Bs[buf][kp][sc + 32 * u] = ya[u][0];
+            Bs[buf][kp + 1][sc + 32 * u] = ya[u][1];
+        }
+    };
+
+    d4_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = zero_vec<d4_t>();
+    // Transposed product tile (lanes along output rows): the MFMA A input is the
+    // column operand, the B input the row operand.
+    auto frags = [&](int buf, int k4, double (&fa)[4], double (&fb)[4]) {
+        const int kk = 4 * k4 + (lane >> 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fa[u] = Bs[buf][kk][64 * wc + 16 * u + (lane & 15)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fb[u] = As[buf][kk][64 * wr + 16 * u + (lane & 15)];
+    };
+    auto mma = [&](const double (&fa)[4], const double (&fb)[4]) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) acc[cb][r4] = mfma_f64(fa[cb], fb[r4], acc[cb][r4]);
+    };
+    auto compute = [&](int buf) {
+        double fa0[4], fb0[4], fa1[4], fb1[4];
+        __builtin_amdgcn_s_setprio(1);
+        frags(buf, 0, fa0, fb0);
+#pragma unroll
+        for (int k4 = 0; k4 < TG_BK / 4; k4 += 2) {
+            frags(buf, k4 + 1, fa1, fb1);
+            mma(fa0, fb0);
+            if (k4 + 2 < TG_BK / 4) frags(buf, k4 + 2, fa0, fb0);
+            mma(fa1, fb1);
+        }
+        __builtin_amdgcn_s_setprio(0);
+    };
+
+    if (nk > 0) {
+        load(0);
+        store(0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) load(kt + 1);
+            compute(kt & 1);      // zero-filled K positions add nothing
+            if (kt + 1 < nk) store((kt + 1) & 1);
+            __syncthreads();
+        }
+    }
+
+    double* Dq = D + (int64_t)q * dstride;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = col0 + 64 * wc + 16 * cb + 4 * r + (lane >> 4);
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int i = row0 + 64 * wr + 16 * r4 + (lane & 15);
+                if (i < M && j < N && (!UPPER || i <= j)) Dq[i + (int64_t)j * ldd] = acc[cb][r4][r];
+            }
+        }
+}
+
+// D(i, j) = sum_q P[q * pstride + i + j * M] for q = 0, 1, ... in order
+// (UPPER: entries with i > j are set to zero instead).
+__global__ void tn_reduce_kernel(int M, int N, int ks, const double* __restrict__ P, int64_t pstride,
+                                 double* __restrict__ D, int64_t ldd, int upper, const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    const int64_t total = (int64_t)M * N;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % M), j = (int)(e / M);
+        double v = 0.0;
+        if (!upper || i <= j)
+            for (int q = 0; q < ks; ++q) v += P[q * pstride + e];
+        D[i + (int64_t)j * ldd] = v;
+    }
+}
+
+// D(i, j) = 0 for i > j (the strict lower triangle of an n x n matrix).
+__global__ void zero_strict_lower_kernel(int n, double* __restrict__ D, int64_t ldd, const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        if (i > j) D[i + (int64_t)j * ldd] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- in-block MGS
+constexpr int QR_LDS = QR_PANEL_LDS_DOUBLES;   // panel slab, doubles
+constexpr int QR_NT = 256;
+constexpr int QR_SPIN_LIMIT = 1 << 20;
+
+// Block columns [0, w) of Mp (m rows, leading dimension ldm) are replaced by the
+// orthonormal columns of modified Gram-Schmidt.  Workgroup g holds rows
+// [g RR, (g+1) RR) in LDS (column pitch RR + 1); gridDim.x = P = ceil(m / RR)
+// workgroups, all resident at once (one per CU, by their LDS).
+//
+// Round j: (a) each workgroup forms its rows' share of v_j . v_c, c = j..w-1
+// (wave h sums rows [h RR/4, (h+1) RR/4) in row order, the four waves' sums
+// are added in wave order) and publishes it in part[j % 2][g][c - j]; (b) the
+// workgroups count themselves in on *ctl and wait until all P have; (c) each
+// workgroup adds the P shares, wave h over workgroups [h P/4, (h+1) P/4) in
+// order, then the four in wave order: all workgroups obtain the same sums S_c;
+// (d) ||v_j|| = sqrt(S_j), q_j = v_j / ||v_j||, and v_c -= q_j (S_c / ||v_j||)
+// for c > j (S_c / ||v_j|| is q_j . v_c up to rounding).
+// Shares of round j are overwritten in round j + 2 only after every workgroup
+// has passed round j + 1's count, i.e. after it read round j's shares.
+// A norm that is not > 0 (zero or NaN) sets *info = col0 + j + 1 and ends the
+// kernel in every workgroup (all hold the same sums); a count wait that exceeds
+// its bound sets *info = -1.
+template <int RR>
+__global__ __launch_bounds__(QR_NT, 1)
+void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ldm, double* part, int* ctl,
+                     int* info)
+{
+    static_assert(RR % 4 == 0 && RR <= QR_NT && QR_NT % RR == 0, "row split");
+    constexpr int RP = RR + 1;
+    constexpr int RQ = RR / 4;
+    constexpr int CSTEP = QR_NT / RR;
+    __shared__ double slab[QR_LDS];
+    __shared__ double red[4][QR_PANEL_WMAX];
+    __shared__ double dv[QR_PANEL_WMAX];
+    __shared__ int bad;
+    if (__hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    const int P = gridDim.x, g = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, h = t >> 6;
+    const int r0 = g * RR;
+    for (int idx = t; idx < w * RR; idx += QR_NT) {
+        const int c = idx / RR, r = idx % RR;
+        slab[c * RP + r] = r0 + r < m ? Mp[r0 + r + (int64_t)c * ldm] : 0.0;
+    }
+    if (t == 0) bad = 0;
+    const int g_lo = h * P / 4, g_hi = (h + 1) * P / 4;
+    const int ur = t % RR, uc = t / RR;
+    __syncthreads();
+
+    for (int j = 0; j < w; ++j) {
+        const int nc = w - j;
+        double* pj = part + (size_t)(j & 1) * (size_t)P * (size_t)w;
+        // (a)
+        for (int ci = lane; ci < nc; ci += 64) {
+            const double* vj = slab + j * RP + h * RQ;
+            const double* vc = slab + (j + ci) * RP + h * RQ;
+            double acc = 0.0;
+#pragma unroll 8
+            for (int r = 0; r < RQ; ++r) acc += vj[r] * vc[r];
+            red[h][ci] = acc;
+        }
+        __syncthreads();
+        if (t < nc) {
+            const double p = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+            __hip_atomic_store(pj + (size_t)g * w + t, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        }
+        __syncthreads();
+        // (b)
+        if (t == 0) {
+            __hip_atomic_fetch_add(ctl, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const int target = P * (j + 1);
+            int spins = 0;
+            while (__hip_atomic_load(ctl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (++spins > QR_SPIN_LIMIT) {
+                    bad = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        if (bad) {
+            if (t == 0) __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        // (c)
+        for (int ci = lane; ci < nc; ci += 64) {
+            double acc = 0.0;
+            for (int gg = g_lo; gg < g_hi; ++gg)
+                acc += __hip_atomic_load(pj + (size_t)gg * w + ci, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            red[h][ci] = acc;
+        }
+        __syncthreads();
+        if (t < nc) dv[t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+        __syncthreads();
+        // (d)
+        const double nrm = sqrt(dv[0]);
+        if (!(nrm > 0.0)) {
+            if (g == 0 && t == 0) __hip_atomic_store(info, col0 + j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        const double qv = slab[j * RP + ur] / nrm;
+        __syncthreads();                     // every read of v_j is done
+        if (uc == 0) slab[j * RP + ur] = qv;
+        for (int c = j + 1 + uc; c < w; c += CSTEP) slab[c * RP + ur] -= qv * (dv[c - j] / nrm);
+        __syncthreads();
+    }
+    for (int idx = t; idx < w * RR; idx += QR_NT) {
+        const int c = idx / RR, r = idx % RR;
+        if (r0 + r < m) Mp[r0 + r + (int64_t)c * ldm] = slab[c * RP + r];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+int qr_panel_rows(int64_t m) {
+    // 128 rows per workgroup while that needs at most one workgroup per CU,
+    // else 256 (then the panel is at most 71 columns wide)
+    const int64_t cus = cu_count();
+    if ((m + 127) / 128 <= cus) return 128;
+    if ((m + 255) / 256 <= cus) return 256;
+    return 0;
+}
+
+int qr_panel_max_width(int64_t m) {
+    const int rr = qr_panel_rows(m);
+    if (rr == 0) return 0;
+    return std::min(QR_PANEL_WMAX, QR_PANEL_LDS_DOUBLES / (rr + 1));
+}
+
+size_t qr_panel_part_elems(int64_t m, int w) {
+    const int rr = qr_panel_rows(m);
+    if (rr == 0) return 0;
+    return 2 * (size_t)((m + rr - 1) / rr) * (size_t)w;
+}
+
+hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* ctl, int* info,
+                           hipStream_t st) {
+    if (m <= 0 || w <= 0) return hipSuccess;
+    const int rr = qr_panel_rows(m);
+    if (rr == 0 || w > qr_panel_max_width(m)) return hipErrorInvalidValue;
+    const int P = (m + rr - 1) / rr;
+    hipError_t e = launch_set_int(ctl, 0, st);
+    if (e != hipSuccess) return e;
+    if (rr == 128)
+        hipLaunchKernelGGL(qr_panel_kernel<128>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, ctl, info);
+    else
+        hipLaunchKernelGGL(qr_panel_kernel<256>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, ctl, info);
+    return hipGetLastError();
+}
+
+namespace {
+struct TnPlan {
+    int tiles_m, tiles, ks, kchunk;
+};
+
+TnPlan tn_plan(int M, int N, int K, bool upper) {
+    TnPlan p;
+    p.tiles_m = (M + TG_T - 1) / TG_T;
+    const int tn = (N + TG_T - 1) / TG_T;
+    p.tiles = upper ? tn * (tn + 1) / 2 : p.tiles_m * tn;
+    const int target = 2 * cu_count();
+    int ks = 1;
+    while (ks < 16 && (int64_t)p.tiles * ks < target && K / (2 * ks) >= 512) ks *= 2;
+    int kchunk = (K + ks - 1) / ks;
+    kchunk = (kchunk + TG_BK - 1) / TG_BK * TG_BK;
+    p.kchunk = std::max(kchunk, TG_BK);
+    p.ks = (K + p.kchunk - 1) / p.kchunk;
+    if (p.ks < 1) p.ks = 1;
+    return p;
+}
+}  // namespace
+
+size_t tn_gemm_part_elems(int M, int N, int K, bool upper) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    const TnPlan p = tn_plan(M, N, K, upper);
+    return p.ks > 1 ? (size_t)p.ks * (size_t)M * (size_t)N : 0;
+}
+
+bool tn_gemm_fits(int64_t K, int64_t ldx, int64_t ldy) {
+    const int64_t span = (int64_t)K + (int64_t)TG_T * std::max(ldx, ldy);
+    return span * 8 < (int64_t)BUF_RECORDS - 64;
+}
+
+hipError_t launch_tn_gemm(int M, int N, int K, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* D,
+                          int64_t ldd, bool upper, double* part, const int* info, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (upper && M != N) return hipErrorInvalidValue;
+    if (K <= 0) {
+        // an empty sum: zeros (and the strict lower triangle for UPPER)
+        hipLaunchKernelGGL(tn_reduce_kernel, dim3(std::min<int64_t>(4096, ((int64_t)M * N + 255) / 256)), dim3(256),
+                           0, st, M, N, 0, (const double*)nullptr, (int64_t)0, D, ldd, upper ? 1 : 0, info);
+        return hipGetLastError();
+    }
+    if (!tn_gemm_fits(K, ldx, ldy)) return hipErrorInvalidValue;
+    const TnPlan p = tn_plan(M, N, K, upper);
+    const int nwg = p.tiles * p.ks;
+    if (p.ks == 1) {
+        if (upper)
+            hipLaunchKernelGGL(tn_gemm_kernel<true>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, 1, p.tiles_m,
+                               X, ldx, Y, ldy, D, ldd, (int64_t)0, info);
+        else
+            hipLaunchKernelGGL(tn_gemm_kernel<false>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, 1, p.tiles_m,
+                               X, ldx, Y, ldy, D, ldd, (int64_t)0, info);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !upper) return e;
+        hipLaunchKernelGGL(zero_strict_lower_kernel, dim3(std::min<int64_t>(4096, ((int64_t)M * N + 255) / 256)),
+                           dim3(256), 0, st, M, D, ldd, info);
+        return hipGetLastError();
+    }
+    if (part == nullptr) return hipErrorInvalidValue;
+    const int64_t ps = (int64_t)M * N;
+    if (upper)
+        hipLaunchKernelGGL(tn_gemm_kernel<true>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, p.ks, p.tiles_m, X,
+                           ldx, Y, ldy, part, (int64_t)M, ps, info);
+    else
+        hipLaunchKernelGGL(tn_gemm_kernel<false>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, p.ks, p.tiles_m,
+                           X, ldx, Y, ldy, part, (int64_t)M, ps, info);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tn_reduce_kernel, dim3(std::min<int64_t>(4096, (ps + 255) / 256)), dim3(256), 0, st, M, N,
+                       p.ks, (const double*)part, ps, D, ldd, upper ? 1 : 0, info);
+    return hipGetLastError();
+}
+
+}  // namespace ff

@@ -18,6 +18,11 @@ conditioning:
 * ``lu_int_family``  A = L0 U0, L0 unit lower and U0 upper with diag in {1,2},
   off-diagonal entries in {-1,0,1}.
 * ``diag_dominant``  U(-1,1) entries, diagonal 1 + row sum of |off-diagonal|.
+* ``qr_int_family``  A = Q0 R0 with Q0 = H[:, :n] / sqrt(m) (H the m x m Sylvester
+  Hadamard matrix, m a power of 4 so sqrt(m) is a power of two) and R0 = sqrt(m) U,
+  U upper triangular with diagonal in {1,2} and entries in {-1,0,1} above it:
+  every value Gram-Schmidt forms is a dyadic rational of modest size, so Q and R
+  must come out as Q0 and R0 bit for bit.
 
 All matrices are returned column-major (numpy order='F') float64.  Symmetric
 families are mirrored lower -> upper after forming, so they are bitwise symmetric.
@@ -102,6 +107,34 @@ def default_s(n: int) -> int:
     return max(1, int(round(float(n) ** 0.5286)))
 
 
+def hadamard(m: int) -> np.ndarray:
+    """Sylvester Hadamard matrix of order m (a power of two), entries +-1."""
+    if m < 1 or m & (m - 1):
+        raise ValueError("m must be a power of two")
+    H = np.ones((1, 1))
+    while H.shape[0] < m:
+        H = np.block([[H, H], [H, -H]])
+    return H
+
+
+def _qr_int_parts(m: int, n: int, seed: int):
+    k = int(round(np.log(m) / np.log(4)))
+    if 4 ** k != m or n > m:
+        raise ValueError("m must be a power of 4 and n <= m")
+    rng = np.random.default_rng(seed)
+    U = np.triu(rng.integers(-1, 2, size=(n, n)), 1).astype(np.float64)
+    U[np.diag_indices(n)] = rng.integers(1, 3, size=n)
+    return k, U
+
+
+def qr_int_family(m: int, n: int, seed: int = 0):
+    """(Q0, R0, A): A = H[:, :n] U exactly, Q0 = H[:, :n] / 2^k, R0 = 2^k U (m = 4^k)."""
+    k, U = _qr_int_parts(m, n, seed)
+    Hn = hadamard(m)[:, :n]
+    A = Hn @ U                                      # integers of magnitude <= n + 1: exact
+    return (np.asfortranarray(Hn / 2.0 ** k), np.asfortranarray(U * 2.0 ** k), np.asfortranarray(A))
+
+
 # ---------------------------------------------------------------------------
 # Device-side generators for the large configurations (torch; seeded per device).
 # The returned tensors hold the matrix in column-major order: element (i, j) at
@@ -180,3 +213,21 @@ def lu_int_family_device(n: int, seed: int = 0, device="cuda"):
     del lo, up
     A = torch.mm(L0, U0)
     return L0, U0, A
+
+
+def qr_int_family_device(m: int, n: int, seed: int = 0, device="cuda"):
+    """(Q0, R0, A) of ``qr_int_family`` as column-major device tensors (stride (1, rows));
+    A = H[:, :n] U by a binary64 GEMM, exact (integer partial sums of magnitude <= n + 1)."""
+    import torch
+    k, U = _qr_int_parts(m, n, seed)
+    H = torch.ones(1, 1, dtype=torch.float64, device=device)
+    while H.shape[0] < m:
+        H = torch.cat([torch.cat([H, H], 1), torch.cat([H, -H], 1)], 0)
+    Hn = H[:, :n].contiguous()
+    del H
+    Ud = torch.from_numpy(U).to(device)
+    A = torch.mm(Hn, Ud)
+
+    def cm(t):
+        return t.t().contiguous().t()
+    return cm(Hn / 2.0 ** k), cm(Ud * 2.0 ** k), cm(A)

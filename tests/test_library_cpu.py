@@ -127,3 +127,20 @@ def test_solve_info_layout_matches_the_header():
     fields = re.findall(r"(int32_t|double)\s+(\w+);", body)
     ctype = {"int32_t": ctypes.c_int32, "double": ctypes.c_double}
     assert [(n, ctype[t]) for t, n in fields] == list(binding.SolveInfo._fields_)
+
+
+def test_qr_argument_checks_and_workspace(lib):
+    # rejected before any device work: these run without a GPU
+    info = ctypes.c_int32(0)
+    p = ctypes.c_void_p(16)
+    assert lib.qr_factor(10, 20, 4, p, 10, p, 10, p, 20, 0, 0, p, 1 << 20, ctypes.byref(info), None) == -1
+    assert lib.qr_factor(20, 10, 0, p, 20, p, 20, p, 10, 0, 0, p, 1 << 20, ctypes.byref(info), None) == -3
+    assert lib.qr_factor(20, 10, 4, p, 19, p, 20, p, 10, 0, 0, p, 1 << 20, ctypes.byref(info), None) == -5
+    assert lib.qr_factor(20, 10, 4, p, 20, p, 20, p, 9, 0, 0, p, 1 << 20, ctypes.byref(info), None) == -9
+    assert lib.qr_factor(20, 10, 4, p, 20, p, 20, p, 10, 0, 1, p, 1 << 20, ctypes.byref(info), None) == -11
+    assert lib.qr_factor(20, 10, 4, p, 20, p, 20, p, 10, 0, 0, p, 1 << 20, None, None) == -14
+    assert lib.ff_qr_workspace_size(20, 10, 4, 0, 0) > 0
+    assert lib.ff_qr_workspace_size(10, 20, 4, 0, 0) == 0
+    assert lib.ff_qr_step(1000, 1000, 100) == 100
+    assert lib.ff_qr_step(1000, 50, 100) == 50
+    assert 1 <= lib.ff_qr_step(16384, 16384, 10 ** 6) <= 256

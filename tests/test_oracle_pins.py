@@ -532,3 +532,14 @@ def test_qr_project_integer_exact():
     Mn, C = oracle.qr_project(Bq, Bm.copy())
     assert np.array_equal(C, Bq.T @ Bm)
     assert np.array_equal(Mn, Bm - Bq @ (Bq.T @ Bm))
+
+
+@pytest.mark.parametrize("m,n", [(16, 16), (64, 40), (256, 256)])
+@pytest.mark.parametrize("s", [1, 5, 16, 300])
+def test_qr_integer_family_exact(m, n, s):
+    """A = H[:, :n] U: every quantity Gram-Schmidt forms is exact, so Algorithm 3 with
+    any step must return Q0 = H / 2^k and R0 = 2^k U bit for bit."""
+    Q0, R0, A = wl.qr_int_family(m, n, seed=m + s)
+    Q, R, _, info = oracle.qr_alg3(A, s)
+    assert info == 0
+    assert np.array_equal(Q, Q0) and np.array_equal(R, R0)
