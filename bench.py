@@ -60,7 +60,7 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision table")
     p.add_argument("--mixed-only", action="store_true", help="only the mixed-precision table")
-    p.add_argument("--leg", choices=("lowprec", "trisolve"), default=None,
+    p.add_argument("--leg", choices=("lowprec", "trisolve", "qr"), default=None,
                    help="only one leg, for profiling: the binary32 / bfloat16 factorisations, or the triangular solves")
     p.add_argument("--serving-only", action="store_true", help="only the serving leg (many independent solves)")
     p.add_argument("--serving-requests", type=int, default=10000)
@@ -105,6 +105,8 @@ def main():
         if args.leg == "lowprec":
             A0 = wl.spd_scaled_device(n, seed=0, lam=1.0, device=dev)
             res = run_low_precision_factor(ff, torch, dev, n, A0)
+        elif args.leg == "qr":
+            res = run_qr(ff, torch, wl, dev, n=n)
         else:
             res = run_trisolve(ff, torch, dev, n)
         log(f"[bench] {args.leg}: {res}")
@@ -360,6 +362,14 @@ def run_extras(ff, torch, wl, dev, n, A0):
         out["trisolve_n16384"] = {"error": str(e)}
     torch.cuda.empty_cache()
 
+    # --- QR (Algorithm 3)
+    try:
+        out["qr_f64_n16384"] = run_qr(ff, torch, wl, dev, n=n)
+        log(f"[bench] QR: {out['qr_f64_n16384']}")
+    except Exception as e:
+        out["qr_f64_n16384"] = {"error": str(e)}
+    torch.cuda.empty_cache()
+
     # --- serving: continuous batching of many independent solves
     try:
         out["serving"] = run_serving(ff, torch, wl, dev)
@@ -612,6 +622,61 @@ def run_low_precision_factor(ff, torch, dev, n, A0, reps=3):
     return res
 
 
+def run_qr(ff, torch, wl, dev, n=16384, steps=(64, 96, 128, 142), reps=3, paper_sizes=((2000, 100), (4000, 200))):
+    """qr_factor (Algorithm 3) on the benchmark family A = G G^T / n + I: median
+    time per step, the rate at the conventional 4n^3/3 and at the algorithm's own
+    count (projections 2 n^3, R = Q^T A's upper triangle n^2 (n + 1)), and
+    orthogonality / residual by torch's binary64 GEMMs; the paper's two sizes
+    (n = 2000, s = 100; n = 4000, s = 200, the block capped at ff.qr_step) for
+    context."""
+    res = {}
+    A = wl.spd_scaled_device(n, seed=0, lam=1.0, device=dev).t()     # symmetric
+    Q = ff.colmajor_empty(n, n, torch.float64, dev)
+    R = ff.colmajor_empty(n, n, torch.float64, dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    sweep = {}
+    for s in steps:
+        ws = torch.empty(max(1, ff.qr_workspace_size(n, n, s)), dtype=torch.uint8, device=dev)
+
+        def call():
+            ff.qr_factor(A, s, Q=Q, R=R, ws=ws, info=info)
+        dt, _ = median_time(call, reps, torch)
+        sweep[s] = (dt, ff.qr_step(n, n, s), int(info.item()))
+        del ws
+    s_best = min(sweep, key=lambda k: sweep[k][0])
+    dt, blk, inf = sweep[s_best]
+    ws = torch.empty(max(1, ff.qr_workspace_size(n, n, s_best)), dtype=torch.uint8, device=dev)
+    ff.qr_factor(A, s_best, Q=Q, R=R, ws=ws, info=info)
+    torch.cuda.synchronize()
+    QtQ = torch.mm(Q.t(), Q)
+    QtQ.diagonal().sub_(1.0)
+    orth = float(QtQ.abs().max())
+    del QtQ
+    resid = float((torch.mm(Q, R) - A).abs().max() / A.abs().max())
+    alg = 2.0 * n ** 3 + n * n * (n + 1.0)
+    res[f"n{n}"] = {"s": s_best, "block": blk, "ms": round(dt * 1e3, 3), "info": inf,
+                    "tflops_4n3_3": round(4 * n ** 3 / 3 / dt / 1e12, 3),
+                    "tflops_algorithmic": round(alg / dt / 1e12, 3),
+                    "frac_of_fp64_mfma_peak": round(alg / dt / 1e12 / MI355X_PEAK_TFLOPS["f64"], 4),
+                    "orth_max": orth, "resid_max_rel": resid,
+                    "s_sweep_ms": {str(k): round(v[0] * 1e3, 3) for k, v in sweep.items()}}
+    del A, Q, R, ws
+    torch.cuda.empty_cache()
+    for m, s in paper_sizes:
+        A = wl.spd_scaled_device(m, seed=1, lam=1.0, device=dev).t()
+        Q = ff.colmajor_empty(m, m, torch.float64, dev)
+        R = ff.colmajor_empty(m, m, torch.float64, dev)
+        ws = torch.empty(max(1, ff.qr_workspace_size(m, m, s)), dtype=torch.uint8, device=dev)
+
+        def call():
+            ff.qr_factor(A, s, Q=Q, R=R, ws=ws, info=info)
+        dt, _ = median_time(call, max(reps, 5), torch)
+        res[f"n{m}_s{s}"] = {"block": ff.qr_step(m, m, s), "ms": round(dt * 1e3, 3), "info": int(info.item()),
+                             "tflops_4n3_3": round(4 * m ** 3 / 3 / dt / 1e12, 3)}
+        del A, Q, R, ws
+    return res
+
+
 def run_trisolve(ff, torch, dev, n, reps=5):
     """chol_trisolve (forward + backward sweep, including the per-factor inverse
     blocks) on a well-conditioned factor: median ms per call and the rate against
@@ -640,13 +705,19 @@ def run_trisolve(ff, torch, dev, n, reps=5):
     return res
 
 
+# (name, factor precision, GMRES-based refinement)
+VARIANTS = (("f64", "f64", False), ("f32", "f32", False), ("bf16", "bf16", False),
+            ("f32_gmres", "f32", True), ("bf16_gmres", "bf16", True))
+
+
 def run_mixed_table(ff, torch, wl, dev, sizes=(16384, 32768), lams=(1.0, 1e-3, 1e-6), reps=3, oracle_refs=True,
                     oracle_L1=None):
     """Mixed-precision solves against the plain binary64 solve over the
     configuration's grid: n, lambda (A = G G^T / n + lambda I) and 1 or 16
     right-hand sides.  binary64: factor + one forward/backward solve.  binary32 and
     bfloat16: factor, refinement to ||dX|| <= 1e-12 ||X|| (or stagnation) with
-    escalation to a higher precision when that fails.  Every result's error is
+    escalation to a higher precision when that fails; the *_gmres variants solve
+    each correction equation by factor-preconditioned GMRES.  Every result's error is
     stated: backward error by torch's binary64 GEMM (independent of the library),
     forward error against the CPU oracle's solution at n = 16384 and against the
     binary64 GPU solve at larger n (labelled).  Accuracy criterion: backward error
@@ -672,16 +743,17 @@ def run_mixed_table(ff, torch, wl, dev, sizes=(16384, 32768), lams=(1.0, 1e-3, 1
                 B = wl.rhs_device(n, nrhs, seed=1000, device=dev).t()       # n x nrhs column-major
                 Xo = oracle.chol_solve(Lo, B.cpu().numpy()) if Lo is not None else None
                 cell, xs = {}, {}
-                for dtype in ("f64", "f32", "bf16"):
+                for name, dtype, gm in VARIANTS:
                     s = MIXED_STEP.get(n, MIXED_STEP[16384])[dtype]
                     W = ff.colmajor_empty(n, n, torch.float64 if dtype == "f64" else torch.float32, dev)
-                    ws = torch.empty(ff.solve_workspace_size(n, s, nrhs, dtype, escalate=dtype != "f64"),
+                    ws = torch.empty(ff.solve_workspace_size(n, s, nrhs, dtype, escalate=dtype != "f64", gmres=gm),
                                      dtype=torch.uint8, device=dev)
                     X = ff.colmajor_empty(n, nrhs, torch.float64, dev)
 
                     def solve():
                         return ff.chol_solve(A.t(), B, s, dtype=dtype, W=W, X=X, ws=ws, tol=1e-12,
-                                             max_iter=0 if dtype == "f64" else 50, escalate=dtype != "f64")[2]
+                                             max_iter=0 if dtype == "f64" else (20 if gm else 50),
+                                             escalate=dtype != "f64", gmres=gm)[2]
                     dt, info = median_time(solve, reps, torch)
                     R = B - A @ X
                     bx = float((R.abs().amax(dim=0) / (anorm * X.abs().amax(dim=0) + B.abs().amax(dim=0))).max())
@@ -689,22 +761,23 @@ def run_mixed_table(ff, torch, wl, dev, sizes=(16384, 32768), lams=(1.0, 1e-3, 1
                          "dtype_used": ["f64", "f32", "bf16"][info["dtype_used"]], "escalations": info["escalations"],
                          "first_info": info["first_info"], "iters": info["total_iters"], "info": info["info"],
                          "bwd_x": bx}
+                    if gm:
+                        e["krylov_iters"] = info["krylov_iters"]
                     if Xo is not None:
                         e["fwd_x_vs_oracle"] = float(np.max(np.abs(X.cpu().numpy() - Xo)) / np.max(np.abs(Xo)))
-                    xs[dtype] = X
-                    cell[dtype] = e
+                    xs[name] = X
+                    cell[name] = e
                     del W, ws, R
                 if Xo is None:
                     X64 = xs["f64"]
-                    for dtype in ("f64", "f32", "bf16"):
-                        cell[dtype]["fwd_x_vs_f64_gpu_solve"] = float((xs[dtype] - X64).abs().max() / X64.abs().max())
+                    for name in cell:
+                        cell[name]["fwd_x_vs_f64_gpu_solve"] = float((xs[name] - X64).abs().max() / X64.abs().max())
                 fkey = "fwd_x_vs_oracle" if Xo is not None else "fwd_x_vs_f64_gpu_solve"
-                for dtype in ("f64", "f32", "bf16"):
-                    e = cell[dtype]
+                for name, e in cell.items():
                     e["meets_1e-12"] = bool(e["info"] == 0 and e["bwd_x"] <= 1e-12
                                             and (lam < 1e-3 or e[fkey] <= 1e-12))
-                for dtype in ("f32", "bf16"):
-                    cell[dtype]["beats_f64"] = bool(cell[dtype]["meets_1e-12"] and cell[dtype]["ms"] < cell["f64"]["ms"])
+                    if name != "f64":
+                        e["beats_f64"] = bool(e["meets_1e-12"] and e["ms"] < cell["f64"]["ms"])
                 key = f"n{n}_lam{lam:g}_nrhs{nrhs}"
                 table[key] = cell
                 log(f"[bench] mixed {key}: " + ", ".join(

@@ -957,10 +957,10 @@ int noalloc_scratch(void** out) {
 }
 
 // ---------------------------------------------------------------- QR (Algorithm 3)
-// Workspace of qr_factor: the grid-count word, the panel's published shares,
+// Workspace of qr_factor: the panel workgroups' flags, their published shares,
 // the block product C = B_Q^T M[:, c..] and the split-K partial products.
 struct QrWs {
-    int* ctl;
+    int* flag;
     double* part;
     double* C;
     double* tp;
@@ -981,7 +981,7 @@ QrWs carve_qr(void* base, int64_t m, int64_t n, int64_t s) {
         const int64_t N = n - z - wb;
         if (N > 0) tp = std::max(tp, tn_gemm_part_elems(wb, (int)N, (int)m, false));
     }
-    w.ctl = cv.take<int>(64);
+    w.flag = cv.take<int>(QR_PANEL_MAXWG);
     w.part = cv.take<double>(qr_panel_part_elems(m, ws));
     w.C = cv.take<double>((size_t)ws * (size_t)n);
     w.tp = cv.take<double>(tp);
@@ -996,10 +996,11 @@ int qr_blocked(int m, int n, int ws, const double* A, int64_t lda, double* Q, in
                const QrWs& w, int* d_info, hipStream_t st) {
     FF_TRY(hipMemcpy2DAsync(Q, (size_t)ldq * sizeof(double), A, (size_t)lda * sizeof(double),
                             (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st));
+    FF_TRY(launch_qr_flags_clear(w.flag, st));
     for (int z = 0; z < n; z += ws) {
         const int wb = std::min(ws, n - z);
         double* Bq = Q + (int64_t)z * ldq;
-        FF_TRY(launch_qr_panel(m, wb, z, Bq, ldq, w.part, w.ctl, d_info, st));
+        FF_TRY(launch_qr_panel(m, wb, z, Bq, ldq, w.part, w.flag, d_info, st));
         const int N = n - z - wb;
         if (N <= 0) break;
         double* Bm = Q + (int64_t)(z + wb) * ldq;

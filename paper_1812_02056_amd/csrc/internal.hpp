@@ -18,15 +18,19 @@ hipError_t launch_set_int(int* p, int v, hipStream_t st);
 
 // QR (qr.hip).  In-block modified Gram-Schmidt of w columns of Mp (m rows) on
 // co-resident workgroups of qr_panel_rows(m) rows each (0: m too large);
-// w <= qr_panel_max_width(m).  part: qr_panel_part_elems(m, w) doubles; ctl: one
-// int of scratch; info: 0 on entry or the kernel does nothing; set to col0 + j + 1
-// when column j's norm is not > 0, to -1 when a grid-wide wait expired.
+// w <= qr_panel_max_width(m).  part: qr_panel_part_elems(m, w) doubles; flag:
+// QR_PANEL_MAXWG ints, cleared by launch_qr_flags_clear once before the first
+// panel of a factorisation (panels take increasing col0); info: 0 on entry or the
+// kernel does nothing; set to col0 + j + 1 when column j's norm is not > 0, to
+// -1 when a grid-wide wait expired.
 constexpr int QR_PANEL_LDS_DOUBLES = 18432;   // 144 KB of LDS per workgroup
 constexpr int QR_PANEL_WMAX = 256;
+constexpr int QR_PANEL_MAXWG = 256;
+hipError_t launch_qr_flags_clear(int* flag, hipStream_t st);
 int qr_panel_rows(int64_t m);
 int qr_panel_max_width(int64_t m);
 size_t qr_panel_part_elems(int64_t m, int w);
-hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* ctl, int* info,
+hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* flag, int* info,
                            hipStream_t st);
 // D = X^T Y (M x N) with X(k, i) = X[k + i*ldx], Y(k, j) = Y[k + j*ldy], k < K.
 // upper: M == N and only the upper triangle is formed, the strict lower

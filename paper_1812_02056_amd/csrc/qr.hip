@@ -220,6 +220,7 @@ __global__ void zero_strict_lower_kernel(int n, double* __restrict__ D, int64_t 
 constexpr int QR_LDS = QR_PANEL_LDS_DOUBLES;   // panel slab, doubles
 constexpr int QR_NT = 256;
 constexpr int QR_SPIN_LIMIT = 1 << 20;
+constexpr int QR_GB = 16;           // shares per column a lane loads at once
 
 // Block columns [0, w) of Mp (m rows, leading dimension ldm) are replaced by the
 // orthonormal columns of modified Gram-Schmidt.  Workgroup g holds rows
@@ -229,19 +230,28 @@ constexpr int QR_SPIN_LIMIT = 1 << 20;
 // Round j: (a) each workgroup forms its rows' share of v_j . v_c, c = j..w-1
 // (wave h sums rows [h RR/4, (h+1) RR/4) in row order, the four waves' sums
 // are added in wave order) and publishes it in part[j % 2][g][c - j]; (b) the
-// workgroups count themselves in on *ctl and wait until all P have; (c) each
+// workgroup sets flag[g] = col0 + j + 1 and waits until every flag has reached
+// that value (flags grow over the whole factorisation, so they are cleared once
+// per call, and no workgroup contends for another's word); (c) each
 // workgroup adds the P shares, wave h over workgroups [h P/4, (h+1) P/4) in
 // order, then the four in wave order: all workgroups obtain the same sums S_c;
 // (d) ||v_j|| = sqrt(S_j), q_j = v_j / ||v_j||, and v_c -= q_j (S_c / ||v_j||)
 // for c > j (S_c / ||v_j|| is q_j . v_c up to rounding).
+// The panel is at most 256 columns wide, so a lane holds at most 4 of them.
 // Shares of round j are overwritten in round j + 2 only after every workgroup
 // has passed round j + 1's count, i.e. after it read round j's shares.
+// Shares and flags are agent-scope atomics, which gfx950 serves at the
+// device's coherence point (no stale per-XCD L2 copy); a share's store has
+// completed (waitcnt) before its workgroup sets its flag, and the shares are
+// loaded only after every flag was seen set.  No cache-wide write-back or
+// invalidate is needed, so the 2w waits of a panel stay at the latency of a
+// few device-memory round trips.
 // A norm that is not > 0 (zero or NaN) sets *info = col0 + j + 1 and ends the
 // kernel in every workgroup (all hold the same sums); a count wait that exceeds
 // its bound sets *info = -1.
 template <int RR>
 __global__ __launch_bounds__(QR_NT, 1)
-void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ldm, double* part, int* ctl,
+void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ldm, double* part, int* flag,
                      int* info)
 {
     static_assert(RR % 4 == 0 && RR <= QR_NT && QR_NT % RR == 0, "row split");
@@ -251,6 +261,7 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
     __shared__ double slab[QR_LDS];
     __shared__ double red[4][QR_PANEL_WMAX];
     __shared__ double dv[QR_PANEL_WMAX];
+    __shared__ double dq[QR_PANEL_WMAX];
     __shared__ int bad;
     if (__hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
     const int P = gridDim.x, g = blockIdx.x;
@@ -281,20 +292,31 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
         if (t < nc) {
             const double p = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
             __hip_atomic_store(pj + (size_t)g * w + t, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);   // the share is written through before the count below
         }
         __syncthreads();
-        // (b)
-        if (t == 0) {
-            __hip_atomic_fetch_add(ctl, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const int target = P * (j + 1);
+        // (b) count in: flag[g] = col0 + j + 1; wave 0 polls every workgroup's flag
+        if (t == 0) __hip_atomic_store(flag + g, col0 + j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h == 0) {
+            const int target = col0 + j + 1;
             int spins = 0;
-            while (__hip_atomic_load(ctl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (++spins > QR_SPIN_LIMIT) {
-                    bad = 1;
-                    break;
+            bool done = false;
+            while (!done) {
+                bool mine = true;
+#pragma unroll
+                for (int u = 0; u < QR_PANEL_MAXWG / 64; ++u) {
+                    const int gg = lane + 64 * u;
+                    if (gg < P)
+                        mine &= __hip_atomic_load(flag + gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
                 }
-                __builtin_amdgcn_s_sleep(1);
+                done = __all(mine);
+                if (!done) {
+                    if (++spins > QR_SPIN_LIMIT) {
+                        if (lane == 0) bad = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
             }
         }
         __syncthreads();
@@ -302,12 +324,30 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
             if (t == 0) __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        // (c)
-        for (int ci = lane; ci < nc; ci += 64) {
-            double acc = 0.0;
-            for (int gg = g_lo; gg < g_hi; ++gg)
-                acc += __hip_atomic_load(pj + (size_t)gg * w + ci, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            red[h][ci] = acc;
+        // (c) every lane keeps up to 4 columns x QR_GB shares in flight; out-of-range
+        // slots load a clamped (valid) address and are masked at use
+        {
+            double accv[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int gg0 = g_lo; gg0 < g_hi; gg0 += QR_GB) {
+                double v[4][QR_GB];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int e = 0; e < QR_GB; ++e) {
+                        const int gg = min(gg0 + e, g_hi - 1);
+                        const int ci = min(lane + 64 * u, nc - 1);
+                        v[u][e] = __hip_atomic_load(pj + (size_t)gg * w + ci, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                    }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int e = 0; e < QR_GB; ++e)
+                        if (gg0 + e < g_hi) accv[u] += v[u][e];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (lane + 64 * u < nc) red[h][lane + 64 * u] = accv[u];
         }
         __syncthreads();
         if (t < nc) dv[t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
@@ -318,10 +358,11 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
             if (g == 0 && t == 0) __hip_atomic_store(info, col0 + j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
+        if (t > 0 && t < nc) dq[t] = dv[t] / nrm;
         const double qv = slab[j * RP + ur] / nrm;
-        __syncthreads();                     // every read of v_j is done
+        __syncthreads();                     // every read of v_j is done, dq is complete
         if (uc == 0) slab[j * RP + ur] = qv;
-        for (int c = j + 1 + uc; c < w; c += CSTEP) slab[c * RP + ur] -= qv * (dv[c - j] / nrm);
+        for (int c = j + 1 + uc; c < w; c += CSTEP) slab[c * RP + ur] -= qv * dq[c - j];
         __syncthreads();
     }
     for (int idx = t; idx < w * RR; idx += QR_NT) {
@@ -330,13 +371,17 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
     }
 }
 
+__global__ void qr_flags_clear_kernel(int* flag) {
+    flag[threadIdx.x] = 0;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
 int qr_panel_rows(int64_t m) {
     // 128 rows per workgroup while that needs at most one workgroup per CU,
     // else 256 (then the panel is at most 71 columns wide)
-    const int64_t cus = cu_count();
+    const int64_t cus = std::min(cu_count(), QR_PANEL_MAXWG);
     if ((m + 127) / 128 <= cus) return 128;
     if ((m + 255) / 256 <= cus) return 256;
     return 0;
@@ -354,18 +399,22 @@ size_t qr_panel_part_elems(int64_t m, int w) {
     return 2 * (size_t)((m + rr - 1) / rr) * (size_t)w;
 }
 
-hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* ctl, int* info,
+hipError_t launch_qr_flags_clear(int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(qr_flags_clear_kernel, dim3(1), dim3(QR_PANEL_MAXWG), 0, st, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* flag, int* info,
                            hipStream_t st) {
     if (m <= 0 || w <= 0) return hipSuccess;
     const int rr = qr_panel_rows(m);
     if (rr == 0 || w > qr_panel_max_width(m)) return hipErrorInvalidValue;
     const int P = (m + rr - 1) / rr;
-    hipError_t e = launch_set_int(ctl, 0, st);
-    if (e != hipSuccess) return e;
+    if (P > QR_PANEL_MAXWG) return hipErrorInvalidValue;
     if (rr == 128)
-        hipLaunchKernelGGL(qr_panel_kernel<128>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, ctl, info);
+        hipLaunchKernelGGL(qr_panel_kernel<128>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, flag, info);
     else
-        hipLaunchKernelGGL(qr_panel_kernel<256>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, ctl, info);
+        hipLaunchKernelGGL(qr_panel_kernel<256>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, flag, info);
     return hipGetLastError();
 }
 
