@@ -688,7 +688,7 @@ def run_trisolve(ff, torch, dev, n, reps=5):
     for dtype, st in (("f64", torch.float64), ("f32", torch.float32)):
         Lc = L64.t().contiguous().t().to(st)   # column-major storage of L
         ws = torch.zeros(ff.trisolve_workspace_size(n, dtype), dtype=torch.uint8, device=dev)
-        for nrhs in (1, 16):
+        for nrhs in (1, 4, 8, 16):
             B = torch.randn(nrhs, n, dtype=st, device=dev, generator=g).t()
             X = B.clone()
 

@@ -38,10 +38,19 @@ struct Carver {
     }
 };
 
+// Workspace of a float-storage factorisation: the w x w binary64 diagonal block
+// (widened, factored, rounded back), then for FF_BF16 the transposed bfloat16
+// copy of the panel the update reads (n rows of bf16t_width(w) values).
 size_t diag_ws_bytes(int64_t n, int64_t s, int dtype) {
     if (dtype == FF_F64 || n <= 0) return 0;
     const int64_t w = std::min<int64_t>(s, n);
-    return align_up((size_t)w * (size_t)w * sizeof(double));
+    size_t b = align_up((size_t)w * (size_t)w * sizeof(double));
+    if (dtype == FF_BF16) b += align_up((size_t)n * (size_t)bf16t_width((int)w) * 2);
+    return b;
+}
+__bf16* bf16_panel_ws(double* ws64, int64_t n, int64_t s) {
+    const int64_t w = std::min<int64_t>(s, n);
+    return reinterpret_cast<__bf16*>(reinterpret_cast<char*>(ws64) + align_up((size_t)w * (size_t)w * sizeof(double)));
 }
 
 #define FF_TRY(expr)                                  \
@@ -231,10 +240,13 @@ int chol_panel(int n, int c0, int w, S* A, int64_t lda, int dtype, double* ws64,
 // columns [q0, q1) of the m x m trailing matrix, lower part only.
 // [f0, f1): the part of the region's tile order to apply (see launch_update);
 // max_cus > 0 sizes the launch for a stream that owns only that many CUs.
+// pt (FF_BF16): the transposed bfloat16 panel copy; the call whose region starts
+// at row and column 0 (the first of a step) writes it, later calls of the step
+// on the same stream read it.
 template <typename S>
 int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, int q1, int dtype, unsigned flags,
                 const int* info, hipStream_t st, int reserve = 0, double f0 = 0.0, double f1 = 1.0,
-                int max_cus = 0) {
+                int max_cus = 0, __bf16* pt = nullptr) {
     const int M = m - r0, N = q1 - q0;
     if (M <= 0 || N <= 0) return 0;
     S* C = A22 + (int64_t)r0 + (int64_t)q0 * lda;
@@ -254,7 +266,12 @@ int chol_update(int m, int w, S* A22, int64_t lda, const S* P, int r0, int q0, i
     } else {
         UpdTimer tm(M, N, w, shift, reserve, st, f0, f1, dtype == FF_BF16 ? FF_UPD_SHAPE_BF16 : FF_UPD_SHAPE_F32,
                     (int)sizeof(float));
-        if (dtype == FF_BF16)
+        if (dtype == FF_BF16 && pt) {
+            const int wp = bf16t_width(w);
+            if (r0 == 0 && q0 == 0) FF_TRY(launch_panel_bf16t(m, w, P, lda, pt, st));
+            FF_TRY(launch_update_bf16t(M, N, w, C, lda, pt + (int64_t)r0 * wp, pt + (int64_t)q0 * wp, true, shift,
+                                       info, st, reserve));
+        } else if (dtype == FF_BF16)
             FF_TRY(launch_update_bf16(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, shift, info, st, reserve));
         else
             FF_TRY(launch_update<float>(M, N, w, C, lda, P + r0, lda, P + q0, lda, true, true, shift, info, st,
@@ -384,6 +401,7 @@ template <typename S>
 int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, double* ws64, int* info,
                  int col_base, hipStream_t st, bool lookahead) {
     if (n <= 0) return 0;
+    __bf16* pt = (dtype == FF_BF16 && ws64) ? bf16_panel_ws(ws64, n, s) : nullptr;
     hipStream_t side = nullptr;
     int dev = 0;
     Events evs;
@@ -402,7 +420,7 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
             if (rc || m <= 0) break;
             S* A21 = A + (int64_t)(c0 + w) + (int64_t)c0 * lda;
             S* A22 = A + (int64_t)(c0 + w) + (int64_t)(c0 + w) * lda;
-            rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, m, dtype, flags, info, st);
+            rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, m, dtype, flags, info, st, 0, 0.0, 1.0, 0, pt);
         }
         return rc;
     };
@@ -428,13 +446,14 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         if (m <= last_in_order) {
             // the last steps in order on `st`: there the whole update is shorter
             // than the two hand-overs between the streams a lookahead step makes
-            rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, m, dtype, flags, info, st);
+            rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, m, dtype, flags, info, st, 0, 0.0, 1.0, 0, pt);
             release_side(dev, side);
             return rc ? rc : in_order(c0 + w);
         }
         const int wn = chol_block_width(s, c0 + w, n, flags);    // width of the next block
         // 1) the next block's columns of the update, then hand them to the side stream
-        rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, wn, dtype, flags & ~FF_FLAG_STRASSEN1, info, st);
+        rc = chol_update<S>(m, w, A22, lda, A21, 0, 0, wn, dtype, flags & ~FF_FLAG_STRASSEN1, info, st, 0, 0.0, 1.0,
+                            0, pt);
         if (rc) return fail(rc);
         hipEvent_t en = evs.make();
         if (!en || hipEventRecord(en, st) != hipSuccess || hipStreamWaitEvent(side, en, 0) != hipSuccess)
@@ -459,7 +478,7 @@ int chol_blocked(int n, int s, S* A, int64_t lda, int dtype, unsigned flags, dou
         }
         hipEvent_t ep2 = evs.make();
         if (!ep2 || hipEventRecord(ep2, side) != hipSuccess) return fail(FF_ERR_HIP);
-        rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, st, reserve, 0.0, 1.0 - tail);
+        rc = chol_update<S>(m, w, A22, lda, A21, wn, wn, m, dtype, flags, info, st, reserve, 0.0, 1.0 - tail, 0, pt);
         if (rc) return fail(rc);
         if (hipStreamWaitEvent(st, ep2, 0) != hipSuccess) return fail(FF_ERR_HIP);
     }

@@ -60,6 +60,14 @@ hipError_t launch_update(int M, int N, int K, T* C, int64_t ldc, const T* X, int
 hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const float* X, int64_t ldx,
                               const float* Y, int64_t ldy, bool lower, int shift, const int* info, hipStream_t st,
                               int reserve_cus = 0);
+// The same from a transposed bfloat16 copy of the panel: launch_panel_bf16t
+// writes Pt[r * bf16t_width(w) + k] = bf16(P[r + k*ldp]) (zero-padded K) for
+// r < m; launch_update_bf16t then takes X rows from Xt and Y rows from Yt
+// (pointers into that copy, a row of bf16t_width(w) values each).
+int bf16t_width(int w);
+hipError_t launch_panel_bf16t(int m, int w, const float* P, int64_t ldp, __bf16* Pt, hipStream_t st);
+hipError_t launch_update_bf16t(int M, int N, int w, float* C, int64_t ldc, const __bf16* Xt, const __bf16* Yt,
+                               bool lower, int shift, const int* info, hipStream_t st, int reserve_cus = 0);
 // Persistent workgroups an update launch uses when reserve_cus CUs are kept free.
 int update_workers(int reserve_cus);
 // Kernel shape launch_update picks for an M x N region (FF_UPD_SHAPE_*).
@@ -145,11 +153,16 @@ hipError_t launch_convert_from_f64(int n, int nrhs, const double* B, int64_t ldb
 //         partial sums, pre-filled with a sentinel before every sweep).
 //   ctl   TRI_CTL ints: [0] error word (nonzero once a bounded wait of any
 //         sweep expired; never cleared here, callers clear it once per call),
-//         [1], [2] the two sweeps' workgroup tickets.
+//         [1, 1 + TRI_GROUPS) and [1 + TRI_GROUPS, 1 + 2 TRI_GROUPS) the two
+//         sweeps' workgroup tickets, one per group of right-hand sides.
+// Up to 4 right-hand sides are solved by one chain of workgroups; 5..16 by
+// ceil(nr / 4) independent chains of 4 in the same launch.
 constexpr int TRI_TB = 64;          // row block
 constexpr int TRI_RC = 16;          // right-hand sides per sweep
 constexpr int TRI_F = 2;            // newest solved blocks the solving workgroup folds itself
-constexpr int TRI_CTL = 4;
+constexpr int TRI_GC = 4;           // right-hand sides per chain when several chains run
+constexpr int TRI_GROUPS = TRI_RC / TRI_GC;
+constexpr int TRI_CTL = 1 + 2 * TRI_GROUPS;
 constexpr int RESIDUAL_CB = 16;     // 64-column blocks per residual workgroup
 inline int trisolve_nblk(int n) { return (n + TRI_TB - 1) / TRI_TB; }
 inline size_t trisolve_fac_elems(int n) { return (size_t)trisolve_nblk(n) * (2 + 2 * TRI_F) * TRI_TB * TRI_TB; }

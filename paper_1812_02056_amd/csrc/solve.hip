@@ -474,49 +474,54 @@ __device__ void tri_helper(int jj, int n, int nr, const S* __restrict__ L, int64
 // RC), all SENT on entry.
 template <typename S, bool TRANS, int NRC>
 __global__ __launch_bounds__(256)
-void trisolve_kernel(int n, int nr, const S* __restrict__ L, int64_t ldl, const S* __restrict__ fac, S* X,
-                     int64_t ldx, S* pub, int* err, int* ticket)
+void trisolve_kernel(int n, int nr_all, int groups, const S* __restrict__ L, int64_t ldl, const S* __restrict__ fac,
+                     S* X, int64_t ldx, S* pub, int* err, int* ticket)
 {
     __shared__ S smem[SWEEP_LDS_ELEMS];
     __shared__ int sh_ticket, sh_bad;
+    // workgroup b serves chain b % groups (columns [c0, c0 + NRC)); within a
+    // chain the first workgroup to start is the solver
+    const int grp = blockIdx.x % groups;
     if (threadIdx.x == 0) {
-        sh_ticket = atomicAdd(ticket, 1);
+        sh_ticket = atomicAdd(ticket + grp, 1);
         sh_bad = 0;
     }
     __syncthreads();
     const int nblk = (n + TB - 1) / TB;
-    S* xpub = pub;
-    S* part = pub + (size_t)nblk * TB * RC;
+    const int c0 = grp * NRC;
+    const int nr = min(NRC, nr_all - c0);
+    X += (int64_t)c0 * ldx;
+    S* xpub = pub + c0;
+    S* part = pub + (size_t)nblk * TB * RC + c0;
     if (sh_ticket == 0)
         tri_solver<S, TRANS, NRC>(n, nr, L, ldl, fac, X, ldx, xpub, part, err, smem, &sh_bad);
     else
         tri_helper<S, TRANS, NRC>(TRI_F + sh_ticket, n, nr, L, ldl, xpub, part, err, smem, &sh_bad);
 }
 
-// Fill the hand-off area with SENT and clear the two sweep tickets.
+// Fill the hand-off area with SENT and clear the sweeps' tickets.
 template <typename S>
 __global__ void pub_reset_kernel(S* pub, size_t count, int* tickets) {
     using U = typename PubBits<S>::U;
     U* q = reinterpret_cast<U*>(pub);
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
         q[i] = PubBits<S>::SENT;
-    if (blockIdx.x == 0 && threadIdx.x < 2) tickets[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 2 * TRI_GROUPS) tickets[threadIdx.x] = 0;
 }
 
 template <typename S, bool TRANS>
 hipError_t launch_sweep(int n, int nr, const S* L, int64_t ldl, const S* fac, S* X, int64_t ldx, S* pub, int* err,
                         int* ticket, hipStream_t st) {
     const int nblk = (n + TB - 1) / TB;
-    const dim3 grid(1 + std::max(0, nblk - TRI_F - 1));
-    if (nr == 1)
-        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, 1>), grid, dim3(256), 0, st, n, nr, L, ldl, fac, X, ldx, pub,
-                           err, ticket);
-    else if (nr <= 4)
-        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, 4>), grid, dim3(256), 0, st, n, nr, L, ldl, fac, X, ldx, pub,
-                           err, ticket);
-    else
-        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, RC>), grid, dim3(256), 0, st, n, nr, L, ldl, fac, X, ldx, pub,
-                           err, ticket);
+    const int per_chain = 1 + std::max(0, nblk - TRI_F - 1);
+    if (nr == 1) {
+        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, 1>), dim3(per_chain), dim3(256), 0, st, n, nr, 1, L, ldl, fac,
+                           X, ldx, pub, err, ticket);
+    } else {
+        const int groups = (nr + TRI_GC - 1) / TRI_GC;
+        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, TRI_GC>), dim3(per_chain * groups), dim3(256), 0, st, n, nr,
+                           groups, L, ldl, fac, X, ldx, pub, err, ticket);
+    }
     return hipGetLastError();
 }
 
@@ -830,7 +835,8 @@ hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t
         S* Xc = X + (int64_t)c0 * ldx;
         hipLaunchKernelGGL((pub_reset_kernel<S>), dim3(rgrid), dim3(256), 0, st, w.pub, all, w.ctl + 1);
         hipError_t e = launch_sweep<S, false>(n, nr, L, ldl, w.fac, Xc, ldx, w.pub, w.ctl, w.ctl + 1, st);
-        if (e == hipSuccess) e = launch_sweep<S, true>(n, nr, L, ldl, w.fac, Xc, ldx, w.pub + sweep, w.ctl, w.ctl + 2, st);
+        if (e == hipSuccess)
+            e = launch_sweep<S, true>(n, nr, L, ldl, w.fac, Xc, ldx, w.pub + sweep, w.ctl, w.ctl + 1 + TRI_GROUPS, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

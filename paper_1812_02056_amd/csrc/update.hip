@@ -449,6 +449,163 @@ void update_bf16_kernel(int M, int N, int K, float* __restrict__ C, int64_t ldc,
     }
 }
 
+// bfloat16-operand update from a transposed bfloat16 copy of the panel (the
+// form the factorisations use).  The copy is made once per step:
+//     Pt[r * wp + k] = bf16(P[r + k * ldp])  for k < w,   0 for w <= k < wp,
+// wp = w rounded up to BT_BK, so a row's K values are contiguous and zero-padded:
+// a stage is four 16-byte loads per thread and operand with no K guard and no
+// conversion in the K loop (the float-operand kernel above makes 32 scalar
+// 4-byte loads per thread and stage and converts them).  64-deep stages (two
+// 32-deep MFMA steps) and two workgroups per CU hide the load latency behind
+// MFMA work.  Every output takes the same MFMAs in the same K order as the
+// float-operand kernel on the same rounded operands, so the results agree bit
+// for bit.
+constexpr int BT_BK = 64;
+constexpr int BT_PITCH = 72;     // bfloat16 per LDS row: 144 B, 16-byte aligned rows
+
+__global__ __launch_bounds__(256)
+void panel_bf16t_kernel(int m, int w, int wp, const float* __restrict__ P, int64_t ldp, __bf16* __restrict__ Pt)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 t[64][BT_PITCH];
+    const int r0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e & 63, k = e >> 6;
+        const float v = (r0 + r < m && k0 + k < w) ? P[r0 + r + (int64_t)(k0 + k) * ldp] : 0.0f;
+        t[r][k] = to_bf16(v);
+    }
+    __syncthreads();
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    for (int c = threadIdx.x; c < 64 * 8; c += 256) {
+        const int r = c >> 3, q = c & 7;
+        if (r0 + r < m)
+            *reinterpret_cast<u4*>(Pt + (int64_t)(r0 + r) * wp + k0 + 8 * q) = *reinterpret_cast<const u4*>(&t[r][8 * q]);
+    }
+}
+
+template <bool LOWER>
+__global__ __launch_bounds__(NT, 2)
+void update_bf16t_kernel(int M, int N, int wp, float* __restrict__ C, int64_t ldc, const __bf16* __restrict__ Xt,
+                         const __bf16* __restrict__ Yt, Grid g, const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][BF_TILE][BT_PITCH];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BF_TILE][BT_PITCH];
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave & 1, wc = wave >> 1;
+    const int sr = tid >> 1, kh = 32 * (tid & 1);       // staging: row, 32-value half of the stage
+    const int nk = wp / BT_BK;
+
+    int it0, it1, itd;
+    tile_walk(g, it0, it1, itd);
+    for (int it = it0; it < it1; it += itd) {
+        int bi, bj;
+        if (g.balanced) tile_of_index(g, LOWER, it, bi, bj);
+        else if (!tile_of_slot(g, it, LOWER, bi, bj)) continue;
+        const int row0 = bi * BF_TILE, col0 = bj * BF_TILE;
+        const int mrem = M - row0, nrem = N - col0;
+        const bool active = !LOWER || (row0 + 64 * wr + 63) - (col0 + 64 * wc) >= g.shift;
+        const rsrc_t rx = make_rsrc(Xt + (int64_t)row0 * wp);
+        const rsrc_t ry = make_rsrc(Yt + (int64_t)col0 * wp);
+        const rsrc_t rc = make_rsrc(C + row0 + (int64_t)col0 * ldc);
+        const int ox = sr < mrem ? (sr * wp + kh) * 2 : BUF_OOB;
+        const int oy = sr < nrem ? (sr * wp + kh) * 2 : BUF_OOB;
+
+        u4 ra[4], rb[4];
+        auto load = [&](int kt) {
+            const int kb = kt * BT_BK * 2;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ra[q] = __builtin_amdgcn_raw_buffer_load_b128(rx, ox == BUF_OOB ? BUF_OOB : ox + kb + 16 * q, 0, 0);
+                rb[q] = __builtin_amdgcn_raw_buffer_load_b128(ry, oy == BUF_OOB ? BUF_OOB : oy + kb + 16 * q, 0, 0);
+            }
+        };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                *reinterpret_cast<u4*>(&As[buf][sr][kh + 8 * q]) = ra[q];
+                *reinterpret_cast<u4*>(&Bs[buf][sr][kh + 8 * q]) = rb[q];
+            }
+        };
+        f4_t acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = zero_vec<f4_t>();
+        load(0);
+        store(0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int buf = kt & 1;
+            if (kt + 1 < nk) load(kt + 1);
+            __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+            for (int ks = 0; ks < BT_BK / 32; ++ks) {
+                bf8_t fa[4], fb[4];
+                const int ko = 32 * ks + 8 * (lane >> 4);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    fa[cb] = *reinterpret_cast<const bf8_t*>(&Bs[buf][64 * wc + 16 * cb + (lane & 15)][ko]);
+#pragma unroll
+                for (int r4 = 0; r4 < 4; ++r4)
+                    fb[r4] = *reinterpret_cast<const bf8_t*>(&As[buf][64 * wr + 16 * r4 + (lane & 15)][ko]);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4)
+                        acc[cb][r4] = mfma_bf16(fa[cb], fb[r4], acc[cb][r4]);
+            }
+            __builtin_amdgcn_s_setprio(0);
+            if (kt + 1 < nk) store(buf ^ 1);
+            __syncthreads();
+        }
+        // write-back C - S, one 16-column block group at a time (the other
+        // workgroup on the CU covers the load latency); whole tiles use the
+        // lane's base offset, the column in the scalar offset and the row block
+        // in the immediate; edge and diagonal tiles mask each entry
+        const bool full = mrem >= BF_TILE && nrem >= BF_TILE && (!LOWER || row0 - (col0 + BF_TILE - 1) >= g.shift);
+        const int li0 = 64 * wr + (lane & 15);
+        const int lj0 = 64 * wc + 4 * (lane >> 4);
+        const int cs = (int)ldc * 4;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            float cv[4][4];
+            if (full) {
+                const int base = active ? (li0 + lj0 * (int)ldc) * 4 : BUF_OOB;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4)
+                        cv[r4][r] = buf_load<float>(rc, base == BUF_OOB ? BUF_OOB : base + 64 * r4, (16 * cb + r) * cs);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4)
+                        buf_store<float>(rc, base == BUF_OOB ? BUF_OOB : base + 64 * r4, cv[r4][r] - acc[cb][r4][r],
+                                         (16 * cb + r) * cs);
+            } else {
+                int off[4][4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4) {
+                        const int li = li0 + 16 * r4, lj = lj0 + 16 * cb + r;
+                        const bool ok =
+                            active && li < mrem && lj < nrem && (!LOWER || (row0 + li) - (col0 + lj) >= g.shift);
+                        off[r4][r] = ok ? (li + lj * (int)ldc) * 4 : BUF_OOB;
+                        cv[r4][r] = buf_load<float>(rc, off[r4][r]);
+                    }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4) buf_store<float>(rc, off[r4][r], cv[r4][r] - acc[cb][r4][r]);
+            }
+        }
+    }
+}
+
 // Largest K for which every in-range operand byte offset of one tile stays below
 // BUF_RECORDS; longer products are applied in K chunks (chunks in increasing k).
 inline int max_k_chunk(int64_t ldx, int64_t ldy, bool yrows, size_t sz) {
@@ -614,6 +771,30 @@ hipError_t launch_update_bf16(int M, int N, int K, float* C, int64_t ldc, const 
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+int bf16t_width(int w) { return (w + BT_BK - 1) / BT_BK * BT_BK; }
+
+hipError_t launch_panel_bf16t(int m, int w, const float* P, int64_t ldp, __bf16* Pt, hipStream_t st) {
+    if (m <= 0 || w <= 0) return hipSuccess;
+    const int wp = bf16t_width(w);
+    hipLaunchKernelGGL(panel_bf16t_kernel, dim3((m + 63) / 64, wp / 64), dim3(256), 0, st, m, w, wp, P, ldp, Pt);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_bf16t(int M, int N, int w, float* C, int64_t ldc, const __bf16* Xt, const __bf16* Yt,
+                               bool lower, int shift, const int* info, hipStream_t st, int reserve_cus) {
+    if (M <= 0 || N <= 0 || w <= 0) return hipSuccess;
+    if (!ld_fits(ldc, sizeof(float))) return hipErrorInvalidValue;
+    const int wp = bf16t_width(w);
+    if ((int64_t)BF_TILE * wp * 2 >= (int64_t)BUF_RECORDS / 2) return hipErrorInvalidValue;
+    Grid g = make_grid(BF_TILE, M, N, lower, shift);
+    const int nwg = persistent_grid(g, 2 * update_workers(reserve_cus));
+    if (lower)
+        hipLaunchKernelGGL(update_bf16t_kernel<true>, dim3(nwg), dim3(NT), 0, st, M, N, wp, C, ldc, Xt, Yt, g, info);
+    else
+        hipLaunchKernelGGL(update_bf16t_kernel<false>, dim3(nwg), dim3(NT), 0, st, M, N, wp, C, ldc, Xt, Yt, g, info);
+    return hipGetLastError();
 }
 
 template hipError_t launch_update<double>(int, int, int, double*, int64_t, const double*, int64_t, const double*,
