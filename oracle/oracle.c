@@ -353,19 +353,41 @@ void oracle_qr_project(int64_t m, int64_t w, int64_t k, const double *Bq, int64_
 }
 
 /*
- * Algorithm 3 of Sec. 2 with step s.  M starts as a copy of A and Q as zeros;
- * z is the first column of the current block.  For c = 0, 1, ..., n-1:
- *   - when c = z + s: project the block Q[:, z..c-1] out of M[:, c..n-1]
- *     (oracle_qr_project) and set z = c;
- *   - v = M[:, c]; for j = z..c-1 in order: v -= q_j (q_j^T v), the product
- *     taken with the vector as updated so far;
- *   - v /= ||v|| (the norm a sum of squares in row order, then sqrt; each entry
- *     divided by it) and Q[:, c] = v.
+ * Algorithm 3 of Sec. 2 with step s, organised by blocks.  M starts as a copy
+ * of A.  For each block of w = min(s, n - c0) columns starting at c0:
+ *   (i)  the block's columns are orthonormalised among themselves by modified
+ *        Gram-Schmidt: column c loses its component along each finished column
+ *        q_j of the block (j = c0, ..., c-1, in that order, every product taken
+ *        with the vector as updated so far) and is divided by its norm (a sum
+ *        of squares in row order, then sqrt);
+ *   (ii) the finished block is projected out of every later column at once
+ *        (oracle_qr_project), so later blocks start from columns already free
+ *        of it.
  * Then R = Q^T A in full.  With s = 1 every column is projected out as soon as
  * it is finished, and with s >= n no block projection happens; the two are the
  * right- and left-looking orderings of modified Gram-Schmidt and perform the
  * same operations on every column.
  */
+static int qr_orthonormalise_block(int64_t m, int64_t c0, int64_t w, double *M, double *Q, int64_t ldq)
+{
+    for (int64_t c = c0; c < c0 + w; ++c) {
+        double *v = M + (size_t)c * (size_t)m;
+        for (int64_t j = c0; j < c; ++j) {
+            const double *qj = Q + (size_t)j * (size_t)ldq;
+            double d = 0.0;
+            for (int64_t i = 0; i < m; ++i) d += qj[i] * v[i];
+            for (int64_t i = 0; i < m; ++i) v[i] -= qj[i] * d;
+        }
+        double ss = 0.0;
+        for (int64_t i = 0; i < m; ++i) ss += v[i] * v[i];
+        const double nrm = sqrt(ss);
+        if (!(nrm > 0.0)) return (int)(c + 1);
+        double *qc = Q + (size_t)c * (size_t)ldq;
+        for (int64_t i = 0; i < m; ++i) qc[i] = v[i] / nrm;
+    }
+    return 0;
+}
+
 int64_t oracle_qr_alg3(int64_t m, int64_t n, int64_t s, const double *A, int64_t lda,
                        double *Q, int64_t ldq, double *R, int64_t ldr, int *info)
 {
@@ -373,45 +395,31 @@ int64_t oracle_qr_alg3(int64_t m, int64_t n, int64_t s, const double *A, int64_t
     if (n <= 0) return 0;
     double *M = (double *)malloc((size_t)m * (size_t)n * sizeof(double));
     if (!M) return -1;
-    for (int64_t j = 0; j < n; ++j)
+    for (int64_t j = 0; j < n; ++j) {
         memcpy(M + (size_t)j * (size_t)m, A + (size_t)j * (size_t)lda, (size_t)m * sizeof(double));
-    for (int64_t j = 0; j < n; ++j)
         memset(Q + (size_t)j * (size_t)ldq, 0, (size_t)m * sizeof(double));
-    int64_t z = 0, projections = 0;
-    for (int64_t c = 0; c < n; ++c) {
-        if (c == z + s) {
-            oracle_qr_project(m, c - z, n - c, Q + (size_t)z * (size_t)ldq, ldq,
-                              M + (size_t)c * (size_t)m, m, NULL, 0);
-            ++projections;
-            z = c;
-        }
-        double *v = M + (size_t)c * (size_t)m;
-        for (int64_t j = z; j < c; ++j) {
-            const double *u = Q + (size_t)j * (size_t)ldq;
-            double d = 0.0;
-            for (int64_t i = 0; i < m; ++i) d += u[i] * v[i];
-            for (int64_t i = 0; i < m; ++i) v[i] -= u[i] * d;
-        }
-        double ss = 0.0;
-        for (int64_t i = 0; i < m; ++i) ss += v[i] * v[i];
-        const double nrm = sqrt(ss);
-        if (!(nrm > 0.0)) {
-            *info = (int)(c + 1);
-            free(M);
-            return projections;
-        }
-        double *qc = Q + (size_t)c * (size_t)ldq;
-        for (int64_t i = 0; i < m; ++i) qc[i] = v[i] / nrm;
     }
+    int64_t projections = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += s) {
+        const int64_t w = (n - c0 < s) ? n - c0 : s;
+        *info = qr_orthonormalise_block(m, c0, w, M, Q, ldq);
+        if (*info) break;
+        if (c0 + w >= n) break;
+        oracle_qr_project(m, w, n - c0 - w, Q + (size_t)c0 * (size_t)ldq, ldq,
+                          M + (size_t)(c0 + w) * (size_t)m, m, NULL, 0);
+        ++projections;
+    }
+    if (*info == 0) {
 #pragma omp parallel for schedule(dynamic, 4)
-    for (int64_t j = 0; j < n; ++j)
-        for (int64_t i = 0; i < n; ++i) {
-            const double *qi = Q + (size_t)i * (size_t)ldq;
-            const double *aj = A + (size_t)j * (size_t)lda;
-            double d = 0.0;
-            for (int64_t k = 0; k < m; ++k) d += qi[k] * aj[k];
-            R[IDX(i, j, ldr)] = d;
-        }
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i) {
+                const double *qi = Q + (size_t)i * (size_t)ldq;
+                const double *aj = A + (size_t)j * (size_t)lda;
+                double d = 0.0;
+                for (int64_t k = 0; k < m; ++k) d += qi[k] * aj[k];
+                R[IDX(i, j, ldr)] = d;
+            }
+    }
     free(M);
     return projections;
 }
