@@ -976,10 +976,9 @@ int noalloc_scratch(void** out) {
 }
 
 // ---------------------------------------------------------------- QR (Algorithm 3)
-// Workspace of qr_factor: the panel workgroups' flags, their published shares,
+// Workspace of qr_factor: the panel workgroups' hand-off slots,
 // the block product C = B_Q^T M[:, c..] and the split-K partial products.
 struct QrWs {
-    int* flag;
     double* part;
     double* C;
     double* tp;
@@ -999,8 +998,8 @@ QrWs carve_qr(void* base, int64_t m, int64_t n, int64_t s) {
         const int wb = (int)std::min<int64_t>(ws, n - z);
         const int64_t N = n - z - wb;
         if (N > 0) tp = std::max(tp, tn_gemm_part_elems(wb, (int)N, (int)m, false));
+        tp = std::max(tp, tn_gemm_part_elems(wb, (int)(n - z), (int)m, false));   // the block's rows of R
     }
-    w.flag = cv.take<int>(QR_PANEL_MAXWG);
     w.part = cv.take<double>(qr_panel_part_elems(m, ws));
     w.C = cv.take<double>((size_t)ws * (size_t)n);
     w.tp = cv.take<double>(tp);
@@ -1011,23 +1010,72 @@ QrWs carve_qr(void* base, int64_t m, int64_t n, int64_t s) {
 // Algorithm 3 with step ws: Q := A (Q holds M), then per block the in-block
 // Gram-Schmidt, the block product C = B_Q^T M[:, c..] and M[:, c..] -= B_Q C;
 // finally R = Q^T A.  Every kernel does nothing once *d_info != 0.
+//
+// R's rows of a block, R[z:z+w, z:n] = Q_b^T A[:, z:n], need only that block
+// of Q, so they are formed on a side stream while the next block's
+// Gram-Schmidt runs: that kernel holds one workgroup on each of P CUs and
+// leaves the rest idle, and the side product is capped at the other CUs'
+// worth of workgroups so the panel's workgroups still find free CUs.  R's
+// strict lower triangle is cleared once the side stream has joined.
 int qr_blocked(int m, int n, int ws, const double* A, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
                const QrWs& w, int* d_info, hipStream_t st) {
     FF_TRY(hipMemcpy2DAsync(Q, (size_t)ldq * sizeof(double), A, (size_t)lda * sizeof(double),
                             (size_t)m * sizeof(double), (size_t)n, hipMemcpyDeviceToDevice, st));
-    FF_TRY(launch_qr_flags_clear(w.flag, st));
+    FF_TRY(launch_qr_part_clear(m, w.part, st));
+    const int side_wg = cu_count() - qr_panel_workgroups(m);
+    int dev = 0;
+    hipStream_t side = nullptr;
+    // (only for blocks of whole 128-row product tiles: narrower or ragged blocks
+    // leave the side product's tiles partly empty, and it then slows the
+    // projections it shares the CUs with more than it saves)
+    if (n > ws && side_wg >= 32 && ws % 128 == 0) {
+        if (hipGetDevice(&dev) != hipSuccess) return FF_ERR_HIP;
+        side = acquire_side(dev);
+    }
+    Events evs;
+    auto fail = [&](int code) {
+        if (side) release_side(dev, side);
+        return code;
+    };
+    // R rows of the block at column z (width wb), on `on`
+    // (max_wg > 0: no K split; otherwise the split-K partials go to w.tp)
+    auto r_rows = [&](int z, int wb, hipStream_t on, int max_wg) -> hipError_t {
+        return launch_tn_gemm(wb, n - z, m, Q + (int64_t)z * ldq, ldq, A + (int64_t)z * lda, lda,
+                              R + z + (int64_t)z * ldr, ldr, false, max_wg > 0 ? nullptr : w.tp, d_info, on, max_wg);
+    };
+    int prev_z = -1, prev_w = 0;
     for (int z = 0; z < n; z += ws) {
         const int wb = std::min(ws, n - z);
         double* Bq = Q + (int64_t)z * ldq;
-        FF_TRY(launch_qr_panel(m, wb, z, Bq, ldq, w.part, w.flag, d_info, st));
+        if (side && prev_z >= 0) {
+            // the previous block's R rows start with this block's panel
+            hipEvent_t e = evs.make();
+            if (!e || hipEventRecord(e, st) != hipSuccess || hipStreamWaitEvent(side, e, 0) != hipSuccess)
+                return fail(FF_ERR_HIP);
+            if (r_rows(prev_z, prev_w, side, side_wg) != hipSuccess) return fail(FF_ERR_HIP);
+        }
+        if (launch_qr_panel(m, wb, z, Bq, ldq, w.part, d_info, st) != hipSuccess) return fail(FF_ERR_HIP);
+        prev_z = z;
+        prev_w = wb;
         const int N = n - z - wb;
         if (N <= 0) break;
         double* Bm = Q + (int64_t)(z + wb) * ldq;
-        FF_TRY(launch_tn_gemm(wb, N, m, Bq, ldq, Bm, ldq, w.C, wb, false, w.tp, d_info, st));
-        FF_TRY(launch_update<double>(m, N, wb, Bm, ldq, Bq, ldq, w.C, wb, false, false, 0, d_info, st, 0, 0, 0.0,
-                                     1.0));
+        if (launch_tn_gemm(wb, N, m, Bq, ldq, Bm, ldq, w.C, wb, false, w.tp, d_info, st) != hipSuccess ||
+            launch_update<double>(m, N, wb, Bm, ldq, Bq, ldq, w.C, wb, false, false, 0, d_info, st, 0, 0, 0.0,
+                                  1.0) != hipSuccess)
+            return fail(FF_ERR_HIP);
     }
-    FF_TRY(launch_tn_gemm(n, n, m, Q, ldq, A, lda, R, ldr, true, w.tp, d_info, st));
+    if (!side) {
+        FF_TRY(launch_tn_gemm(n, n, m, Q, ldq, A, lda, R, ldr, true, w.tp, d_info, st));
+        return 0;
+    }
+    // the last block's rows on the caller's stream, then join and clear below the diagonal
+    if (r_rows(prev_z, prev_w, st, 0) != hipSuccess) return fail(FF_ERR_HIP);
+    hipEvent_t ej = evs.make();
+    if (!ej || hipEventRecord(ej, side) != hipSuccess || hipStreamWaitEvent(st, ej, 0) != hipSuccess)
+        return fail(FF_ERR_HIP);
+    release_side(dev, side);
+    FF_TRY(launch_zero_strict_lower(n, R, ldr, d_info, st));
     return 0;
 }
 }  // namespace

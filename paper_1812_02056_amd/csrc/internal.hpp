@@ -18,28 +18,31 @@ hipError_t launch_set_int(int* p, int v, hipStream_t st);
 
 // QR (qr.hip).  In-block modified Gram-Schmidt of w columns of Mp (m rows) on
 // co-resident workgroups of qr_panel_rows(m) rows each (0: m too large);
-// w <= qr_panel_max_width(m).  part: qr_panel_part_elems(m, w) doubles; flag:
-// QR_PANEL_MAXWG ints, cleared by launch_qr_flags_clear once before the first
-// panel of a factorisation (panels take increasing col0); info: 0 on entry or the
-// kernel does nothing; set to col0 + j + 1 when column j's norm is not > 0, to
-// -1 when a grid-wide wait expired.
+// w <= qr_panel_max_width(m).  part: qr_panel_part_elems(m, w) doubles of
+// hand-off slots, filled with the sentinel by launch_qr_part_clear once before
+// the first panel of a factorisation (panels take increasing col0); info: 0 on
+// entry or the kernel does nothing; set to col0 + j + 1 when column j's norm is
+// not > 0, to -1 when a wait between the workgroups expired.
 constexpr int QR_PANEL_LDS_DOUBLES = 18432;   // 144 KB of LDS per workgroup
 constexpr int QR_PANEL_WMAX = 256;
 constexpr int QR_PANEL_MAXWG = 256;
-hipError_t launch_qr_flags_clear(int* flag, hipStream_t st);
+hipError_t launch_qr_part_clear(int64_t m, double* part, hipStream_t st);
 int qr_panel_rows(int64_t m);
 int qr_panel_max_width(int64_t m);
 size_t qr_panel_part_elems(int64_t m, int w);
-hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* flag, int* info,
-                           hipStream_t st);
+hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* info, hipStream_t st);
 // D = X^T Y (M x N) with X(k, i) = X[k + i*ldx], Y(k, j) = Y[k + j*ldy], k < K.
 // upper: M == N and only the upper triangle is formed, the strict lower
 // triangle of D is set to zero.  part: tn_gemm_part_elems(M, N, K, upper)
 // doubles (may be null when that is 0).  Nothing happens when *info != 0.
+// max_wg > 0: at most that many workgroups walk the tiles (no K split, part
+// unused), so that the launch leaves the other CUs to concurrent work.
 size_t tn_gemm_part_elems(int M, int N, int K, bool upper);
 bool tn_gemm_fits(int64_t K, int64_t ldx, int64_t ldy);
 hipError_t launch_tn_gemm(int M, int N, int K, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* D,
-                          int64_t ldd, bool upper, double* part, const int* info, hipStream_t st);
+                          int64_t ldd, bool upper, double* part, const int* info, hipStream_t st, int max_wg = 0);
+int qr_panel_workgroups(int64_t m);
+hipError_t launch_zero_strict_lower(int n, double* D, int64_t ldd, const int* info, hipStream_t st);
 hipError_t launch_copy_int(const int* src, int* dst, hipStream_t st);
 
 // Trailing updates (update.hip).

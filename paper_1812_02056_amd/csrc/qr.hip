@@ -60,15 +60,32 @@ __device__ __forceinline__ void load2(rsrc_t r, int off, double& a, double& b) {
 // tile grid (column-major triangle order) and only entries with i <= j are
 // written.
 template <bool UPPER>
+__device__ __forceinline__ void tn_item(int b, int M, int N, int K, int kchunk, int ks, int tiles_m,
+                                        const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y,
+                                        int64_t ldy, double* __restrict__ D, int64_t ldd, int64_t dstride,
+                                        double (&As)[2][TG_BK][TG_P], double (&Bs)[2][TG_BK][TG_P]);
+
+template <bool UPPER>
 __global__ __launch_bounds__(TG_NT, 2)
-void tn_gemm_kernel(int M, int N, int K, int kchunk, int ks, int tiles_m, const double* __restrict__ X,
+void tn_gemm_kernel(int M, int N, int K, int kchunk, int ks, int tiles_m, int nitems, const double* __restrict__ X,
                     int64_t ldx, const double* __restrict__ Y, int64_t ldy, double* __restrict__ D, int64_t ldd,
                     int64_t dstride, const int* __restrict__ info)
 {
     if (info && *info != 0) return;
     __shared__ double As[2][TG_BK][TG_P];   // As[k][i] = X(k0 + k, row0 + i)
     __shared__ double Bs[2][TG_BK][TG_P];   // Bs[k][j] = Y(k0 + k, col0 + j)
-    const int b = blockIdx.x;
+    for (int b = blockIdx.x; b < nitems; b += gridDim.x)
+        tn_item<UPPER>(b, M, N, K, kchunk, ks, tiles_m, X, ldx, Y, ldy, D, ldd, dstride, As, Bs);
+}
+
+// One work item of tn_gemm_kernel (K part b % ks of tile b / ks); ends with a
+// barrier so the next item may reuse the LDS buffers.
+template <bool UPPER>
+__device__ __forceinline__ void tn_item(int b, int M, int N, int K, int kchunk, int ks, int tiles_m,
+                                        const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y,
+                                        int64_t ldy, double* __restrict__ D, int64_t ldd, int64_t dstride,
+                                        double (&As)[2][TG_BK][TG_P], double (&Bs)[2][TG_BK][TG_P])
+{
     const int q = b % ks, tile = b / ks;
     int bi, bj;
     if (UPPER) {
@@ -187,6 +204,7 @@ void tn_gemm_kernel(int M, int N, int K, int kchunk, int ks, int tiles_m, const 
                 if (i < M && j < N && (!UPPER || i <= j)) Dq[i + (int64_t)j * ldd] = acc[cb][r4][r];
             }
         }
+    __syncthreads();
 }
 
 // D(i, j) = sum_q P[q * pstride + i + j * M] for q = 0, 1, ... in order
@@ -222,42 +240,62 @@ constexpr int QR_NT = 256;
 constexpr int QR_SPIN_LIMIT = 1 << 20;
 constexpr int QR_GB = 16;           // shares per column a lane loads at once
 
+// Hand-off words of the panel: SENT marks a share not written yet; a share whose
+// bits equal SENT (a NaN) is stored as the canonical quiet NaN instead.
+constexpr unsigned long long QR_SENT = 0xFFFFFFFFFFFFFFFFull;
+constexpr unsigned long long QR_QNAN = 0x7FF8000000000000ull;
+
+__device__ __forceinline__ void share_put(double* p, double v) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b == QR_SENT) b = QR_QNAN;
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void share_clear(double* p) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), QR_SENT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long share_peek(const double* p) {
+    return __hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Block columns [0, w) of Mp (m rows, leading dimension ldm) are replaced by the
 // orthonormal columns of modified Gram-Schmidt.  Workgroup g holds rows
 // [g RR, (g+1) RR) in LDS (column pitch RR + 1); gridDim.x = P = ceil(m / RR)
 // workgroups, all resident at once (one per CU, by their LDS).
 //
-// Round j: (a) each workgroup forms its rows' share of v_j . v_c, c = j..w-1
-// (wave h sums rows [h RR/4, (h+1) RR/4) in row order, the four waves' sums
-// are added in wave order) and publishes it in part[j % 2][g][c - j]; (b) the
-// workgroup sets flag[g] = col0 + j + 1 and waits until every flag has reached
-// that value (flags grow over the whole factorisation, so they are cleared once
-// per call, and no workgroup contends for another's word); (c) each
-// workgroup adds the P shares, wave h over workgroups [h P/4, (h+1) P/4) in
-// order, then the four in wave order: all workgroups obtain the same sums S_c;
-// (d) ||v_j|| = sqrt(S_j), q_j = v_j / ||v_j||, and v_c -= q_j (S_c / ||v_j||)
-// for c > j (S_c / ||v_j|| is q_j . v_c up to rounding).
-// The panel is at most 256 columns wide, so a lane holds at most 4 of them.
-// Shares of round j are overwritten in round j + 2 only after every workgroup
-// has passed round j + 1's count, i.e. after it read round j's shares.
-// Shares and flags are agent-scope atomics, which gfx950 serves at the
-// device's coherence point (no stale per-XCD L2 copy); a share's store has
-// completed (waitcnt) before its workgroup sets its flag, and the shares are
-// loaded only after every flag was seen set.  No cache-wide write-back or
-// invalidate is needed, so the 2w waits of a panel stay at the latency of a
-// few device-memory round trips.
+// Round j (global round G = col0 + j): (a) each workgroup forms its rows' share
+// of v_j . v_c, c = j..w-1 (wave h sums rows [h RR/4, (h+1) RR/4) in row order,
+// the four waves' sums are added in wave order); it clears its own slots of
+// buffer (G + 1) % 3 and then publishes the shares in its slots of buffer G % 3,
+// part[G % 3][g][c - j]; (b) each workgroup reads the P shares of every column,
+// polling each slot until it no longer holds SENT, and adds them in workgroup
+// order (wave h over workgroups [h P/4, (h+1) P/4) in order, then the four in
+// wave order): all workgroups obtain the same sums S_c; (c) ||v_j|| = sqrt(S_j),
+// q_j = v_j / ||v_j||, and v_c -= q_j (S_c / ||v_j||) for c > j (S_c / ||v_j|| is
+// q_j . v_c up to rounding).
+// The shares are their own ready flags, so no separate count is needed.  A
+// workgroup clears buffer (G + 1) % 3, last used in round G - 2, only after it has
+// read every share of round G - 1, which every workgroup published after it had
+// read round G - 2; and it clears before it publishes round G (the same thread
+// writes both, with a completion wait between), so whoever reads round G + 1
+// finds SENT or the new share.  Global round numbers keep the rotation going
+// across the panels of one factorisation; the slots are cleared once per call.
+// Shares are agent-scope atomics, which gfx950 serves at the device's coherence
+// point (no stale per-XCD L2 copy), so no cache-wide write-back or invalidate is
+// needed.
 // A norm that is not > 0 (zero or NaN) sets *info = col0 + j + 1 and ends the
-// kernel in every workgroup (all hold the same sums); a count wait that exceeds
-// its bound sets *info = -1.
+// kernel in every workgroup (all hold the same sums); a wait that exceeds its
+// bound sets *info = -1.  The panel is at most QR_PANEL_WMAX = 256 columns wide,
+// so a lane holds at most 4 of them.
 template <int RR>
 __global__ __launch_bounds__(QR_NT, 1)
-void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ldm, double* part, int* flag,
-                     int* info)
+void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ldm, double* part, int* info)
 {
     static_assert(RR % 4 == 0 && RR <= QR_NT && QR_NT % RR == 0, "row split");
     constexpr int RP = RR + 1;
     constexpr int RQ = RR / 4;
     constexpr int CSTEP = QR_NT / RR;
+    constexpr int WS = QR_PANEL_WMAX;      // slot row length (fixed across panels)
     __shared__ double slab[QR_LDS];
     __shared__ double red[4][QR_PANEL_WMAX];
     __shared__ double dv[QR_PANEL_WMAX];
@@ -267,6 +305,7 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
     const int P = gridDim.x, g = blockIdx.x;
     const int t = threadIdx.x, lane = t & 63, h = t >> 6;
     const int r0 = g * RR;
+    const size_t bstride = (size_t)P * WS;
     for (int idx = t; idx < w * RR; idx += QR_NT) {
         const int c = idx / RR, r = idx % RR;
         slab[c * RP + r] = r0 + r < m ? Mp[r0 + r + (int64_t)c * ldm] : 0.0;
@@ -278,7 +317,9 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
 
     for (int j = 0; j < w; ++j) {
         const int nc = w - j;
-        double* pj = part + (size_t)(j & 1) * (size_t)P * (size_t)w;
+        const int G = col0 + j;
+        double* pj = part + (size_t)(G % 3) * bstride;
+        double* pn = part + (size_t)((G + 1) % 3) * bstride;
         // (a)
         for (int ci = lane; ci < nc; ci += 64) {
             const double* vj = slab + j * RP + h * RQ;
@@ -289,70 +330,60 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
             red[h][ci] = acc;
         }
         __syncthreads();
-        if (t < nc) {
-            const double p = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
-            __hip_atomic_store(pj + (size_t)g * w + t, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_s_waitcnt(0);   // the share is written through before the count below
+        if (t < WS) {
+            share_clear(pn + (size_t)g * WS + t);
+            __builtin_amdgcn_s_waitcnt(0);   // the clear lands before this round's share
+            if (t < nc) share_put(pj + (size_t)g * WS + t, ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t]);
         }
-        __syncthreads();
-        // (b) count in: flag[g] = col0 + j + 1; wave 0 polls every workgroup's flag
-        if (t == 0) __hip_atomic_store(flag + g, col0 + j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (h == 0) {
-            const int target = col0 + j + 1;
-            int spins = 0;
-            bool done = false;
-            while (!done) {
-                bool mine = true;
+        __syncthreads();   // every share is read from red before (b) overwrites it
+        // (b) every lane keeps up to 4 columns x QR_GB shares in flight and polls
+        // them until none is SENT; out-of-range slots load a clamped (valid)
+        // address and are ignored
+        {
+            double accv[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int gg0 = g_lo; gg0 < g_hi; gg0 += QR_GB) {
+                unsigned long long v[4][QR_GB];
+                int spins = 0;
+                while (true) {
+                    bool pending = false;
 #pragma unroll
-                for (int u = 0; u < QR_PANEL_MAXWG / 64; ++u) {
-                    const int gg = lane + 64 * u;
-                    if (gg < P)
-                        mine &= __hip_atomic_load(flag + gg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
-                }
-                done = __all(mine);
-                if (!done) {
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int e = 0; e < QR_GB; ++e) {
+                            const int gg = min(gg0 + e, g_hi - 1);
+                            const int ci = min(lane + 64 * u, nc - 1);
+                            v[u][e] = share_peek(pj + (size_t)gg * WS + ci);
+                        }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int e = 0; e < QR_GB; ++e)
+                            pending |= (gg0 + e < g_hi && lane + 64 * u < nc && v[u][e] == QR_SENT);
+                    if (!__any(pending)) break;
                     if (++spins > QR_SPIN_LIMIT) {
-                        if (lane == 0) bad = 1;
+                        bad = 1;
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
-            }
-        }
-        __syncthreads();
-        if (bad) {
-            if (t == 0) __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
-        }
-        // (c) every lane keeps up to 4 columns x QR_GB shares in flight; out-of-range
-        // slots load a clamped (valid) address and are masked at use
-        {
-            double accv[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int gg0 = g_lo; gg0 < g_hi; gg0 += QR_GB) {
-                double v[4][QR_GB];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int e = 0; e < QR_GB; ++e) {
-                        const int gg = min(gg0 + e, g_hi - 1);
-                        const int ci = min(lane + 64 * u, nc - 1);
-                        v[u][e] = __hip_atomic_load(pj + (size_t)gg * w + ci, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-                    }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                     for (int e = 0; e < QR_GB; ++e)
-                        if (gg0 + e < g_hi) accv[u] += v[u][e];
+                        if (gg0 + e < g_hi) accv[u] += __longlong_as_double((long long)v[u][e]);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (lane + 64 * u < nc) red[h][lane + 64 * u] = accv[u];
         }
         __syncthreads();
+        if (bad) {
+            if (t == 0) __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
         if (t < nc) dv[t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
         __syncthreads();
-        // (d)
+        // (c)
         const double nrm = sqrt(dv[0]);
         if (!(nrm > 0.0)) {
             if (g == 0 && t == 0) __hip_atomic_store(info, col0 + j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -371,9 +402,11 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
     }
 }
 
-__global__ void qr_flags_clear_kernel(int* flag) {
-    flag[threadIdx.x] = 0;
+__global__ void qr_part_clear_kernel(double* part, size_t count) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        reinterpret_cast<unsigned long long*>(part)[i] = QR_SENT;
 }
+
 
 }  // namespace
 
@@ -387,34 +420,43 @@ int qr_panel_rows(int64_t m) {
     return 0;
 }
 
+int qr_panel_workgroups(int64_t m) {
+    const int rr = qr_panel_rows(m);
+    return rr == 0 ? 0 : (int)((m + rr - 1) / rr);
+}
+
 int qr_panel_max_width(int64_t m) {
     const int rr = qr_panel_rows(m);
     if (rr == 0) return 0;
     return std::min(QR_PANEL_WMAX, QR_PANEL_LDS_DOUBLES / (rr + 1));
 }
 
+// Three rotating buffers of P x QR_PANEL_WMAX slots (independent of the panel width).
 size_t qr_panel_part_elems(int64_t m, int w) {
+    (void)w;
     const int rr = qr_panel_rows(m);
     if (rr == 0) return 0;
-    return 2 * (size_t)((m + rr - 1) / rr) * (size_t)w;
+    return 3 * (size_t)((m + rr - 1) / rr) * (size_t)QR_PANEL_WMAX;
 }
 
-hipError_t launch_qr_flags_clear(int* flag, hipStream_t st) {
-    hipLaunchKernelGGL(qr_flags_clear_kernel, dim3(1), dim3(QR_PANEL_MAXWG), 0, st, flag);
+hipError_t launch_qr_part_clear(int64_t m, double* part, hipStream_t st) {
+    const size_t count = qr_panel_part_elems(m, 0);
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(qr_part_clear_kernel, dim3((unsigned)std::min<size_t>(1024, (count + 255) / 256)), dim3(256),
+                       0, st, part, count);
     return hipGetLastError();
 }
 
-hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* flag, int* info,
-                           hipStream_t st) {
+hipError_t launch_qr_panel(int m, int w, int col0, double* Mp, int64_t ldm, double* part, int* info, hipStream_t st) {
     if (m <= 0 || w <= 0) return hipSuccess;
     const int rr = qr_panel_rows(m);
     if (rr == 0 || w > qr_panel_max_width(m)) return hipErrorInvalidValue;
     const int P = (m + rr - 1) / rr;
     if (P > QR_PANEL_MAXWG) return hipErrorInvalidValue;
     if (rr == 128)
-        hipLaunchKernelGGL(qr_panel_kernel<128>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, flag, info);
+        hipLaunchKernelGGL(qr_panel_kernel<128>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, info);
     else
-        hipLaunchKernelGGL(qr_panel_kernel<256>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, flag, info);
+        hipLaunchKernelGGL(qr_panel_kernel<256>, dim3(P), dim3(QR_NT), 0, st, m, w, col0, Mp, ldm, part, info);
     return hipGetLastError();
 }
 
@@ -438,7 +480,20 @@ TnPlan tn_plan(int M, int N, int K, bool upper) {
     if (p.ks < 1) p.ks = 1;
     return p;
 }
+TnPlan tn_plan_unsplit(int M, int N, int K, bool upper) {
+    TnPlan p = tn_plan(M, N, K, upper);
+    p.ks = 1;
+    p.kchunk = (K + TG_BK - 1) / TG_BK * TG_BK;
+    return p;
+}
 }  // namespace
+
+hipError_t launch_zero_strict_lower(int n, double* D, int64_t ldd, const int* info, hipStream_t st) {
+    if (n <= 1) return hipSuccess;
+    hipLaunchKernelGGL(zero_strict_lower_kernel, dim3(std::min<int64_t>(4096, ((int64_t)n * n + 255) / 256)),
+                       dim3(256), 0, st, n, D, ldd, info);
+    return hipGetLastError();
+}
 
 size_t tn_gemm_part_elems(int M, int N, int K, bool upper) {
     if (M <= 0 || N <= 0 || K <= 0) return 0;
@@ -452,7 +507,7 @@ bool tn_gemm_fits(int64_t K, int64_t ldx, int64_t ldy) {
 }
 
 hipError_t launch_tn_gemm(int M, int N, int K, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* D,
-                          int64_t ldd, bool upper, double* part, const int* info, hipStream_t st) {
+                          int64_t ldd, bool upper, double* part, const int* info, hipStream_t st, int max_wg) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (upper && M != N) return hipErrorInvalidValue;
     if (K <= 0) {
@@ -462,15 +517,16 @@ hipError_t launch_tn_gemm(int M, int N, int K, const double* X, int64_t ldx, con
         return hipGetLastError();
     }
     if (!tn_gemm_fits(K, ldx, ldy)) return hipErrorInvalidValue;
-    const TnPlan p = tn_plan(M, N, K, upper);
-    const int nwg = p.tiles * p.ks;
+    const TnPlan p = max_wg > 0 ? tn_plan_unsplit(M, N, K, upper) : tn_plan(M, N, K, upper);
+    const int nitems = p.tiles * p.ks;
+    const int nwg = max_wg > 0 ? std::min(nitems, max_wg) : nitems;
     if (p.ks == 1) {
         if (upper)
             hipLaunchKernelGGL(tn_gemm_kernel<true>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, 1, p.tiles_m,
-                               X, ldx, Y, ldy, D, ldd, (int64_t)0, info);
+                               nitems, X, ldx, Y, ldy, D, ldd, (int64_t)0, info);
         else
             hipLaunchKernelGGL(tn_gemm_kernel<false>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, 1, p.tiles_m,
-                               X, ldx, Y, ldy, D, ldd, (int64_t)0, info);
+                               nitems, X, ldx, Y, ldy, D, ldd, (int64_t)0, info);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !upper) return e;
         hipLaunchKernelGGL(zero_strict_lower_kernel, dim3(std::min<int64_t>(4096, ((int64_t)M * N + 255) / 256)),
@@ -480,11 +536,11 @@ hipError_t launch_tn_gemm(int M, int N, int K, const double* X, int64_t ldx, con
     if (part == nullptr) return hipErrorInvalidValue;
     const int64_t ps = (int64_t)M * N;
     if (upper)
-        hipLaunchKernelGGL(tn_gemm_kernel<true>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, p.ks, p.tiles_m, X,
-                           ldx, Y, ldy, part, (int64_t)M, ps, info);
+        hipLaunchKernelGGL(tn_gemm_kernel<true>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, p.ks, p.tiles_m,
+                           nitems, X, ldx, Y, ldy, part, (int64_t)M, ps, info);
     else
         hipLaunchKernelGGL(tn_gemm_kernel<false>, dim3(nwg), dim3(TG_NT), 0, st, M, N, K, p.kchunk, p.ks, p.tiles_m,
-                           X, ldx, Y, ldy, part, (int64_t)M, ps, info);
+                           nitems, X, ldx, Y, ldy, part, (int64_t)M, ps, info);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(tn_reduce_kernel, dim3(std::min<int64_t>(4096, (ps + 255) / 256)), dim3(256), 0, st, M, N,
