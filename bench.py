@@ -341,7 +341,35 @@ def run_extras(ff, torch, wl, dev, n, A0):
                                       "info": int(info.item()), "bwd_A": bwd,
                                       "s_sweep_ms": {str(k): round(v * 1e3, 3) for k, v in sweep_lu.items()}}
         log(f"[bench] LU: {out['lu_nopiv_f64_n16384']}")
-        del D, Dc, LU, Lm, Um
+        del LU, Lm, Um
+        # Strassen on the LU product: one level per super-tile, and two levels
+        # (a matrix-level level over it), against the classical update
+        lu_str = {}
+        for levels in (1, 2):
+            for s_lu in (512, 768):
+                wsp = torch.empty(max(1, ff.load().ff_lu_workspace_size(n, s_lu, 0, 1 if levels == 1 else 32)),
+                                  dtype=torch.uint8, device=dev)
+                Dc.copy_(D)
+                ff.lu_nopiv_factor(Dc.t(), s_lu, info=info, strassen=levels, ws=wsp)      # warm-up
+                best_s = 1e30
+                for _ in range(3):
+                    Dc.copy_(D)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ff.lu_nopiv_factor(Dc.t(), s_lu, info=info, strassen=levels, ws=wsp)
+                    torch.cuda.synchronize()
+                    best_s = min(best_s, time.perf_counter() - t0)
+                LU = Dc.t()
+                bwd_s = float(torch.linalg.norm(D.t() - (torch.tril(LU, -1) + torch.eye(n, dtype=torch.float64,
+                                                                                             device=dev))
+                                                @ torch.triu(LU)) / torch.linalg.norm(D))
+                lu_str[f"s{s_lu}_strassen{levels}"] = {"ms": round(best_s * 1e3, 3), "bwd_A": bwd_s,
+                                                        "classical_ms": round(sweep_lu[s_lu] * 1e3, 3),
+                                                        "info": int(info.item())}
+                del wsp, LU
+        out["lu_strassen_vs_classical"] = lu_str
+        log(f"[bench] LU strassen: {lu_str}")
+        del D, Dc
     except Exception as e:
         out["lu_nopiv_f64_n16384"] = {"error": str(e)}
     torch.cuda.empty_cache()

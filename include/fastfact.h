@@ -90,6 +90,21 @@ enum {
                                       the left by the factor (M = W W^T in W's
                                       precision), instead of by one pair of
                                       triangular solves; see chol_solve. */
+    FF_FLAG_STRASSEN2 = 1u << 5,    /* lu_nopiv_factor only: two Strassen levels
+                                      (the paper times its Strassen variant with
+                                      two and three recursions, Sec. 2 timing
+                                      paragraph): on trailing products of
+                                      m >= 2048 rows a matrix-level level splits
+                                      m and the step in halves into Strassen's
+                                      7 products, each computed by the one-level
+                                      kernel of FF_FLAG_STRASSEN1 (odd last rows,
+                                      columns or steps are applied classically);
+                                      smaller products take one level.  Needs
+                                      the workspace of ff_lu_workspace_size
+                                      (n/2 x n/2 + n x s/2 doubles).  Binary64
+                                      only; not combinable with
+                                      FF_FLAG_STRASSEN1; FF_ERR_UNSUPPORTED for
+                                      chol_factor. */
     FF_FLAG_FIXED_STEP = 1u << 2    /* every block exactly s columns wide (the
                                       step of Sec. 2 Algorithms 1 and 2
                                       verbatim).  Without it, the first block

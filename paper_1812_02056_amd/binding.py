@@ -26,6 +26,7 @@ FLAG_NO_LOOKAHEAD = 2
 FLAG_FIXED_STEP = 4
 FLAG_ESCALATE = 8
 FLAG_GMRES_IR = 16
+FLAG_STRASSEN2 = 32
 ERR_HIP, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_SCRATCH = -100, -101, -102, -103
 
 _DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
@@ -237,18 +238,21 @@ def chol_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_lookahe
 
 
 def lu_nopiv_factor(A: torch.Tensor, s: int, dtype="f64", strassen=False, no_lookahead=False, stream=None,
-                    info: torch.Tensor | None = None, sync=False, fixed_step=False):
+                    info: torch.Tensor | None = None, sync=False, fixed_step=False, ws: torch.Tensor | None = None):
     """In-place LU without pivoting, Doolittle packed (unit-lower L below the diagonal, U on and above).
+    strassen: False, True / 1 (one level, FF_FLAG_STRASSEN1) or 2 (two levels, FF_FLAG_STRASSEN2).
     fixed_step: every block exactly s wide (FF_FLAG_FIXED_STEP)."""
     lib = load()
     dt = _dt(dtype)
     n = int(A.shape[0])
     if A.shape[1] != n:
         raise ValueError("A must be square")
-    flags = ((FLAG_STRASSEN1 if strassen else 0) | (FLAG_NO_LOOKAHEAD if no_lookahead else 0)
-             | (FLAG_FIXED_STEP if fixed_step else 0))
+    levels = int(strassen)
+    flags = ((FLAG_STRASSEN1 if levels == 1 else FLAG_STRASSEN2 if levels == 2 else 0)
+             | (FLAG_NO_LOOKAHEAD if no_lookahead else 0) | (FLAG_FIXED_STEP if fixed_step else 0))
     need = int(lib.ff_lu_workspace_size(n, s, dt, flags))
-    ws = _workspace(need, A.device)
+    if ws is None:
+        ws = _workspace(need, A.device)
     if info is None:
         info = torch.empty(1, dtype=torch.int32, device=A.device)
     rc = lib.lu_nopiv_factor(n, s, _ptr(A), _ld(A, "A"), dt, flags, _ptr(ws), 0 if ws is None else ws.numel(),

@@ -524,7 +524,18 @@ inline int lu_block_width(int s, int c0, int n, unsigned flags) {
     const int w = (s > LU_LDS_MAX && edge && !(flags & FF_FLAG_FIXED_STEP)) ? LU_LDS_MAX : s;
     return std::min(w, n - c0);
 }
-int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st);
+int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st,
+               double* s2ws = nullptr);
+// A22 -= X Y for the LU: classical, one Strassen level, or two (FF_FLAG_STRASSEN2,
+// scratch s2ws); reserve CUs are left to the side stream.
+hipError_t lu_product(int m, int w, double* C, int64_t lda, const double* X, const double* Y, unsigned flags,
+                      double* s2ws, const int* info, hipStream_t st, int reserve = 0) {
+    if (flags & FF_FLAG_STRASSEN2)
+        return launch_update_gemm_strassen2_f64(m, w, C, lda, X, lda, Y, lda, s2ws, info, st, reserve);
+    if (flags & FF_FLAG_STRASSEN1)
+        return launch_update_gemm_strassen_f64(m, w, C, lda, X, lda, Y, lda, info, st, reserve);
+    return launch_update<double>(m, m, w, C, lda, X, lda, Y, lda, false, false, 0, info, st, reserve);
+}
 // GETRF-nopiv of the w x w diagonal block: one LDS kernel up to LU_LDS_MAX,
 // blocks of LU_LDS_MAX (in order) when wider.
 int lu_diag(int w, double* A11, int64_t lda, int* info, int col_base, hipStream_t st) {
@@ -554,7 +565,7 @@ int lu_panel(int n, int c0, int w, double* A, int64_t lda, int* info, int col_ba
 
 // Blocks from column c_start on, in order on `st`.
 int lu_in_order(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st,
-                int c_start) {
+                int c_start, double* s2ws = nullptr) {
     for (int c0 = c_start, w = 0; c0 < n; c0 += w) {
         w = lu_block_width(s, c0, n, flags);
         const int m = n - c0 - w;
@@ -574,10 +585,7 @@ int lu_in_order(int n, int s, double* A, int64_t lda, unsigned flags, int* info,
         // T(k, j) = L11(j, k) with unit diagonal
         rc = trsm_blocked<double>(m, w, A12, lda, false, A11, lda, true, 1, info, st);
         if (rc) return rc;
-        if (flags & FF_FLAG_STRASSEN1)
-            FF_TRY(launch_update_gemm_strassen_f64(m, w, A22, lda, A21, lda, A12, lda, info, st));
-        else
-            FF_TRY(launch_update<double>(m, m, w, A22, lda, A21, lda, A12, lda, false, false, 0, info, st));
+        FF_TRY(lu_product(m, w, A22, lda, A21, A12, flags, s2ws, info, st));
     }
     return 0;
 }
@@ -586,7 +594,8 @@ int lu_in_order(int n, int s, double* A, int64_t lda, unsigned flags, int* info,
 // runs on `st` on all but `reserve` CUs, the side stream factors block k + 1
 // (whose column and row strips were updated first) and then takes the tail of
 // update k's tile order.
-int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st) {
+int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st,
+                 double* s2ws) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return FF_ERR_HIP;
     hipStream_t side = acquire_side(dev);
@@ -612,11 +621,9 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
         if (m <= last_in_order) {
             // the last steps in order on `st`: there the whole update is shorter
             // than the two hand-overs between the streams a lookahead step makes
-            hipError_t e = (flags & FF_FLAG_STRASSEN1)
-                               ? launch_update_gemm_strassen_f64(m, w, A22, lda, A21, lda, A12, lda, info, st)
-                               : launch_update<double>(m, m, w, A22, lda, A21, lda, A12, lda, false, false, 0, info, st);
+            hipError_t e = lu_product(m, w, A22, lda, A21, A12, flags, s2ws, info, st);
             release_side(dev, side);
-            return e != hipSuccess ? FF_ERR_HIP : lu_in_order(n, s, A, lda, flags, info, col_base, st, c0 + w);
+            return e != hipSuccess ? FF_ERR_HIP : lu_in_order(n, s, A, lda, flags, info, col_base, st, c0 + w, s2ws);
         }
         const int wn = lu_block_width(s, c0 + w, n, flags);
         const int mr = m - wn;
@@ -634,7 +641,7 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
         //    the panel
         double tail = 0.0, u_est = 0.0, p_est = 0.0;
         const int reserve = lookahead_reserve(mr, w, wn, sizeof(double), lu_diag_us(wn), &tail, 2.0, 2, &u_est, &p_est);
-        const bool strassen = (flags & FF_FLAG_STRASSEN1) != 0;
+        const bool strassen = (flags & (FF_FLAG_STRASSEN1 | FF_FLAG_STRASSEN2)) != 0;
         if (strassen || tail < 0.01 || mr <= 0 || !update_splittable(mr, mr, false, 0, reserve))
             tail = 0.0;
         else
@@ -653,7 +660,7 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
         if (!ep2 || hipEventRecord(ep2, side) != hipSuccess) return fail(FF_ERR_HIP);
         if (mr > 0) {
             if (strassen)
-                e = launch_update_gemm_strassen_f64(mr, w, C2, lda, X2, lda, Y2, lda, info, st, reserve);
+                e = lu_product(mr, w, C2, lda, X2, Y2, flags, s2ws, info, st, reserve);
             else
                 e = launch_update<double>(mr, mr, w, C2, lda, X2, lda, Y2, lda, false, false, 0, info, st, reserve, 0,
                                           0.0, 1.0 - tail);
@@ -665,9 +672,10 @@ int lu_lookahead(int n, int s, double* A, int64_t lda, unsigned flags, int* info
     return 0;
 }
 
-int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st) {
-    if (n > s && !(flags & FF_FLAG_NO_LOOKAHEAD)) return lu_lookahead(n, s, A, lda, flags, info, col_base, st);
-    return lu_in_order(n, s, A, lda, flags, info, col_base, st, 0);
+int lu_blocked(int n, int s, double* A, int64_t lda, unsigned flags, int* info, int col_base, hipStream_t st,
+               double* s2ws) {
+    if (n > s && !(flags & FF_FLAG_NO_LOOKAHEAD)) return lu_lookahead(n, s, A, lda, flags, info, col_base, st, s2ws);
+    return lu_in_order(n, s, A, lda, flags, info, col_base, st, 0, s2ws);
 }
 
 int check_common(int64_t n, int64_t s, const void* A, int64_t lda, int dtype, unsigned flags) {
@@ -676,7 +684,8 @@ int check_common(int64_t n, int64_t s, const void* A, int64_t lda, int dtype, un
     if (n > 0 && A == nullptr) return -3;
     if (lda < std::max<int64_t>(1, n)) return -4;
     if (dtype != FF_F64 && dtype != FF_F32 && dtype != FF_BF16) return -5;
-    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP)) return -6;
+    if (flags & ~(unsigned)(FF_FLAG_STRASSEN1 | FF_FLAG_STRASSEN2 | FF_FLAG_NO_LOOKAHEAD | FF_FLAG_FIXED_STEP))
+        return -6;
     return 0;
 }
 
@@ -1112,6 +1121,7 @@ int chol_factor(int64_t n, int64_t s, void* A, int64_t lda, int dtype, unsigned 
     if (rc) return rc;
     if (d_info == nullptr) return -9;
     if ((flags & FF_FLAG_STRASSEN1) && dtype != FF_F64) return FF_ERR_UNSUPPORTED;
+    if (flags & FF_FLAG_STRASSEN2) return FF_ERR_UNSUPPORTED;
     const size_t need = ff_chol_workspace_size(n, s, dtype, flags);
     if (need > 0 && (ws == nullptr || ws_bytes < need)) return FF_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1127,22 +1137,24 @@ int chol_factor(int64_t n, int64_t s, void* A, int64_t lda, int dtype, unsigned 
 }
 
 size_t ff_lu_workspace_size(int64_t n, int64_t s, int dtype, unsigned flags) {
-    (void)n; (void)s; (void)dtype; (void)flags;
-    return 0;
+    if (n <= 0 || s < 1 || dtype != FF_F64 || !(flags & FF_FLAG_STRASSEN2)) return 0;
+    return strassen2_ws_doubles((int)n, (int)std::min<int64_t>(s, n)) * sizeof(double);
 }
-
 int lu_nopiv_factor(int64_t n, int64_t s, void* A, int64_t lda, int dtype, unsigned flags, void* ws, size_t ws_bytes,
                     int32_t* d_info, void* stream) {
-    (void)ws; (void)ws_bytes;
     int rc = check_common(n, s, A, lda, dtype, flags);
     if (rc) return rc;
     if (d_info == nullptr) return -9;
     if (dtype != FF_F64) return FF_ERR_UNSUPPORTED;
+    if ((flags & FF_FLAG_STRASSEN1) && (flags & FF_FLAG_STRASSEN2)) return -6;
+    const size_t need = ff_lu_workspace_size(n, s, dtype, flags);
+    if (need > 0 && (ws == nullptr || ws_bytes < need)) return FF_ERR_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (launch_set_int(d_info, 0, st) != hipSuccess) return FF_ERR_HIP;
     if (n == 0) return 0;
     const int si = (int)std::min<int64_t>(s, n);
-    return lu_blocked((int)n, si, static_cast<double*>(A), lda, flags, d_info, 0, st);
+    return lu_blocked((int)n, si, static_cast<double*>(A), lda, flags, d_info, 0, st,
+                      (flags & FF_FLAG_STRASSEN2) ? static_cast<double*>(ws) : nullptr);
 }
 
 size_t ff_qr_workspace_size(int64_t m, int64_t n, int64_t s, int dtype, unsigned flags) {

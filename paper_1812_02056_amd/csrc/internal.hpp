@@ -87,6 +87,13 @@ int update_order_tiles(int M, int N, bool lower, int shift, int reserve_cus);
 // all but reserve_cus CUs.
 hipError_t launch_update_syrk_strassen_f64(int m, int w, double* C, int64_t ldc, const double* P, int64_t ldp,
                                            const int* info, hipStream_t st, int reserve_cus = 0);
+// Two Strassen levels for the LU product (a matrix-level level over the
+// one-level kernel) once m >= STRASSEN2_MIN_M; ws: strassen2_ws_doubles(m, w).
+constexpr int STRASSEN2_MIN_M = 2048;
+size_t strassen2_ws_doubles(int m, int w);
+hipError_t launch_update_gemm_strassen2_f64(int m, int w, double* C, int64_t ldc, const double* X, int64_t ldx,
+                                            const double* Y, int64_t ldy, double* ws, const int* info, hipStream_t st,
+                                            int reserve_cus = 0);
 hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc, const double* X, int64_t ldx,
                                            const double* Y, int64_t ldy, const int* info, hipStream_t st,
                                            int reserve_cus = 0);

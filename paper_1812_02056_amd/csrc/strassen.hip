@@ -32,6 +32,8 @@
 // blocks) at the same position, forms the seven operand sums in registers while
 // staging, and writes them to LDS.  Stages of 8 K positions are double-buffered
 // in LDS and loaded one stage ahead.
+#include <algorithm>
+
 #include "common.hpp"
 #include "grid.hpp"
 #include "internal.hpp"
@@ -306,6 +308,145 @@ hipError_t launch_update_gemm_strassen_f64(int m, int w, double* C, int64_t ldc,
                                            const double* Y, int64_t ldy, const int* info, hipStream_t st,
                                            int reserve_cus) {
     return launch_strassen(m, m, w, C, ldc, X, ldx, Y, ldy, false, false, info, st, reserve_cus);
+}
+
+// ---------------------------------------------------------------- a second level
+// The paper's experiments apply Strassen recursively (Sec. 2, timing paragraph).
+// A second level at matrix scale on the LU product C -= X Y (C m x m, X m x w,
+// Y w x m): with mh = floor(m / 2), kh = floor(w / 2) the leading 2mh x 2mh part
+// of C takes Strassen's seven half-size products over the leading 2kh columns of
+// X, each product computed by the one-level kernel above (so every output takes
+// two levels); an odd last row, column or K index is applied classically first.
+// Products that feed one quadrant are subtracted into it directly (M6 into C22,
+// M7 into C11); the other five are formed into a scratch T (T = 0, T -= .., so
+// T = -Mi) and added to, or subtracted from, the quadrants they feed:
+//     C11 -= M1 + M4 - M5 + M7   C12 -= M3 + M5   C21 -= M2 + M4
+//     C22 -= M1 - M2 + M3 + M6
+// Workspace: strassen2_ws_doubles(m, w) doubles (operand sums and T).
+namespace {
+__global__ void s2_sum_kernel(int m, int n, const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                              int64_t ldb, double beta, double* __restrict__ D, int64_t ldd,
+                              const int* __restrict__ info) {
+    if (info && *info != 0) return;
+    for (int j = blockIdx.y; j < n; j += gridDim.y)
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+            D[i + (int64_t)j * ldd] = A[i + (int64_t)j * lda] + beta * B[i + (int64_t)j * ldb];
+}
+__global__ void s2_axpy_kernel(int m, int n, const double* __restrict__ T, int64_t ldt, double alpha,
+                               double* __restrict__ C, int64_t ldc, const int* __restrict__ info) {
+    if (info && *info != 0) return;
+    for (int j = blockIdx.y; j < n; j += gridDim.y)
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+            C[i + (int64_t)j * ldc] += alpha * T[i + (int64_t)j * ldt];
+}
+__global__ void s2_zero_kernel(int m, int n, double* __restrict__ T, int64_t ldt, const int* __restrict__ info) {
+    if (info && *info != 0) return;
+    for (int j = blockIdx.y; j < n; j += gridDim.y)
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+            T[i + (int64_t)j * ldt] = 0.0;
+}
+dim3 s2_grid(int m, int n) { return dim3((unsigned)std::min(4, (m + 255) / 256), (unsigned)std::min(n, 4096)); }
+}  // namespace
+
+size_t strassen2_ws_doubles(int m, int w) {
+    const size_t mh = (size_t)(m / 2), kh = (size_t)(w / 2);
+    return 2 * mh * kh + mh * mh;
+}
+
+hipError_t launch_update_gemm_strassen2_f64(int m, int w, double* C, int64_t ldc, const double* X, int64_t ldx,
+                                            const double* Y, int64_t ldy, double* ws, const int* info, hipStream_t st,
+                                            int reserve_cus) {
+    if (m <= 0 || w <= 0) return hipSuccess;
+    if (m < STRASSEN2_MIN_M || w < 2 || ws == nullptr)
+        return launch_update_gemm_strassen_f64(m, w, C, ldc, X, ldx, Y, ldy, info, st, reserve_cus);
+    const int mh = m / 2, kh = w / 2;
+    hipError_t e = hipSuccess;
+    // classical remainders: the odd K index over all of C, then an odd last row and column
+    if (w > 2 * kh)
+        e = launch_update<double>(m, m, w - 2 * kh, C, ldc, X + (int64_t)2 * kh * ldx, ldx, Y + 2 * kh, ldy, false,
+                                  false, 0, info, st, reserve_cus);
+    if (e == hipSuccess && m > 2 * mh) {
+        e = launch_update<double>(m - 2 * mh, m, 2 * kh, C + 2 * mh, ldc, X + 2 * mh, ldx, Y, ldy, false, false, 0,
+                                  info, st, reserve_cus);
+        if (e == hipSuccess)
+            e = launch_update<double>(2 * mh, m - 2 * mh, 2 * kh, C + (int64_t)2 * mh * ldc, ldc, X, ldx,
+                                      Y + (int64_t)2 * mh * ldy, ldy, false, false, 0, info, st, reserve_cus);
+    }
+    if (e != hipSuccess) return e;
+    double* TX = ws;
+    double* TY = ws + (size_t)mh * kh;
+    double* T = TY + (size_t)kh * mh;
+    const double *X11 = X, *X12 = X + (int64_t)kh * ldx, *X21 = X + mh, *X22 = X + mh + (int64_t)kh * ldx;
+    const double *Y11 = Y, *Y12 = Y + (int64_t)mh * ldy, *Y21 = Y + kh, *Y22 = Y + kh + (int64_t)mh * ldy;
+    double *C11 = C, *C12 = C + (int64_t)mh * ldc, *C21 = C + mh, *C22 = C + mh + (int64_t)mh * ldc;
+    auto sumx = [&](const double* A, const double* B, double beta) {
+        hipLaunchKernelGGL(s2_sum_kernel, s2_grid(mh, kh), dim3(256), 0, st, mh, kh, A, ldx, B, ldx, beta, TX,
+                           (int64_t)mh, info);
+        return hipGetLastError();
+    };
+    auto sumy = [&](const double* A, const double* B, double beta) {
+        hipLaunchKernelGGL(s2_sum_kernel, s2_grid(kh, mh), dim3(256), 0, st, kh, mh, A, ldy, B, ldy, beta, TY,
+                           (int64_t)kh, info);
+        return hipGetLastError();
+    };
+    auto zero_t = [&]() {
+        hipLaunchKernelGGL(s2_zero_kernel, s2_grid(mh, mh), dim3(256), 0, st, mh, mh, T, (int64_t)mh, info);
+        return hipGetLastError();
+    };
+    auto add_t = [&](double* Cq, double alpha) {
+        hipLaunchKernelGGL(s2_axpy_kernel, s2_grid(mh, mh), dim3(256), 0, st, mh, mh, (const double*)T, (int64_t)mh,
+                           alpha, Cq, ldc, info);
+        return hipGetLastError();
+    };
+    auto prod = [&](double* Cq, int64_t ldcq, const double* A, int64_t lda, const double* B, int64_t ldb) {
+        return launch_update_gemm_strassen_f64(mh, kh, Cq, ldcq, A, lda, B, ldb, info, st, reserve_cus);
+    };
+#define S2_TRY(x)                          \
+    do {                                   \
+        hipError_t e_ = (x);               \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)
+    // M1 = (X11 + X22)(Y11 + Y22): C11, C22
+    S2_TRY(sumx(X11, X22, 1.0));
+    S2_TRY(sumy(Y11, Y22, 1.0));
+    S2_TRY(zero_t());
+    S2_TRY(prod(T, mh, TX, mh, TY, kh));
+    S2_TRY(add_t(C11, 1.0));
+    S2_TRY(add_t(C22, 1.0));
+    // M2 = (X21 + X22) Y11: C21, C22 (-)
+    S2_TRY(sumx(X21, X22, 1.0));
+    S2_TRY(zero_t());
+    S2_TRY(prod(T, mh, TX, mh, Y11, ldy));
+    S2_TRY(add_t(C21, 1.0));
+    S2_TRY(add_t(C22, -1.0));
+    // M3 = X11 (Y12 - Y22): C12, C22
+    S2_TRY(sumy(Y12, Y22, -1.0));
+    S2_TRY(zero_t());
+    S2_TRY(prod(T, mh, X11, ldx, TY, kh));
+    S2_TRY(add_t(C12, 1.0));
+    S2_TRY(add_t(C22, 1.0));
+    // M4 = X22 (Y21 - Y11): C11, C21
+    S2_TRY(sumy(Y21, Y11, -1.0));
+    S2_TRY(zero_t());
+    S2_TRY(prod(T, mh, X22, ldx, TY, kh));
+    S2_TRY(add_t(C11, 1.0));
+    S2_TRY(add_t(C21, 1.0));
+    // M5 = (X11 + X12) Y22: C11 (-), C12
+    S2_TRY(sumx(X11, X12, 1.0));
+    S2_TRY(zero_t());
+    S2_TRY(prod(T, mh, TX, mh, Y22, ldy));
+    S2_TRY(add_t(C11, -1.0));
+    S2_TRY(add_t(C12, 1.0));
+    // M6 = (X21 - X11)(Y11 + Y12): into C22
+    S2_TRY(sumx(X21, X11, -1.0));
+    S2_TRY(sumy(Y11, Y12, 1.0));
+    S2_TRY(prod(C22, ldc, TX, mh, TY, kh));
+    // M7 = (X12 - X22)(Y21 + Y22): into C11
+    S2_TRY(sumx(X12, X22, -1.0));
+    S2_TRY(sumy(Y21, Y22, 1.0));
+    S2_TRY(prod(C11, ldc, TX, mh, TY, kh));
+#undef S2_TRY
+    return hipSuccess;
 }
 
 }  // namespace ff

@@ -60,8 +60,9 @@ def chol_int_family(n: int, seed: int = 0, p_zero: float = 1.0 / 3.0):
     off = rng.choice(np.array([-1, 0, 1], dtype=np.int64), size=(n, n), p=[p_nz, p_zero, p_nz])
     L0 = np.tril(off, -1)
     L0[np.diag_indices(n)] = rng.integers(1, 3, size=n)
-    A = L0 @ L0.T                                  # exact in int64
-    return np.asfortranarray(L0.astype(np.float64)), np.asfortranarray(A.astype(np.float64))
+    L0f = L0.astype(np.float64)
+    A = L0f @ L0f.T                                # integer partial sums of magnitude <= 4n: exact in binary64
+    return np.asfortranarray(L0f), np.asfortranarray(A)
 
 
 def chol_float_family(n: int, seed: int = 0, scaled: bool = True):
@@ -83,9 +84,9 @@ def lu_int_family(n: int, seed: int = 0):
     L0 = np.tril(rng.choice(vals, size=(n, n)), -1) + np.eye(n, dtype=np.int64)
     U0 = np.triu(rng.choice(vals, size=(n, n)), 1)
     U0[np.diag_indices(n)] = rng.integers(1, 3, size=n)
-    A = L0 @ U0
-    return (np.asfortranarray(L0.astype(np.float64)), np.asfortranarray(U0.astype(np.float64)),
-            np.asfortranarray(A.astype(np.float64)))
+    L0f, U0f = L0.astype(np.float64), U0.astype(np.float64)
+    A = L0f @ U0f              # integer partial sums of magnitude <= 2n: exact in binary64
+    return np.asfortranarray(L0f), np.asfortranarray(U0f), np.asfortranarray(A)
 
 
 def diag_dominant(n: int, seed: int = 0) -> np.ndarray:

@@ -174,3 +174,49 @@ def test_strassen_update_skipped_when_info_set():
     i2 = ff.chol_factor(A2, 64, dtype="f64", strassen=True, sync=True, no_lookahead=True)
     assert i1 == i2 == 11
     assert np.array_equal(host(A1), host(A2))
+
+
+# Two Strassen levels (FF_FLAG_STRASSEN2): a matrix-level level over the
+# one-level kernel on trailing products of m >= 2048 rows.  On the integer family
+# every operand sum, product and accumulation stays a small integer, so the
+# factors must be the generating ones bit for bit; odd n and odd steps exercise the
+# classical remainders of the matrix-level split.
+@pytest.mark.parametrize("n,s,no_lookahead", [(4096, 256, False), (4097, 257, False), (4400, 384, True),
+                                              (2600, 129, False)])
+def test_strassen2_lu_integer_family_bitwise(n, s, no_lookahead):
+    L0, U0, A = wl.lu_int_family(n, seed=3 * n + s)
+    Ad = dev(A, ld=n + 3)
+    assert ff.lu_nopiv_factor(Ad, s, dtype="f64", strassen=2, no_lookahead=no_lookahead, sync=True) == 0
+    LU = host(Ad)
+    assert np.array_equal(np.tril(LU, -1) + np.eye(n), L0)
+    assert np.array_equal(np.triu(LU), U0)
+
+
+def test_strassen2_lu_diag_dominant_against_oracle():
+    # two levels: operand sums of up to four entries and Strassen's constant grown
+    # by about 12 per level (Higham, Accuracy and Stability, Sec. 23.2.2); the
+    # factors of this well-conditioned matrix stay within 1e-10 of the oracle's
+    n, s = 3000, 384
+    A = wl.diag_dominant(n, seed=19)
+    Ad = dev(A)
+    assert ff.lu_nopiv_factor(Ad, s, dtype="f64", strassen=2, sync=True) == 0
+    LU = host(Ad)
+    LUo, _ = oracle.lu(A)
+    Lg, Lo = np.tril(LU, -1), np.tril(LUo, -1)
+    Ug, Uo = np.triu(LU), np.triu(LUo)
+    el = np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo + np.eye(n))
+    eu = np.linalg.norm(Ug - Uo) / np.linalg.norm(Uo)
+    print(f"two-level Strassen LU n={n} s={s}: rel_L {el:.2e} rel_U {eu:.2e} bwd {oracle.bwd_lu(A, LU):.2e}")
+    assert el <= 1e-10 and eu <= 1e-10
+    assert oracle.bwd_lu(A, LU) <= 1e-12
+
+
+def test_strassen2_lu_fullsize_integer_family_bitwise():
+    n, s = 16384, 768
+    L0, U0, A = wl.lu_int_family_device(n, seed=23, device=DEV)
+    Acm = A.t().contiguous().t()
+    assert ff.lu_nopiv_factor(Acm, s, dtype="f64", strassen=2, sync=True) == 0
+    assert torch.equal(torch.tril(Acm, -1) + torch.eye(n, dtype=torch.float64, device=DEV), L0)
+    assert torch.equal(torch.triu(Acm), U0)
+    del L0, U0, A, Acm
+    torch.cuda.empty_cache()

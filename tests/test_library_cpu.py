@@ -90,7 +90,7 @@ def test_flag_constants_match_the_header():
     text = _header_without_comments()
     flags = dict(re.findall(r"\b(FF_FLAG_[A-Z0-9_]+)\s*=\s*1u\s*<<\s*(\d+)", text))
     assert set(flags) == {"FF_FLAG_STRASSEN1", "FF_FLAG_NO_LOOKAHEAD", "FF_FLAG_FIXED_STEP", "FF_FLAG_ESCALATE",
-                          "FF_FLAG_GMRES_IR"}
+                          "FF_FLAG_GMRES_IR", "FF_FLAG_STRASSEN2"}
     for name, shift in flags.items():
         assert getattr(binding, name[3:]) == 1 << int(shift), name
 
@@ -144,3 +144,14 @@ def test_qr_argument_checks_and_workspace(lib):
     assert lib.ff_qr_step(1000, 1000, 100) == 100
     assert lib.ff_qr_step(1000, 50, 100) == 50
     assert 1 <= lib.ff_qr_step(16384, 16384, 10 ** 6) <= 256
+
+
+def test_strassen2_flag_checks_and_workspace(lib):
+    p = ctypes.c_void_p(16)
+    info = ctypes.c_int32(0)
+    # two levels need a workspace for LU (binary64 only), and are not taken by Cholesky
+    assert lib.ff_lu_workspace_size(4096, 512, 0, 32) >= (2048 * 2048 + 2 * 2048 * 256) * 8
+    assert lib.ff_lu_workspace_size(4096, 512, 0, 0) == 0
+    assert lib.lu_nopiv_factor(4096, 512, p, 4096, 0, 32, None, 0, ctypes.byref(info), None) == -101
+    assert lib.lu_nopiv_factor(4096, 512, p, 4096, 0, 1 | 32, p, 1 << 40, ctypes.byref(info), None) == -6
+    assert lib.chol_factor(4096, 512, p, 4096, 0, 32, p, 1 << 40, ctypes.byref(info), None) == -102
