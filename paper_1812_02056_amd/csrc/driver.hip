@@ -694,6 +694,7 @@ int check_common(int64_t n, int64_t s, const void* A, int64_t lda, int dtype, un
 // residual relative to its starting norm.
 constexpr int GM_RESTART = 30;
 constexpr double GM_INNER_TOL = 1e-8;
+constexpr int GM_SCAL = 4 * 32;     // device scalars per column: squared norm, h1, h2, y
 
 template <typename S>
 struct SolveWs {
@@ -737,110 +738,133 @@ SolveWs<S> carve_solve(void* base, int64_t n, int64_t s, int64_t nrhs, int dtype
     w.D = cv.take<S>((size_t)n * (size_t)nrhs);
     w.rowsum = cv.take<double>((size_t)n);
     w.norms = cv.take<double>(3 + 3 * (size_t)nrhs);
-    w.V = cv.take<double>((size_t)n * (GM_RESTART + 1));
-    w.t = cv.take<double>((size_t)n);
-    w.d = cv.take<double>((size_t)n);
-    w.mpart = cv.take<double>(multidot_part_doubles((int)n));
-    w.scal = cv.take<double>(4 * 32);
+    w.V = cv.take<double>((size_t)n * (GM_RESTART + 1) * (size_t)nrhs);
+    w.t = cv.take<double>((size_t)n * (size_t)nrhs);
+    w.d = cv.take<double>((size_t)n * (size_t)nrhs);
+    w.mpart = cv.take<double>(multidot_part_doubles((int)n) * (size_t)nrhs);
+    w.scal = cv.take<double>((size_t)GM_SCAL * (size_t)nrhs);
     w.bytes = cv.off;
     return w;
 }
 
-// Correction of one column by left-preconditioned GMRES in binary64: solve
-// M^-1 A d = M^-1 r with M = W W^T (the factor in its storage precision, applied
-// by the two triangular solves), then x += d.  On return norms[0..1] hold
-// max|d|, max|x| (device) and *k_used the Krylov steps taken.  Classical
-// Gram-Schmidt applied twice orthogonalises each new vector; the Hessenberg
-// matrix, its Givens rotations and the small triangular solve live on the host.
+// Correction of the active columns of X by left-preconditioned GMRES in binary64:
+// per column, solve M^-1 A d = M^-1 r with M = W W^T (the factor in its storage
+// precision, applied by the two triangular solves) and r = b - A x, then x += d.
+// The columns run in lockstep: one residual, one pair of triangular solves and
+// one set of multi-dot launches per Arnoldi step serve all of them, while each
+// keeps its own basis, Hessenberg matrix and Givens rotations (on the host) and
+// its own stop.  Classical Gram-Schmidt applied twice orthogonalises each new
+// vector.  Inactive columns get d = 0.  On return norms[2c], norms[2c + 1] hold
+// max|d_c|, max|x_c| (device) and k_used[c] the Krylov steps column c took.
 template <typename S>
-int gmres_correct(int n, const double* A64, int64_t lda, const S* W, int64_t ldw, const double* b, double* x,
-                  const SolveWs<S>& w, hipStream_t st, int* k_used) {
+int gmres_correct(int n, int nr, const double* A64, int64_t lda, const S* W, int64_t ldw, const double* B,
+                  int64_t ldb, double* X, int64_t ldx, const SolveWs<S>& w, hipStream_t st, const char* active,
+                  int* k_used) {
     const int m = GM_RESTART;
+    const int64_t vs = (int64_t)n * (m + 1);      // one column's basis
+    const int64_t ps = (int64_t)multidot_part_doubles(n);
     double* V = w.V;
-    double* zero_rhs = w.d;                       // n zeros: the matvec is a residual with b = 0
-    FF_TRY(launch_fill_double(n, zero_rhs, 0.0, st));
-    auto precond = [&](const double* in, double* out) -> hipError_t {
-        // out = W^-T W^-1 in, in the factor's precision
-        hipError_t e = launch_convert_from_f64<S>(n, 1, in, n, w.D, n, st);
-        if (e == hipSuccess) e = trisolve_impl<S>(n, 1, W, ldw, w.D, n, w.tri, false, st);
-        if (e == hipSuccess) e = launch_widen<S>(n, 1, w.D, n, out, n, st);
+    double* zero_rhs = w.d;                       // n x nr zeros: the matvec is a residual with b = 0
+    FF_TRY(launch_fill_double(n * nr, zero_rhs, 0.0, st));
+    auto precond = [&](const double* in, int64_t ldi, double* out, int64_t ldo) -> hipError_t {
+        // out = W^-T W^-1 in, in the factor's precision, all columns
+        hipError_t e = launch_convert_from_f64<S>(n, nr, in, ldi, w.D, n, st);
+        if (e == hipSuccess) e = trisolve_impl<S>(n, nr, W, ldw, w.D, n, w.tri, false, st);
+        if (e == hipSuccess) e = launch_widen<S>(n, nr, w.D, n, out, ldo, st);
         return e;
     };
-    // r = b - A x, z = M^-1 r into V[:, 0], beta^2 = z.z
-    FF_TRY(launch_residual_f64(n, 1, A64, lda, x, n, b, n, w.R, n, nullptr, w.rpart, st));
-    FF_TRY(precond(w.R, V));
-    double* sq = w.scal;                          // device scalars: [0] squared norm, [32..] h1, [64..] h2, [96..] y
+    double* sq = w.scal;                          // column c: [c*GM_SCAL] squared norm, +32 h1, +64 h2, +96 y
     double* h1 = w.scal + 32;
     double* h2 = w.scal + 64;
     double* ydev = w.scal + 96;
-    FF_TRY(launch_multidot(n, 1, V, n, V, w.mpart, sq, st));
-    double beta2 = 0.0;
-    FF_TRY(hipMemcpyAsync(&beta2, sq, sizeof(double), hipMemcpyDeviceToHost, st));
+    // r = b - A x, z = M^-1 r into V_c[:, 0], beta_c^2 = z.z
+    FF_TRY(launch_residual_f64(n, nr, A64, lda, X, ldx, B, ldb, w.R, n, nullptr, w.rpart, st));
+    FF_TRY(precond(w.R, n, V, vs));
+    FF_TRY(launch_multidot(n, nr, 1, V, n, vs, V, vs, w.mpart, sq, GM_SCAL, st));
+    std::vector<double> hostv((size_t)nr * GM_SCAL);
+    FF_TRY(hipMemcpyAsync(hostv.data(), w.scal, hostv.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     FF_TRY(hipStreamSynchronize(st));
-    *k_used = 0;
-    if (!(beta2 > 0.0)) {                         // nothing to correct (or an unusable value)
-        FF_TRY(launch_axpy_max<double>(n, 1, zero_rhs, n, x, n, w.norms, st));
-        return 0;
+    std::vector<double> beta(nr), H((size_t)nr * (m + 1) * m, 0.0), cs((size_t)nr * m), sn((size_t)nr * m),
+        g((size_t)nr * (m + 1), 0.0);
+    std::vector<char> done(nr, 1);
+    int running = 0;
+    for (int c = 0; c < nr; ++c) {
+        k_used[c] = 0;
+        const double b2 = hostv[(size_t)c * GM_SCAL];
+        if (active[c] && b2 > 0.0) {               // else nothing to correct (or an unusable value)
+            beta[c] = std::sqrt(b2);
+            g[(size_t)c * (m + 1)] = beta[c];
+            done[c] = 0;
+            ++running;
+        }
     }
-    const double beta = std::sqrt(beta2);
-    FF_TRY(launch_normalize(n, V, sq, V, st));
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
-    g[0] = beta;
-    int k = 0;
-    for (; k < m; ++k) {
+    FF_TRY(launch_normalize(n, nr, V, vs, sq, GM_SCAL, V, vs, st));
+    for (int k = 0; k < m && running > 0; ++k) {
         double* vk = V + (int64_t)k * n;
         double* vn = V + (int64_t)(k + 1) * n;
         // t = -A v_k (a residual with b = 0), vn = M^-1 (-A v_k), then negated
-        FF_TRY(launch_residual_f64(n, 1, A64, lda, vk, n, zero_rhs, n, w.t, n, nullptr, w.rpart, st));
-        FF_TRY(precond(w.t, vn));
-        FF_TRY(launch_negate(n, vn, vn, st));
-        FF_TRY(launch_multidot(n, k + 1, V, n, vn, w.mpart, h1, st));
-        FF_TRY(launch_gemv_add(n, k + 1, V, n, h1, -1.0, vn, st));
-        FF_TRY(launch_multidot(n, k + 1, V, n, vn, w.mpart, h2, st));
-        FF_TRY(launch_gemv_add(n, k + 1, V, n, h2, -1.0, vn, st));
-        FF_TRY(launch_multidot(n, 1, vn, n, vn, w.mpart, sq, st));
-        double hh[2 * 32 + 1];
-        FF_TRY(hipMemcpyAsync(hh, h1, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
-        FF_TRY(hipMemcpyAsync(hh + 32, h2, 32 * sizeof(double), hipMemcpyDeviceToHost, st));
-        FF_TRY(hipMemcpyAsync(hh + 64, sq, sizeof(double), hipMemcpyDeviceToHost, st));
+        FF_TRY(launch_residual_f64(n, nr, A64, lda, vk, vs, zero_rhs, n, w.t, n, nullptr, w.rpart, st));
+        FF_TRY(precond(w.t, n, vn, vs));
+        FF_TRY(launch_negate(n, nr, vn, vs, vn, vs, st));
+        FF_TRY(launch_multidot(n, nr, k + 1, V, n, vs, vn, vs, w.mpart, h1, GM_SCAL, st));
+        FF_TRY(launch_gemv_add(n, nr, k + 1, V, n, vs, h1, GM_SCAL, -1.0, vn, vs, st));
+        FF_TRY(launch_multidot(n, nr, k + 1, V, n, vs, vn, vs, w.mpart, h2, GM_SCAL, st));
+        FF_TRY(launch_gemv_add(n, nr, k + 1, V, n, vs, h2, GM_SCAL, -1.0, vn, vs, st));
+        FF_TRY(launch_multidot(n, nr, 1, vn, n, vs, vn, vs, w.mpart, sq, GM_SCAL, st));
+        FF_TRY(hipMemcpyAsync(hostv.data(), w.scal, hostv.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         FF_TRY(hipStreamSynchronize(st));
-        double* col = &H[(size_t)k * (m + 1)];    // column k of H, rows 0..k+1
-        for (int i = 0; i <= k; ++i) col[i] = hh[i] + hh[32 + i];
-        const double hn = std::sqrt(std::max(hh[64], 0.0));
-        col[k + 1] = hn;
-        if (hn > 0.0) FF_TRY(launch_normalize(n, vn, sq, vn, st));
-        // apply the earlier rotations, then a new one that zeroes col[k + 1]
-        for (int i = 0; i < k; ++i) {
-            const double a = col[i], c = col[i + 1];
-            col[i] = cs[i] * a + sn[i] * c;
-            col[i + 1] = -sn[i] * a + cs[i] * c;
+        for (int c = 0; c < nr; ++c) {
+            if (done[c]) continue;
+            const double* hc = &hostv[(size_t)c * GM_SCAL];
+            double* col = &H[((size_t)c * m + k) * (m + 1)];   // column k of column c's H, rows 0..k+1
+            for (int i = 0; i <= k; ++i) col[i] = hc[32 + i] + hc[64 + i];
+            const double hn = std::sqrt(std::max(hc[0], 0.0));
+            col[k + 1] = hn;
+            double* csc = &cs[(size_t)c * m];
+            double* snc = &sn[(size_t)c * m];
+            double* gc = &g[(size_t)c * (m + 1)];
+            // apply the earlier rotations, then a new one that zeroes col[k + 1]
+            for (int i = 0; i < k; ++i) {
+                const double a = col[i], b = col[i + 1];
+                col[i] = csc[i] * a + snc[i] * b;
+                col[i + 1] = -snc[i] * a + csc[i] * b;
+            }
+            const double rr = std::hypot(col[k], col[k + 1]);
+            csc[k] = rr > 0.0 ? col[k] / rr : 1.0;
+            snc[k] = rr > 0.0 ? col[k + 1] / rr : 0.0;
+            col[k] = rr;
+            col[k + 1] = 0.0;
+            gc[k + 1] = -snc[k] * gc[k];
+            gc[k] = csc[k] * gc[k];
+            k_used[c] = k + 1;
+            if (std::fabs(gc[k + 1]) <= GM_INNER_TOL * beta[c] || !(hn > 0.0) || !(rr > 0.0)) {
+                done[c] = 1;
+                --running;
+            }
         }
-        const double rr = std::hypot(col[k], col[k + 1]);
-        cs[k] = rr > 0.0 ? col[k] / rr : 1.0;
-        sn[k] = rr > 0.0 ? col[k + 1] / rr : 0.0;
-        col[k] = rr;
-        col[k + 1] = 0.0;
-        g[k + 1] = -sn[k] * g[k];
-        g[k] = cs[k] * g[k];
-        if (std::fabs(g[k + 1]) <= GM_INNER_TOL * beta || !(hn > 0.0) || !(rr > 0.0)) {
-            ++k;
-            break;
+        // columns still running normalise their new vector (a zero norm leaves it as is)
+        FF_TRY(launch_normalize(n, nr, vn, vs, sq, GM_SCAL, vn, vs, st));
+    }
+    // y_c = R_c^-1 g_c (upper triangular k_c x k_c), d_c = V_c y_c, x_c += d_c
+    int kmax = 0;
+    for (int c = 0; c < nr; ++c) {
+        const int kc = k_used[c];
+        kmax = std::max(kmax, kc);
+        double* yc = &hostv[(size_t)c * GM_SCAL + 96];
+        for (int i = 0; i < 32; ++i) yc[i] = 0.0;
+        const double* gc = &g[(size_t)c * (m + 1)];
+        for (int i = kc - 1; i >= 0; --i) {
+            double v = gc[i];
+            for (int j = i + 1; j < kc; ++j) v -= H[((size_t)c * m + j) * (m + 1) + i] * yc[j];
+            const double dii = H[((size_t)c * m + i) * (m + 1) + i];
+            yc[i] = dii != 0.0 ? v / dii : 0.0;
         }
     }
-    *k_used = k;
-    // y = R^-1 g (upper triangular k x k), d = V y, x += d with the max norms
-    std::vector<double> y(k, 0.0);
-    for (int i = k - 1; i >= 0; --i) {
-        double v = g[i];
-        for (int j = i + 1; j < k; ++j) v -= H[(size_t)j * (m + 1) + i] * y[j];
-        const double dii = H[(size_t)i * (m + 1) + i];
-        y[i] = dii != 0.0 ? v / dii : 0.0;
-    }
-    FF_TRY(hipMemcpyAsync(ydev, y.data(), (size_t)k * sizeof(double), hipMemcpyHostToDevice, st));
-    FF_TRY(launch_fill_double(n, w.t, 0.0, st));
-    FF_TRY(launch_gemv_add(n, k, V, n, ydev, 1.0, w.t, st));
-    FF_TRY(launch_axpy_max<double>(n, 1, w.t, n, x, n, w.norms, st));
-    FF_TRY(hipStreamSynchronize(st));             // y's host copy is done before y goes
+    FF_TRY(hipMemcpyAsync(w.scal, hostv.data(), hostv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    FF_TRY(launch_fill_double(n * nr, w.t, 0.0, st));
+    FF_TRY(launch_gemv_add(n, nr, kmax, V, n, vs, ydev, GM_SCAL, 1.0, w.t, n, st));
+    FF_TRY(launch_axpy_max_cols<double>(n, nr, w.t, n, X, ldx, w.norms, st));
+    FF_TRY(hipStreamSynchronize(st));             // the host copy of y is done before hostv goes
     return 0;
 }
 
@@ -879,27 +903,39 @@ int solve_impl(int n, int s, int nrhs, const double* A64, int64_t lda, S* W, int
     double host[2];
     int bad_wait = 0;
     if (flags & FF_FLAG_GMRES_IR) {
-        // each column: outer refinement steps whose correction equation is solved
-        // by preconditioned GMRES; iters reports the most outer steps of a column
+        // outer refinement steps, each solving the correction equations of the
+        // active columns by preconditioned GMRES; a column leaves on its own stop
+        // rule; iters reports the most outer steps of a column
+        std::vector<char> active(nrhs, 1);
+        std::vector<int> kused(nrhs, 0), its(nrhs, 0);
+        std::vector<double> pc(nrhs, -1.0), hn(2 * (size_t)nrhs);
+        std::vector<char> conv(nrhs, 0);
+        int left = nrhs;
+        for (int it = 1; it <= max_iter && left > 0; ++it) {
+            int rc = gmres_correct<S>(n, nrhs, A64, lda, W, ldw, B, ldb, X, ldx, w, st, active.data(), kused.data());
+            if (rc) return rc;
+            FF_TRY(hipMemcpyAsync(hn.data(), w.norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+            FF_TRY(hipStreamSynchronize(st));
+            for (int c = 0; c < nrhs; ++c) {
+                if (!active[c]) continue;
+                out->krylov_iters += kused[c];
+                its[c] = it;
+                const double corr = (hn[2 * c + 1] > 0.0) ? hn[2 * c] / hn[2 * c + 1] : hn[2 * c];
+                out->last_correction = std::max(out->last_correction, corr);
+                if (corr <= tol) {
+                    conv[c] = 1;
+                    active[c] = 0;
+                } else if (!(corr == corr) || (pc[c] >= 0.0 && corr > 0.5 * pc[c])) {
+                    active[c] = 0;
+                }
+                pc[c] = corr;
+                if (!active[c]) --left;
+            }
+        }
         int all_conv = 1, max_it = 0;
         for (int c = 0; c < nrhs; ++c) {
-            double pc = -1.0;
-            int conv = 0, it = 0;
-            for (it = 1; it <= max_iter; ++it) {
-                int k = 0;
-                int rc = gmres_correct<S>(n, A64, lda, W, ldw, B + (int64_t)c * ldb, X + (int64_t)c * ldx, w, st, &k);
-                if (rc) return rc;
-                out->krylov_iters += k;
-                FF_TRY(hipMemcpyAsync(host, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-                FF_TRY(hipStreamSynchronize(st));
-                const double corr = (host[1] > 0.0) ? host[0] / host[1] : host[0];
-                out->last_correction = std::max(out->last_correction, corr);
-                if (corr <= tol) { conv = 1; break; }
-                if (!(corr == corr) || (pc >= 0.0 && corr > 0.5 * pc)) break;
-                pc = corr;
-            }
-            all_conv &= conv;
-            max_it = std::max(max_it, std::min(it, max_iter));
+            all_conv &= conv[c];
+            max_it = std::max(max_it, its[c]);
         }
         out->iters = max_it;
         out->converged = all_conv;

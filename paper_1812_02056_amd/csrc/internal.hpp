@@ -211,15 +211,23 @@ hipError_t launch_norms(int n, int nrhs, const double* rowsum, const double* X, 
                         hipStream_t st);
 
 // GMRES pieces (solve.hip): Krylov basis V n x k (k <= 32) column-major binary64.
-// out[i] = V[:, i] . w (part: multidot_part_doubles(n) doubles of scratch);
-// w += alpha V h; y = x / sqrt(*sq); y = -x.
+// GMRES pieces, batched over nc columns: column c's basis is V + c*vs (ld ldv),
+// its vectors w + c*ws, its scalars out / h / sq + c*os (hs, ss).
+// out_c[i] = V_c[:, i] . w_c, i < k <= 32 (part: nc * multidot_part_doubles(n)
+// doubles of scratch); w_c += alpha V_c h_c; y_c = x_c / sqrt(sq_c) (sq_c > 0);
+// y_c = -x_c.
 size_t multidot_part_doubles(int n);
-hipError_t launch_multidot(int n, int k, const double* V, int64_t ldv, const double* w, double* part, double* out,
-                           hipStream_t st);
-hipError_t launch_gemv_add(int n, int k, const double* V, int64_t ldv, const double* h, double alpha, double* w,
-                           hipStream_t st);
-hipError_t launch_normalize(int n, const double* x, const double* sq, double* y, hipStream_t st);
-hipError_t launch_negate(int n, const double* x, double* y, hipStream_t st);
+hipError_t launch_multidot(int n, int nc, int k, const double* V, int64_t ldv, int64_t vs, const double* w, int64_t ws,
+                           double* part, double* out, int64_t os, hipStream_t st);
+hipError_t launch_gemv_add(int n, int nc, int k, const double* V, int64_t ldv, int64_t vs, const double* h,
+                           int64_t hs, double alpha, double* w, int64_t ws, hipStream_t st);
+hipError_t launch_normalize(int n, int nc, const double* x, int64_t xs, const double* sq, int64_t ss, double* y,
+                            int64_t ys, hipStream_t st);
+hipError_t launch_negate(int n, int nc, const double* x, int64_t xs, double* y, int64_t ys, hipStream_t st);
+// X += D with per-column norms out[2j] = max|D_j|, out[2j + 1] = max|X_j|.
+template <typename S>
+hipError_t launch_axpy_max_cols(int n, int nrhs, const S* D, int64_t ldd, double* X, int64_t ldx, double* out,
+                                hipStream_t st);
 hipError_t launch_fill_double(int n, double* y, double v, hipStream_t st);
 
 }  // namespace ff

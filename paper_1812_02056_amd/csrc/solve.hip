@@ -704,7 +704,7 @@ __global__ void zero2_kernel(double* p) { if (threadIdx.x < 2) p[threadIdx.x] = 
 template <typename S>
 __global__ __launch_bounds__(256)
 void axpy_max_kernel(int n, const S* __restrict__ D, int64_t ldd, double* __restrict__ X, int64_t ldx,
-                     double* __restrict__ out) {
+                     double* __restrict__ out, int os) {
     __shared__ unsigned long long md[256], mx[256];
     const int j = blockIdx.y;
     unsigned long long a = 0, b = 0;
@@ -728,24 +728,30 @@ void axpy_max_kernel(int n, const S* __restrict__ D, int64_t ldd, double* __rest
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        atomicMax(reinterpret_cast<unsigned long long*>(&out[0]), md[0]);
-        atomicMax(reinterpret_cast<unsigned long long*>(&out[1]), mx[0]);
+        atomicMax(reinterpret_cast<unsigned long long*>(&out[j * os]), md[0]);
+        atomicMax(reinterpret_cast<unsigned long long*>(&out[j * os + 1]), mx[0]);
     }
 }
 
 // ---------------------------------------------------------------- GMRES pieces
-// Krylov basis V: n x (k) column-major binary64, ld = ldv.  Sums are taken in a
-// fixed order (per-workgroup partials over row chunks, then the partials in
-// workgroup order), so results do not depend on scheduling.
+// Batched over the columns of a multi-column solve: column c (blockIdx.y) has
+// its own Krylov basis V + c*vs (n x k, column-major, ld = ldv) and vectors at
+// w + c*ws.  Sums are taken in a fixed order (per-workgroup partials over row
+// chunks, then the partials in workgroup order), so results do not depend on
+// scheduling.
 constexpr int KV_MAX = 32;          // basis vectors one launch handles
 constexpr int KV_WG = 256;          // threads per workgroup
 constexpr int KV_ROWS = 2048;       // rows per workgroup
 
-// part[g * KV_MAX + i] = sum over the rows of workgroup g of V[:, i] w.
+// part[c][g * KV_MAX + i] = sum over the rows of workgroup g of V_c[:, i] w_c.
 __global__ __launch_bounds__(KV_WG)
-void multidot_part_kernel(int n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ w,
-                          double* __restrict__ part) {
+void multidot_part_kernel(int n, int k, const double* __restrict__ V, int64_t ldv, int64_t vs,
+                          const double* __restrict__ w, int64_t ws, double* __restrict__ part, int64_t ps) {
     __shared__ double red[KV_WG];
+    const int c = blockIdx.y;
+    V += c * vs;
+    w += c * ws;
+    part += c * ps;
     const int r0 = blockIdx.x * KV_ROWS;
     const int r1 = min(n, r0 + KV_ROWS);
     for (int i = 0; i < k; ++i) {
@@ -762,20 +768,25 @@ void multidot_part_kernel(int n, int k, const double* __restrict__ V, int64_t ld
     }
 }
 
-// out[i] = sum_g part[g * KV_MAX + i] (g ascending), i < k.
-__global__ void multidot_reduce_kernel(int k, int ngroups, const double* __restrict__ part, double* __restrict__ out) {
-    const int i = threadIdx.x;
+// out[c][i] = sum_g part[c][g * KV_MAX + i] (g ascending), i < k.
+__global__ void multidot_reduce_kernel(int k, int ngroups, const double* __restrict__ part, int64_t ps,
+                                       double* __restrict__ out, int64_t os) {
+    const int i = threadIdx.x, c = blockIdx.x;
     if (i >= k) return;
     double s = 0.0;
-    for (int g = 0; g < ngroups; ++g) s += part[g * KV_MAX + i];
-    out[i] = s;
+    for (int g = 0; g < ngroups; ++g) s += part[c * ps + g * KV_MAX + i];
+    out[c * os + i] = s;
 }
 
-// w += alpha * V h (h: k values on the device).
-__global__ void gemv_add_kernel(int n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
-                                double alpha, double* __restrict__ w) {
+// w_c += alpha * V_c h_c (h_c: k values on the device).
+__global__ void gemv_add_kernel(int n, int k, const double* __restrict__ V, int64_t ldv, int64_t vs,
+                                const double* __restrict__ h, int64_t hs_, double alpha, double* __restrict__ w,
+                                int64_t ws) {
     __shared__ double hs[KV_MAX];
-    if (threadIdx.x < k) hs[threadIdx.x] = h[threadIdx.x];
+    const int c = blockIdx.y;
+    V += c * vs;
+    w += c * ws;
+    if (threadIdx.x < k) hs[threadIdx.x] = h[c * hs_ + threadIdx.x];
     __syncthreads();
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         double s = 0.0;
@@ -784,19 +795,26 @@ __global__ void gemv_add_kernel(int n, int k, const double* __restrict__ V, int6
     }
 }
 
-// y = x / sqrt(*sq), sq a device scalar (a squared norm); y may alias x.
-__global__ void normalize_kernel(int n, const double* x, const double* __restrict__ sq, double* y) {
-    const double inv = 1.0 / sqrt(*sq);
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) y[r] = x[r] * inv;
+// y_c = x_c / sqrt(sq_c) where sq_c > 0 (a squared norm), else unchanged; y may alias x.
+__global__ void normalize_kernel(int n, const double* x, int64_t xs, const double* __restrict__ sq, int64_t ss,
+                                 double* y, int64_t ys) {
+    const int c = blockIdx.y;
+    const double q = sq[c * ss];
+    if (!(q > 0.0)) return;
+    const double inv = 1.0 / sqrt(q);
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        y[c * ys + r] = x[c * xs + r] * inv;
 }
 
 __global__ void fill_double_kernel(int n, double* __restrict__ y, double v) {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) y[r] = v;
 }
 
-// y = -x (y may alias x).
-__global__ void negate_kernel(int n, const double* x, double* y) {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) y[r] = -x[r];
+// y_c = -x_c (y may alias x).
+__global__ void negate_kernel(int n, const double* x, int64_t xs, double* y, int64_t ys) {
+    const int c = blockIdx.y;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        y[c * ys + r] = -x[c * xs + r];
 }
 
 }  // namespace
@@ -914,9 +932,23 @@ hipError_t launch_axpy_max(int n, int nrhs, const S* D, int64_t ldd, double* X, 
     hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(64), 0, st, out);
     if (n <= 0 || nrhs <= 0) return hipGetLastError();
     const int gx = std::min((n + 255) / 256, 1024);
-    hipLaunchKernelGGL((axpy_max_kernel<S>), dim3(gx, nrhs), dim3(256), 0, st, n, D, ldd, X, ldx, out);
+    hipLaunchKernelGGL((axpy_max_kernel<S>), dim3(gx, nrhs), dim3(256), 0, st, n, D, ldd, X, ldx, out, 0);
     return hipGetLastError();
 }
+
+// X += D, out[2j] = max|D_j|, out[2j + 1] = max|X_j| per column.
+template <typename S>
+hipError_t launch_axpy_max_cols(int n, int nrhs, const S* D, int64_t ldd, double* X, int64_t ldx, double* out,
+                                hipStream_t st) {
+    if (nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_double_kernel, dim3(1), dim3(256), 0, st, 2 * nrhs, out, 0.0);
+    if (n <= 0) return hipGetLastError();
+    const int gx = std::min((n + 255) / 256, 1024);
+    hipLaunchKernelGGL((axpy_max_kernel<S>), dim3(gx, nrhs), dim3(256), 0, st, n, D, ldd, X, ldx, out, 2);
+    return hipGetLastError();
+}
+template hipError_t launch_axpy_max_cols<double>(int, int, const double*, int64_t, double*, int64_t, double*,
+                                                 hipStream_t);
 template hipError_t launch_widen_lower<float>(int, const float*, int64_t, double*, int64_t, hipStream_t);
 template hipError_t launch_narrow_lower<float>(int, const double*, int64_t, float*, int64_t, hipStream_t);
 template hipError_t launch_widen<double>(int, int, const double*, int64_t, double*, int64_t, hipStream_t);
@@ -926,29 +958,32 @@ template hipError_t launch_axpy_max<float>(int, int, const float*, int64_t, doub
 
 size_t multidot_part_doubles(int n) { return (size_t)((n + KV_ROWS - 1) / KV_ROWS) * KV_MAX; }
 
-hipError_t launch_multidot(int n, int k, const double* V, int64_t ldv, const double* w, double* part, double* out,
-                           hipStream_t st) {
-    if (k <= 0) return hipSuccess;
+hipError_t launch_multidot(int n, int nc, int k, const double* V, int64_t ldv, int64_t vs, const double* w, int64_t ws,
+                           double* part, double* out, int64_t os, hipStream_t st) {
+    if (k <= 0 || nc <= 0) return hipSuccess;
     if (k > KV_MAX) return hipErrorInvalidValue;
     const int ng = (n + KV_ROWS - 1) / KV_ROWS;
+    const int64_t ps = (int64_t)multidot_part_doubles(n);
     if (ng > 0)
-        hipLaunchKernelGGL(multidot_part_kernel, dim3(ng), dim3(KV_WG), 0, st, n, k, V, ldv, w, part);
-    hipLaunchKernelGGL(multidot_reduce_kernel, dim3(1), dim3(KV_MAX), 0, st, k, ng, part, out);
+        hipLaunchKernelGGL(multidot_part_kernel, dim3(ng, nc), dim3(KV_WG), 0, st, n, k, V, ldv, vs, w, ws, part, ps);
+    hipLaunchKernelGGL(multidot_reduce_kernel, dim3(nc), dim3(KV_MAX), 0, st, k, ng, part, ps, out, os);
     return hipGetLastError();
 }
 
-hipError_t launch_gemv_add(int n, int k, const double* V, int64_t ldv, const double* h, double alpha, double* w,
-                           hipStream_t st) {
-    if (k <= 0 || n <= 0) return hipSuccess;
+hipError_t launch_gemv_add(int n, int nc, int k, const double* V, int64_t ldv, int64_t vs, const double* h,
+                           int64_t hs, double alpha, double* w, int64_t ws, hipStream_t st) {
+    if (k <= 0 || n <= 0 || nc <= 0) return hipSuccess;
     if (k > KV_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gemv_add_kernel, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, n, k, V, ldv, h,
-                       alpha, w);
+    hipLaunchKernelGGL(gemv_add_kernel, dim3(std::min(1024, (n + 255) / 256), nc), dim3(256), 0, st, n, k, V, ldv, vs,
+                       h, hs, alpha, w, ws);
     return hipGetLastError();
 }
 
-hipError_t launch_normalize(int n, const double* x, const double* sq, double* y, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(normalize_kernel, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, n, x, sq, y);
+hipError_t launch_normalize(int n, int nc, const double* x, int64_t xs, const double* sq, int64_t ss, double* y,
+                            int64_t ys, hipStream_t st) {
+    if (n <= 0 || nc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normalize_kernel, dim3(std::min(1024, (n + 255) / 256), nc), dim3(256), 0, st, n, x, xs, sq, ss,
+                       y, ys);
     return hipGetLastError();
 }
 
@@ -958,9 +993,9 @@ hipError_t launch_fill_double(int n, double* y, double v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_negate(int n, const double* x, double* y, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(negate_kernel, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, n, x, y);
+hipError_t launch_negate(int n, int nc, const double* x, int64_t xs, double* y, int64_t ys, hipStream_t st) {
+    if (n <= 0 || nc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(negate_kernel, dim3(std::min(1024, (n + 255) / 256), nc), dim3(256), 0, st, n, x, xs, y, ys);
     return hipGetLastError();
 }
 
