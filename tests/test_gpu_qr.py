@@ -166,3 +166,22 @@ def test_qr_rejects_bad_arguments():
         ff.qr_factor(dev(np.zeros((10, 20))), 4)  # m < n
     with pytest.raises(ff.FastFactError):
         ff.qr_factor(dev(np.eye(4)), 4, dtype="f32")
+
+
+def test_qr_tall_matrix_uses_256_row_panel_slices():
+    # more rows than 128 per CU: the panel holds 256 rows per workgroup and its
+    # block is at most 71 columns wide
+    cus = torch.cuda.get_device_properties(DEV).multi_processor_count
+    m, n, s = 128 * cus + 1000, 150, 128
+    ws = ff.qr_step(m, n, s)
+    assert ws <= 71
+    A = np.asfortranarray(np.random.default_rng(27).standard_normal((m, n)))
+    Q, R, info = ff.qr_factor(dev(A), s, sync=True)
+    assert info == 0
+    Qo, Ro, _, io = oracle.qr_alg3(A, ws)
+    assert io == 0
+    kappa = np.linalg.cond(A)
+    dq = np.max(np.abs(host(Q) - Qo))
+    dr = np.max(np.abs(host(R) - np.triu(Ro))) / np.max(np.abs(Ro))
+    print(f"m={m} n={n} (block {ws}): |dQ| = {dq:.2e}, |dR|/|R| = {dr:.2e}")
+    assert dq <= 8 * n * kappa * U and dr <= 8 * n * kappa * U
