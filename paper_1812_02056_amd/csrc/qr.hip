@@ -238,7 +238,6 @@ __global__ void zero_strict_lower_kernel(int n, double* __restrict__ D, int64_t 
 constexpr int QR_LDS = QR_PANEL_LDS_DOUBLES;   // panel slab, doubles
 constexpr int QR_NT = 256;
 constexpr int QR_SPIN_LIMIT = 1 << 20;
-constexpr int QR_GB = 16;           // shares per column a lane loads at once
 
 // Hand-off words of the panel: SENT marks a share not written yet; a share whose
 // bits equal SENT (a NaN) is stored as the canonical quiet NaN instead.
@@ -256,6 +255,44 @@ __device__ __forceinline__ void share_clear(double* p) {
 __device__ __forceinline__ unsigned long long share_peek(const double* p) {
     return __hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Step (b) of a panel round for one wave: the sums over workgroups [g_lo, g_hi)
+// of the shares of columns lane + 64 u, u < NG, into accv (in workgroup order).
+// GB shares per column are loaded at once and polled until none is SENT;
+// out-of-range workgroups load a clamped (valid) address and are ignored.
+template <int NG, int GB>
+__device__ __forceinline__ bool gather_shares(const double* pj, int WS, int g_lo, int g_hi, int lane, int nc,
+                                              double (&accv)[4]) {
+    for (int gg0 = g_lo; gg0 < g_hi; gg0 += GB) {
+        unsigned long long v[NG][GB];
+        int spins = 0;
+        while (true) {
+            bool pending = false;
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+#pragma unroll
+                for (int e = 0; e < GB; ++e) {
+                    const int gg = min(gg0 + e, g_hi - 1);
+                    const int ci = min(lane + 64 * u, nc - 1);
+                    v[u][e] = share_peek(pj + (size_t)gg * WS + ci);
+                }
+#pragma unroll
+            for (int u = 0; u < NG; ++u)
+#pragma unroll
+                for (int e = 0; e < GB; ++e)
+                    pending |= (gg0 + e < g_hi && lane + 64 * u < nc && v[u][e] == QR_SENT);
+            if (!__any(pending)) break;
+            if (++spins > QR_SPIN_LIMIT) return false;
+            __builtin_amdgcn_s_sleep(1);
+        }
+#pragma unroll
+        for (int u = 0; u < NG; ++u)
+#pragma unroll
+            for (int e = 0; e < GB; ++e)
+                if (gg0 + e < g_hi) accv[u] += __longlong_as_double((long long)v[u][e]);
+    }
+    return true;
 }
 
 // Block columns [0, w) of Mp (m rows, leading dimension ldm) are replaced by the
@@ -336,42 +373,19 @@ void qr_panel_kernel(int m, int w, int col0, double* __restrict__ Mp, int64_t ld
             if (t < nc) share_put(pj + (size_t)g * WS + t, ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t]);
         }
         __syncthreads();   // every share is read from red before (b) overwrites it
-        // (b) every lane keeps up to 4 columns x QR_GB shares in flight and polls
-        // them until none is SENT; out-of-range slots load a clamped (valid)
-        // address and are ignored
+        // (b) a lane sums the shares of columns lane + 64 u; the gather is
+        // specialised on the number of 64-column groups so that no load goes to
+        // a column past nc, and a wave's whole workgroup range is loaded in one
+        // batch when it spans at most 32 workgroups (two column groups or fewer)
         {
             double accv[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int gg0 = g_lo; gg0 < g_hi; gg0 += QR_GB) {
-                unsigned long long v[4][QR_GB];
-                int spins = 0;
-                while (true) {
-                    bool pending = false;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int e = 0; e < QR_GB; ++e) {
-                            const int gg = min(gg0 + e, g_hi - 1);
-                            const int ci = min(lane + 64 * u, nc - 1);
-                            v[u][e] = share_peek(pj + (size_t)gg * WS + ci);
-                        }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int e = 0; e < QR_GB; ++e)
-                            pending |= (gg0 + e < g_hi && lane + 64 * u < nc && v[u][e] == QR_SENT);
-                    if (!__any(pending)) break;
-                    if (++spins > QR_SPIN_LIMIT) {
-                        bad = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int e = 0; e < QR_GB; ++e)
-                        if (gg0 + e < g_hi) accv[u] += __longlong_as_double((long long)v[u][e]);
-            }
+            const int ng = (nc + 63) / 64;
+            bool ok;
+            if (ng == 1) ok = gather_shares<1, 32>(pj, WS, g_lo, g_hi, lane, nc, accv);
+            else if (ng == 2) ok = gather_shares<2, 32>(pj, WS, g_lo, g_hi, lane, nc, accv);
+            else if (ng == 3) ok = gather_shares<3, 16>(pj, WS, g_lo, g_hi, lane, nc, accv);
+            else ok = gather_shares<4, 16>(pj, WS, g_lo, g_hi, lane, nc, accv);
+            if (!ok) bad = 1;
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (lane + 64 * u < nc) red[h][lane + 64 * u] = accv[u];
