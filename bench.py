@@ -659,7 +659,7 @@ def run_low_precision_factor(ff, torch, dev, n, A0, reps=3):
     return res
 
 
-def run_qr(ff, torch, wl, dev, n=16384, steps=(64, 96, 128, 142), reps=3, paper_sizes=((2000, 100), (4000, 200))):
+def run_qr(ff, torch, wl, dev, n=16384, steps=(64, 96, 112, 128, 142), reps=3, paper_sizes=((2000, 100), (4000, 200))):
     """qr_factor (Algorithm 3) on the benchmark family A = G G^T / n + I: median
     time per step, the rate at the conventional 4n^3/3 and at the algorithm's own
     count (projections 2 n^3, R = Q^T A's upper triangle n^2 (n + 1)), and

@@ -1043,7 +1043,6 @@ QrWs carve_qr(void* base, int64_t m, int64_t n, int64_t s) {
         const int wb = (int)std::min<int64_t>(ws, n - z);
         const int64_t N = n - z - wb;
         if (N > 0) tp = std::max(tp, tn_gemm_part_elems(wb, (int)N, (int)m, false));
-        tp = std::max(tp, tn_gemm_part_elems(wb, (int)(n - z), (int)m, false));   // the block's rows of R
     }
     w.part = cv.take<double>(qr_panel_part_elems(m, ws));
     w.C = cv.take<double>((size_t)ws * (size_t)n);
@@ -1052,16 +1051,27 @@ QrWs carve_qr(void* base, int64_t m, int64_t n, int64_t s) {
     return w;
 }
 
+// K rows of one R slab: about what the idle CUs finish, one tile each, while
+// a panel of w columns runs (measured at n = 16384: 48 K rows per panel column
+// gives the shortest factorisation, against 24 / 32 / 40 / 56).
+int qr_slab_k(int m, int w) {
+    const int k = std::max(512, (48 * w + 15) / 16 * 16);
+    return std::min(k, m);
+}
+
 // Algorithm 3 with step ws: Q := A (Q holds M), then per block the in-block
 // Gram-Schmidt, the block product C = B_Q^T M[:, c..] and M[:, c..] -= B_Q C;
 // finally R = Q^T A.  Every kernel does nothing once *d_info != 0.
 //
-// R's rows of a block, R[z:z+w, z:n] = Q_b^T A[:, z:n], need only that block
-// of Q, so they are formed on a side stream while the next block's
-// Gram-Schmidt runs: that kernel holds one workgroup on each of P CUs and
-// leaves the rest idle, and the side product is capped at the other CUs'
-// worth of workgroups so the panel's workgroups still find free CUs.  R's
-// strict lower triangle is cleared once the side stream has joined.
+// R's tile rows need only finished columns of Q, and the in-block Gram-Schmidt
+// holds one workgroup on each of P CUs and leaves the rest idle, so R is formed
+// by slabs beside the panels: when a panel starts, a side stream takes a group
+// of finished tiles (at most one per idle CU) over the next K chunk, stored for
+// the first chunk and added for the later ones, in K order; a group is done when
+// its chunks cover all m rows.  A slab is sized to end with the panel, so it
+// leaves the projections the whole chip.  After the last panel the open group's
+// remaining K range and all tiles not yet started are formed on both streams,
+// which then join; R's strict lower triangle is cleared last.
 int qr_blocked(int m, int n, int ws, const double* A, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
                const QrWs& w, int* d_info, hipStream_t st) {
     FF_TRY(hipMemcpy2DAsync(Q, (size_t)ldq * sizeof(double), A, (size_t)lda * sizeof(double),
@@ -1070,10 +1080,7 @@ int qr_blocked(int m, int n, int ws, const double* A, int64_t lda, double* Q, in
     const int side_wg = cu_count() - qr_panel_workgroups(m);
     int dev = 0;
     hipStream_t side = nullptr;
-    // (only for blocks of whole 128-row product tiles: narrower or ragged blocks
-    // leave the side product's tiles partly empty, and it then slows the
-    // projections it shares the CUs with more than it saves)
-    if (n > ws && side_wg >= 32 && ws % 128 == 0) {
+    if (n > ws && side_wg >= 32) {
         if (hipGetDevice(&dev) != hipSuccess) return FF_ERR_HIP;
         side = acquire_side(dev);
     }
@@ -1082,26 +1089,35 @@ int qr_blocked(int m, int n, int ws, const double* A, int64_t lda, double* Q, in
         if (side) release_side(dev, side);
         return code;
     };
-    // R rows of the block at column z (width wb), on `on`
-    // (max_wg > 0: no K split; otherwise the split-K partials go to w.tp)
-    auto r_rows = [&](int z, int wb, hipStream_t on, int max_wg) -> hipError_t {
-        return launch_tn_gemm(wb, n - z, m, Q + (int64_t)z * ldq, ldq, A + (int64_t)z * lda, lda,
-                              R + z + (int64_t)z * ldr, ldr, false, max_wg > 0 ? nullptr : w.tp, d_info, on, max_wg);
-    };
-    int prev_z = -1, prev_w = 0;
+    const int rt = r_slab_tile();
+    const int kc = qr_slab_k(m, ws);
+    int64_t g0 = 0, g1 = 0;   // the open group of R tiles
+    int kpos = 0;             // its next K row
     for (int z = 0; z < n; z += ws) {
         const int wb = std::min(ws, n - z);
         double* Bq = Q + (int64_t)z * ldq;
-        if (side && prev_z >= 0) {
-            // the previous block's R rows start with this block's panel
-            hipEvent_t e = evs.make();
-            if (!e || hipEventRecord(e, st) != hipSuccess || hipStreamWaitEvent(side, e, 0) != hipSuccess)
-                return fail(FF_ERR_HIP);
-            if (r_rows(prev_z, prev_w, side, side_wg) != hipSuccess) return fail(FF_ERR_HIP);
+        if (side && z > 0) {
+            bool open = g1 > g0 && kpos < m;
+            if (!open) {
+                const int64_t avail = r_slab_tiles_before(n, z / rt);
+                if (avail > g1) {
+                    g0 = g1;
+                    g1 = std::min<int64_t>(avail, g0 + side_wg);
+                    kpos = 0;
+                    open = true;
+                }
+            }
+            if (open) {
+                hipEvent_t e = evs.make();
+                if (!e || hipEventRecord(e, st) != hipSuccess || hipStreamWaitEvent(side, e, 0) != hipSuccess)
+                    return fail(FF_ERR_HIP);
+                const int k1 = std::min(m, kpos + kc);
+                if (launch_r_slab(n, g0, g1, kpos, k1, Q, ldq, A, lda, R, ldr, d_info, side, side_wg) != hipSuccess)
+                    return fail(FF_ERR_HIP);
+                kpos = k1;
+            }
         }
         if (launch_qr_panel(m, wb, z, Bq, ldq, w.part, d_info, st) != hipSuccess) return fail(FF_ERR_HIP);
-        prev_z = z;
-        prev_w = wb;
         const int N = n - z - wb;
         if (N <= 0) break;
         double* Bm = Q + (int64_t)(z + wb) * ldq;
@@ -1114,8 +1130,16 @@ int qr_blocked(int m, int n, int ws, const double* A, int64_t lda, double* Q, in
         FF_TRY(launch_tn_gemm(n, n, m, Q, ldq, A, lda, R, ldr, true, w.tp, d_info, st));
         return 0;
     }
-    // the last block's rows on the caller's stream, then join and clear below the diagonal
-    if (r_rows(prev_z, prev_w, st, 0) != hipSuccess) return fail(FF_ERR_HIP);
+    // Every column of Q is final: the open group's remaining K range on the side
+    // stream (after its earlier chunks), the tiles not yet started on the caller's.
+    hipEvent_t ef = evs.make();
+    if (!ef || hipEventRecord(ef, st) != hipSuccess || hipStreamWaitEvent(side, ef, 0) != hipSuccess)
+        return fail(FF_ERR_HIP);
+    if (g1 > g0 && kpos < m &&
+        launch_r_slab(n, g0, g1, kpos, m, Q, ldq, A, lda, R, ldr, d_info, side, side_wg) != hipSuccess)
+        return fail(FF_ERR_HIP);
+    if (launch_r_slab(n, g1, r_slab_tiles_before(n, n), 0, m, Q, ldq, A, lda, R, ldr, d_info, st, 0) != hipSuccess)
+        return fail(FF_ERR_HIP);
     hipEvent_t ej = evs.make();
     if (!ej || hipEventRecord(ej, side) != hipSuccess || hipStreamWaitEvent(st, ej, 0) != hipSuccess)
         return fail(FF_ERR_HIP);

@@ -42,6 +42,17 @@ bool tn_gemm_fits(int64_t K, int64_t ldx, int64_t ldy);
 hipError_t launch_tn_gemm(int M, int N, int K, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* D,
                           int64_t ldd, bool upper, double* part, const int* info, hipStream_t st, int max_wg = 0);
 int qr_panel_workgroups(int64_t m);
+// R = Q^T A by slabs (qr.hip): tiles of r_slab_tile() x r_slab_tile() in the upper
+// triangle of R's tile grid, numbered row by row (tile row r holds the tiles
+// (r, r) ... (r, T - 1)); r_slab_tiles_before(n, rows) counts the tiles of the
+// first `rows` tile rows.  launch_r_slab forms tiles [t0, t1) over the K range
+// [k0, k1): stored when k0 == 0, added otherwise (the earlier K ranges of those
+// tiles must precede it in stream order); at most max_wg workgroups (0: one per
+// tile).  Entries below the diagonal are not written.
+int r_slab_tile();
+int64_t r_slab_tiles_before(int n, int rows);
+hipError_t launch_r_slab(int n, int64_t t0, int64_t t1, int k0, int k1, const double* Q, int64_t ldq, const double* A,
+                         int64_t lda, double* R, int64_t ldr, const int* info, hipStream_t st, int max_wg);
 hipError_t launch_zero_strict_lower(int n, double* D, int64_t ldd, const int* info, hipStream_t st);
 hipError_t launch_copy_int(const int* src, int* dst, hipStream_t st);
 

@@ -53,33 +53,20 @@ __device__ __forceinline__ void load2(rsrc_t r, int off, double& a, double& b) {
     b = __builtin_bit_cast(double, hi);
 }
 
-// D(i, j) = sum over k in this workgroup's K range of X(k, i) Y(k, j), for
-// i < M, j < N, where X(k, i) = X[k + i*ldx] and Y(k, j) = Y[k + j*ldy].
-// Workgroup b takes K part q = b % ks of tile b / ks and writes it to
-// D + q * dstride (ks = 1: D itself).  UPPER: tiles are the upper triangle of the
-// tile grid (column-major triangle order) and only entries with i <= j are
-// written.
-template <bool UPPER>
-__device__ __forceinline__ void tn_item(int b, int M, int N, int K, int kchunk, int ks, int tiles_m,
-                                        const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y,
-                                        int64_t ldy, double* __restrict__ D, int64_t ldd, int64_t dstride,
-                                        double (&As)[2][TG_BK][TG_P], double (&Bs)[2][TG_BK][TG_P]);
+// Tile (bi, bj) of D = X^T Y over the K range [kb, kb + kc):
+// D(i, j) (+)= sum over k of X(k, i) Y(k, j), for i < M, j < N, where
+// X(k, i) = X[k + i*ldx] and Y(k, j) = Y[k + j*ldy].  ADD: the sum is added to
+// D(i, j) instead of stored.  UPPER: only entries with i <= j are written.  Ends
+// with a barrier so the next tile may reuse the LDS buffers.
+template <bool UPPER, bool ADD>
+__device__ __forceinline__ void tn_tile(int bi, int bj, int kb, int kc, int M, int N, const double* __restrict__ X,
+                                        int64_t ldx, const double* __restrict__ Y, int64_t ldy,
+                                        double* __restrict__ D, int64_t ldd, double (&As)[2][TG_BK][TG_P],
+                                        double (&Bs)[2][TG_BK][TG_P]);
 
-template <bool UPPER>
-__global__ __launch_bounds__(TG_NT, 2)
-void tn_gemm_kernel(int M, int N, int K, int kchunk, int ks, int tiles_m, int nitems, const double* __restrict__ X,
-                    int64_t ldx, const double* __restrict__ Y, int64_t ldy, double* __restrict__ D, int64_t ldd,
-                    int64_t dstride, const int* __restrict__ info)
-{
-    if (info && *info != 0) return;
-    __shared__ double As[2][TG_BK][TG_P];   // As[k][i] = X(k0 + k, row0 + i)
-    __shared__ double Bs[2][TG_BK][TG_P];   // Bs[k][j] = Y(k0 + k, col0 + j)
-    for (int b = blockIdx.x; b < nitems; b += gridDim.x)
-        tn_item<UPPER>(b, M, N, K, kchunk, ks, tiles_m, X, ldx, Y, ldy, D, ldd, dstride, As, Bs);
-}
-
-// One work item of tn_gemm_kernel (K part b % ks of tile b / ks); ends with a
-// barrier so the next item may reuse the LDS buffers.
+// Workgroup item b of a K-split product: K part q = b % ks of tile b / ks,
+// written to D + q * dstride (ks = 1: D itself).  UPPER: tiles are the upper
+// triangle of the tile grid (column-major triangle order).
 template <bool UPPER>
 __device__ __forceinline__ void tn_item(int b, int M, int N, int K, int kchunk, int ks, int tiles_m,
                                         const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y,
@@ -96,7 +83,55 @@ __device__ __forceinline__ void tn_item(int b, int M, int N, int K, int kchunk, 
         bj = tile / tiles_m;
     }
     const int kb = q * kchunk;
-    const int kc = min(K, kb + kchunk) - kb;
+    tn_tile<UPPER, false>(bi, bj, kb, min(K, kb + kchunk) - kb, M, N, X, ldx, Y, ldy, D + (int64_t)q * dstride, ldd,
+                          As, Bs);
+}
+
+template <bool UPPER>
+__global__ __launch_bounds__(TG_NT, 2)
+void tn_gemm_kernel(int M, int N, int K, int kchunk, int ks, int tiles_m, int nitems, const double* __restrict__ X,
+                    int64_t ldx, const double* __restrict__ Y, int64_t ldy, double* __restrict__ D, int64_t ldd,
+                    int64_t dstride, const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    __shared__ double As[2][TG_BK][TG_P];   // As[k][i] = X(k0 + k, row0 + i)
+    __shared__ double Bs[2][TG_BK][TG_P];   // Bs[k][j] = Y(k0 + k, col0 + j)
+    for (int b = blockIdx.x; b < nitems; b += gridDim.x)
+        tn_item<UPPER>(b, M, N, K, kchunk, ks, tiles_m, X, ldx, Y, ldy, D, ldd, dstride, As, Bs);
+}
+
+// R's rows by slabs: tiles [t0, t1) of the upper triangle of R's tile grid in
+// row-major order (tile row r holds tiles (r, r), ..., (r, T - 1)), each over the
+// K range [kb, kb + kc) of R = Q^T A; ADD: added to R (a later K range of tiles
+// whose earlier ranges a previous launch stored).  Grid-stride over the tiles.
+template <bool ADD>
+__global__ __launch_bounds__(TG_NT, 2)
+void r_slab_kernel(int n, int T, int t0, int t1, int kb, int kc, const double* __restrict__ X, int64_t ldx,
+                   const double* __restrict__ Y, int64_t ldy, double* __restrict__ D, int64_t ldd,
+                   const int* __restrict__ info)
+{
+    if (info && *info != 0) return;
+    __shared__ double As[2][TG_BK][TG_P];
+    __shared__ double Bs[2][TG_BK][TG_P];
+    // tile row r starts at index r T - r (r - 1) / 2
+    auto start = [&](int64_t r) { return r * T - r * (r - 1) / 2; };
+    const double a = 2.0 * T + 1.0;
+    for (int t = t0 + (int)blockIdx.x; t < t1; t += (int)gridDim.x) {
+        int r = (int)((a - sqrt(fmax(a * a - 8.0 * t, 0.0))) * 0.5);
+        r = r < 0 ? 0 : (r > T - 1 ? T - 1 : r);
+        while (r > 0 && start(r) > t) --r;
+        while (r + 1 < T && start(r + 1) <= t) ++r;
+        const int bj = r + (int)(t - start(r));
+        tn_tile<true, ADD>(r, bj, kb, kc, n, n, X, ldx, Y, ldy, D, ldd, As, Bs);
+    }
+}
+
+template <bool UPPER, bool ADD>
+__device__ __forceinline__ void tn_tile(int bi, int bj, int kb, int kc, int M, int N, const double* __restrict__ X,
+                                        int64_t ldx, const double* __restrict__ Y, int64_t ldy,
+                                        double* __restrict__ D, int64_t ldd, double (&As)[2][TG_BK][TG_P],
+                                        double (&Bs)[2][TG_BK][TG_P])
+{
     const int row0 = bi * TG_T, col0 = bj * TG_T;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -192,7 +227,6 @@ __device__ __forceinline__ void tn_item(int b, int M, int N, int K, int kchunk, 
         }
     }
 
-    double* Dq = D + (int64_t)q * dstride;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -201,7 +235,10 @@ __device__ __forceinline__ void tn_item(int b, int M, int N, int K, int kchunk, 
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 const int i = row0 + 64 * wr + 16 * r4 + (lane & 15);
-                if (i < M && j < N && (!UPPER || i <= j)) Dq[i + (int64_t)j * ldd] = acc[cb][r4][r];
+                if (i < M && j < N && (!UPPER || i <= j)) {
+                    double* d = D + i + (int64_t)j * ldd;
+                    *d = ADD ? *d + acc[cb][r4][r] : acc[cb][r4][r];
+                }
             }
         }
     __syncthreads();
@@ -518,6 +555,30 @@ size_t tn_gemm_part_elems(int M, int N, int K, bool upper) {
 bool tn_gemm_fits(int64_t K, int64_t ldx, int64_t ldy) {
     const int64_t span = (int64_t)K + (int64_t)TG_T * std::max(ldx, ldy);
     return span * 8 < (int64_t)BUF_RECORDS - 64;
+}
+
+int r_slab_tile() { return TG_T; }
+
+int64_t r_slab_tiles_before(int n, int rows) {
+    const int64_t T = (n + TG_T - 1) / TG_T;
+    const int64_t r = std::min<int64_t>(std::max(rows, 0), T);
+    return r * T - r * (r - 1) / 2;
+}
+
+hipError_t launch_r_slab(int n, int64_t t0, int64_t t1, int k0, int k1, const double* Q, int64_t ldq, const double* A,
+                         int64_t lda, double* R, int64_t ldr, const int* info, hipStream_t st, int max_wg) {
+    if (t1 <= t0 || k1 <= k0) return hipSuccess;
+    if (t0 < 0 || t1 > r_slab_tiles_before(n, n) || k0 < 0) return hipErrorInvalidValue;
+    const int T = (n + TG_T - 1) / TG_T;
+    const int64_t nt = t1 - t0;
+    const int nwg = (int)std::min<int64_t>(nt, max_wg > 0 ? max_wg : nt);
+    if (k0 > 0)
+        hipLaunchKernelGGL(r_slab_kernel<true>, dim3(nwg), dim3(TG_NT), 0, st, n, T, (int)t0, (int)t1, k0, k1 - k0, Q,
+                           ldq, A, lda, R, ldr, info);
+    else
+        hipLaunchKernelGGL(r_slab_kernel<false>, dim3(nwg), dim3(TG_NT), 0, st, n, T, (int)t0, (int)t1, k0, k1 - k0,
+                           Q, ldq, A, lda, R, ldr, info);
+    return hipGetLastError();
 }
 
 hipError_t launch_tn_gemm(int M, int N, int K, const double* X, int64_t ldx, const double* Y, int64_t ldy, double* D,

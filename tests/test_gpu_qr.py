@@ -185,3 +185,21 @@ def test_qr_tall_matrix_uses_256_row_panel_slices():
     dr = np.max(np.abs(host(R) - np.triu(Ro))) / np.max(np.abs(Ro))
     print(f"m={m} n={n} (block {ws}): |dQ| = {dq:.2e}, |dR|/|R| = {dr:.2e}")
     assert dq <= 8 * n * kappa * U and dr <= 8 * n * kappa * U
+
+
+@pytest.mark.parametrize("m,n,s", [(16384, 512, 64), (8192, 1100, 96)])
+def test_qr_r_slabs_against_oracle(m, n, s):
+    # tall enough that R's tiles are formed over several K chunks beside the
+    # panels (stored, then added in K order) and the rest after the last panel
+    ws = ff.qr_step(m, n, s)
+    A = np.asfortranarray(np.random.default_rng(m + n).standard_normal((m, n)))
+    Q, R, info = ff.qr_factor(dev(A), s, sync=True)
+    assert info == 0
+    Qo, Ro, _, io = oracle.qr_alg3(A, ws)
+    assert io == 0
+    kappa = np.linalg.cond(A)
+    dq = np.max(np.abs(host(Q) - Qo))
+    dr = np.max(np.abs(host(R) - np.triu(Ro))) / np.max(np.abs(Ro))
+    print(f"m={m} n={n} (block {ws}): |dQ| = {dq:.2e}, |dR|/|R| = {dr:.2e}")
+    assert dq <= 8 * n * kappa * U and dr <= 8 * n * kappa * U
+    assert bool((torch.tril(R, -1) == 0).all())
