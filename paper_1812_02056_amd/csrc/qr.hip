@@ -23,6 +23,9 @@
 //                    and R = Q^T A), v_mfma_f64_16x16x4f64 on 128 x 128 tiles,
 //                    split over K into partial products that tn_reduce_kernel
 //                    sums in a fixed order.
+//   r_slab_kernel    R = Q^T A tile by tile over a K range, stored or added, so
+//                    that R's tiles can be formed on the CUs the panel leaves
+//                    idle as soon as the columns of Q they need are final.
 // The subtraction of (2) is the LU trailing-update kernel (update.hip).
 #include <algorithm>
 
