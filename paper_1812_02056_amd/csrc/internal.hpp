@@ -184,7 +184,7 @@ constexpr int TRI_F = 2;            // newest solved blocks the solving workgrou
 constexpr int TRI_GC = 4;           // right-hand sides per chain when several chains run
 constexpr int TRI_GROUPS = TRI_RC / TRI_GC;
 constexpr int TRI_CTL = 1 + 2 * TRI_GROUPS;
-constexpr int RESIDUAL_CB = 16;     // 64-column blocks per residual workgroup
+constexpr int RESIDUAL_SEG = 4;     // 64-row blocks per residual segment (side of a workgroup's tile square)
 inline int trisolve_nblk(int n) { return (n + TRI_TB - 1) / TRI_TB; }
 inline size_t trisolve_fac_elems(int n) { return (size_t)trisolve_nblk(n) * (2 + 2 * TRI_F) * TRI_TB * TRI_TB; }
 inline size_t trisolve_pub_elems(int n) { return (size_t)4 * trisolve_nblk(n) * TRI_TB * TRI_RC; }
@@ -197,11 +197,11 @@ struct TriWs {
 template <typename S>
 hipError_t trisolve_impl(int n, int nrhs, const S* L, int64_t ldl, S* X, int64_t ldx, const TriWs<S>& w,
                          bool make_fac, hipStream_t st);
-// part: residual_part_doubles(n) doubles of scratch.
-inline size_t residual_part_doubles(int n) {
-    const size_t nch = ((size_t)trisolve_nblk(n) + RESIDUAL_CB - 1) / RESIDUAL_CB;
-    return nch * (size_t)n * 16 + nch * (size_t)n;
-}
+// part: residual_part_doubles(n) doubles of scratch (two partial sums per
+// segment of RESIDUAL_SEG row blocks, for 16 right-hand sides and the absolute
+// row sums).
+inline int residual_segments(int n) { return (trisolve_nblk(n) + RESIDUAL_SEG - 1) / RESIDUAL_SEG; }
+inline size_t residual_part_doubles(int n) { return 17 * ((size_t)residual_segments(n) + 1) * (size_t)n; }
 hipError_t launch_residual_f64(int n, int nrhs, const double* A, int64_t lda, const double* X, int64_t ldx,
                                const double* B, int64_t ldb, double* R, int64_t ldr, double* rowsum, double* part,
                                hipStream_t st);

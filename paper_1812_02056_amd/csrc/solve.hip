@@ -42,7 +42,6 @@ constexpr int TB = TRI_TB;      // row block of the triangular solves
 constexpr int RHS_CHUNK = 16;   // right-hand sides per residual launch
 constexpr int RC = TRI_RC;      // right-hand sides per triangular sweep
 constexpr int NQ = RC / 4;      // columns a thread owns in the sweep's reductions (at most)
-constexpr int RCB = RESIDUAL_CB;// column blocks per residual workgroup
 constexpr int SPIN_LIMIT = 1 << 20;
 
 template <typename S>
@@ -526,101 +525,200 @@ hipError_t launch_sweep(int n, int nr, const S* L, int64_t ldl, const S* fac, S*
 }
 
 // Partial products of R = B - A X in binary64 with A symmetric, only tril(A)
-// read: workgroup (j, c) takes the 64-row block j against column blocks
-// i in [c*RCB, (c+1)*RCB): A[j-block, i-block] for i < j, A[i-block, j-block]^T
-// for i > j, the symmetric diagonal block for i = j.  part[c] receives A X of
-// those columns (n x nr, ld n) and, when rsum is non-null, the absolute row sums.
-__global__ __launch_bounds__(256)
-void residual_part_kernel(int n, int nr, const double* __restrict__ A, int64_t lda, const double* __restrict__ X,
-                          int64_t ldx, double* __restrict__ part, int64_t pstride, double* __restrict__ rsum)
+// read, each stored tile once.  The 64 x 64 tiles of the lower triangle are
+// grouped into segments of RS_G x RS_G tiles; workgroup (J, I), J >= I, takes
+// the tiles (j, i), j in row segment J, i in column segment I, j >= i, column
+// block by column block, and uses each twice:
+//   A(j, i) x_i     for row block j: summed over i (ascending) into
+//                    part[D, I] (rows of segment J);
+//   A(j, i)^T x_j   for row block i (j > i): summed over j (ascending) into
+//                    part[T, J] (rows of segment I).
+// The diagonal tile (i = i) is made symmetric in LDS and taken once, as a row
+// product.  With rsum the absolute row sums are formed the same way (column
+// RHS_CHUNK of each part).  residual_reduce_kernel adds, for a row of segment
+// K, part[D, I] for I = 0..K and then part[T, J] for J = K..nseg-1: a fixed
+// order, so results do not depend on scheduling.
+// Layout: part[D, I] holds rows [I SR, n) (SR = RS_G 64 rows), part[T, J] rows
+// [0, min(n, (J+1) SR)), each as RS_COLS columns of that length; all D parts
+// first, then all T parts: 17 (nseg + 1) n doubles in all.
+constexpr int RS_G = RESIDUAL_SEG;
+constexpr int RS_COLS = RHS_CHUNK + 1;
+constexpr int RS_SR = RS_G * TB;
+__device__ __forceinline__ int64_t rs_d_off(int n, int I) {
+    return (int64_t)RS_COLS * ((int64_t)I * n - (int64_t)RS_SR * I * (I - 1) / 2);
+}
+__device__ __forceinline__ int64_t rs_t_off(int n, int nseg, int J) {
+    return rs_d_off(n, nseg) + (int64_t)RS_COLS * RS_SR * ((int64_t)J * (J + 1) / 2);
+}
+static_assert(RHS_CHUNK == 16 && TB == 64, "one 16 x 16 MFMA tile per wave: 16 right-hand sides, 64-row blocks");
+
+__global__ __launch_bounds__(256, 2)
+void residual_part_kernel(int n, int nr, int nseg, const double* __restrict__ A, int64_t lda,
+                          const double* __restrict__ X, int64_t ldx, double* __restrict__ part, int with_rsum)
 {
-    __shared__ double tile[TB][TB + 1];
-    __shared__ double xv[TB][RHS_CHUNK];
-    const int j = blockIdx.x, c = blockIdx.y;
-    const int r0 = j * TB;
-    const int nbr = min(TB, n - r0);
+    __shared__ double T[TB][TB + 1];           // T[k][r] = A(j0 + r, i0 + k)
+    __shared__ double xi[TB][RHS_CHUNK];       // x of column block i
+    __shared__ double xj[TB][RHS_CHUNK];       // x of row block j
+    const int J = tri_row((int)blockIdx.x);
+    const int I = (int)blockIdx.x - J * (J + 1) / 2;
     const int nblk = (n + TB - 1) / TB;
-    const int tid = threadIdx.x, r = tid % TB, g = tid / TB;
-    const int ib = c * RCB, ie = min(nblk, ib + RCB);
-    double acc[RHS_CHUNK / 4];
-    double asum = 0.0;
-#pragma unroll
-    for (int q = 0; q < RHS_CHUNK / 4; ++q) acc[q] = 0.0;
+    const int jb0 = J * RS_G, jb1 = min(nblk, jb0 + RS_G);
+    const int ib0 = I * RS_G, ib1 = min(nblk, ib0 + RS_G);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // part[D, I] (rows from I SR) and part[T, J] (rows from 0), column stride ldD / ldT
+    const int64_t ldD = n - (int64_t)I * RS_SR, ldT = min((int64_t)n, (int64_t)(J + 1) * RS_SR);
+    double* partD = part + rs_d_off(n, I) - (int64_t)I * RS_SR;
+    double* partT = part + rs_t_off(n, nseg, J);
     constexpr int NE = TB * TB / 256;
-    double tv[NE];
-    auto load_tile = [&](int i) {
-        const int i0 = i * TB, nbi = min(TB, n - i0);
+    // wave wv owns rows 16 wv .. 16 wv + 15 of a row block (and columns
+    // 16 wv .. of a column block) for all 16 right-hand sides; wave 0 also the
+    // row sums (lane = row)
+    d4_t yD[RS_G];
+    double rD[RS_G];
+#pragma unroll
+    for (int u = 0; u < RS_G; ++u) {
+        rD[u] = 0.0;
+        yD[u] = zero_vec<d4_t>();
+    }
+    double tv[NE], xv[4];
+    auto load = [&](int j, int i) {
+        const int i0 = i * TB, j0 = j * TB;
+        const int nbi = min(TB, n - i0), nbj = min(TB, n - j0);
 #pragma unroll
         for (int u = 0; u < NE; ++u) {
             const int e = tid + 256 * u;
-            const int a = e % TB, b = e / TB;
-            bool in;
-            int64_t off;
-            if (i < j) { in = a < nbr && b < nbi; off = (int64_t)(r0 + a) + (int64_t)(i0 + b) * lda; }
-            else if (i > j) { in = a < nbi && b < nbr; off = (int64_t)(i0 + a) + (int64_t)(r0 + b) * lda; }
-            else { in = a < nbr && b < nbr && a >= b; off = (int64_t)(r0 + a) + (int64_t)(r0 + b) * lda; }
-            const double v = A[in ? off : 0];
+            const int a = e % TB, bcol = e / TB;    // row a of block j, column bcol of block i
+            const bool in = a < nbj && bcol < nbi && (j != i || a >= bcol);
+            const double v = A[in ? (int64_t)(j0 + a) + (int64_t)(i0 + bcol) * lda : 0];
             tv[u] = in ? v : 0.0;
         }
-    };
-    if (ib < ie) load_tile(ib);
-    for (int i = ib; i < ie; ++i) {
-        const int i0 = i * TB, nbi = min(TB, n - i0);
 #pragma unroll
-        for (int u = 0; u < NE; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int e = tid + 256 * u;
-            tile[e % TB][e / TB] = tv[u];
+            const int a = e % TB, c = e / TB;
+            xv[u] = (a < nbj && c < nr) ? X[(int64_t)(j0 + a) + (int64_t)c * ldx] : 0.0;
         }
+    };
+    for (int i = ib0; i < ib1; ++i) {
+        const int i0 = i * TB, nbi = min(TB, n - i0);
+        const int jst = J == I ? i : jb0;
+        __syncthreads();   // the previous column block is done with xi
         for (int e = tid; e < TB * RHS_CHUNK; e += 256) {
-            const int a = e % TB, cc = e / TB;
-            xv[a][cc] = (a < nbi && cc < nr) ? X[(int64_t)(i0 + a) + (int64_t)cc * ldx] : 0.0;
+            const int a = e % TB, c = e / TB;
+            xi[a][c] = (a < nbi && c < nr) ? X[(int64_t)(i0 + a) + (int64_t)c * ldx] : 0.0;
         }
-        if (i + 1 < ie) load_tile(i + 1);
-        __syncthreads();
+        d4_t yT = zero_vec<d4_t>();
+        double rT = 0.0;
+        if (jst < jb1) load(jst, i);
+        for (int j = jst; j < jb1; ++j) {
 #pragma unroll
-        for (int q = 0; q < RHS_CHUNK / 4; ++q) {
-            const int cc = g + 4 * q;
-            if (cc < nr) {
-                double sum = 0.0;
-                if (i < j) { for (int k = 0; k < TB; ++k) sum += tile[r][k] * xv[k][cc]; }
-                else if (i > j) { for (int k = 0; k < TB; ++k) sum += tile[k][r] * xv[k][cc]; }
-                else { for (int k = 0; k < TB; ++k) sum += (r >= k ? tile[r][k] : tile[k][r]) * xv[k][cc]; }
-                acc[q] += sum;
+            for (int u = 0; u < NE; ++u) {
+                const int e = tid + 256 * u;
+                T[e / TB][e % TB] = tv[u];
             }
-        }
-        if (rsum && g == 0) {
-            double sum = 0.0;
-            if (i < j) { for (int k = 0; k < TB; ++k) sum += fabs(tile[r][k]); }
-            else if (i > j) { for (int k = 0; k < TB; ++k) sum += fabs(tile[k][r]); }
-            else { for (int k = 0; k < TB; ++k) sum += fabs(r >= k ? tile[r][k] : tile[k][r]); }
-            asum += sum;
-        }
-        __syncthreads();
-    }
-    double* pc = part + (int64_t)c * pstride;
 #pragma unroll
-    for (int q = 0; q < RHS_CHUNK / 4; ++q) {
-        const int cc = g + 4 * q;
-        if (cc < nr && r < nbr) pc[(int64_t)(r0 + r) + (int64_t)cc * n] = acc[q];
+            for (int u = 0; u < 4; ++u) {
+                const int e = tid + 256 * u;
+                xj[e % TB][e / TB] = xv[u];
+            }
+            if (j + 1 < jb1) load(j + 1, i);
+            __syncthreads();
+            if (j == i) {
+                // the diagonal tile: fill the upper part from the lower
+                for (int e = tid; e < TB * TB; e += 256) {
+                    const int r = e % TB, k = e / TB;
+                    if (r < k) T[k][r] = T[r][k];
+                }
+                __syncthreads();
+            }
+            const int jj = j - jb0;
+            // row products of block j, rows 16 wv .. 16 wv + 15 of this wave, as
+            // the transposed MFMA tile: D'[c][r] = sum_k x_i(k, c) A(r, k), lane
+            // r + 16 (c % 4) holding column c = 4 g + lane / 16 in register g
+            {
+                d4_t acc = zero_vec<d4_t>();
+#pragma unroll 4
+                for (int k = 0; k < TB; k += 4) {
+                    const int kk = k + (lane >> 4);
+                    acc = mfma_f64(xi[kk][lane & 15], T[kk][16 * wv + (lane & 15)], acc);
+                }
+#pragma unroll
+                for (int u = 0; u < RS_G; ++u)
+                    if (u == jj) yD[u] += acc;
+                if (with_rsum && wv == 0) {
+                    double ra = 0.0;
+                    for (int k = 0; k < TB; ++k) ra += fabs(T[k][lane]);
+#pragma unroll
+                    for (int u = 0; u < RS_G; ++u)
+                        if (u == jj) rD[u] += ra;
+                }
+            }
+            // column products of block i (j > i), columns 16 wv .. 16 wv + 15 of
+            // the tile: D'[c][k] = sum_r x_j(r, c) A(r, k)
+            if (j > i) {
+                d4_t acc = zero_vec<d4_t>();
+#pragma unroll 4
+                for (int r = 0; r < TB; r += 4) {
+                    const int rr = r + (lane >> 4);
+                    acc = mfma_f64(xj[rr][lane & 15], T[16 * wv + (lane & 15)][rr], acc);
+                }
+                yT += acc;
+                if (with_rsum && wv == 0) {
+                    double ra = 0.0;
+                    for (int r = 0; r < TB; ++r) ra += fabs(T[lane][r]);
+                    rT += ra;
+                }
+            }
+            __syncthreads();   // T and xj are free
+        }
+        // column products of block i from this row segment
+        {
+            const int k = 16 * wv + (lane & 15);
+            if (k < nbi) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int c = 4 * g + (lane >> 4);
+                    if (c < nr) partT[(int64_t)c * ldT + i0 + k] = yT[g];
+                }
+            }
+            if (with_rsum && wv == 0 && lane < nbi) partT[(int64_t)RHS_CHUNK * ldT + i0 + lane] = rT;
+        }
     }
-    if (rsum && g == 0 && r < nbr) rsum[(int64_t)c * n + r0 + r] = asum;
+    // row products of the row segment from this column segment
+#pragma unroll
+    for (int u = 0; u < RS_G; ++u) {
+        const int j0 = (jb0 + u) * TB;
+        if (jb0 + u < jb1) {
+            const int r = j0 + 16 * wv + (lane & 15);
+            if (r < n) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int c = 4 * g + (lane >> 4);
+                    if (c < nr) partD[(int64_t)c * ldD + r] = yD[u][g];
+                }
+            }
+            if (with_rsum && wv == 0 && j0 + lane < n) partD[(int64_t)RHS_CHUNK * ldD + j0 + lane] = rD[u];
+        }
+    }
 }
 
-// R = B - sum_c part[c] (c ascending), rowsum = sum_c rsum[c].
-__global__ void residual_reduce_kernel(int n, int nr, int nch, const double* __restrict__ part, int64_t pstride,
+// R = B - (sum over I <= K of part[D, I] + sum over J >= K of part[T, J]) for a
+// row of segment K, in that order; rowsum likewise from the row-sum column.
+__global__ void residual_reduce_kernel(int n, int nr, int nseg, const double* __restrict__ part,
                                        const double* __restrict__ B, int64_t ldb, double* __restrict__ R, int64_t ldr,
-                                       const double* __restrict__ rsum, double* __restrict__ rowsum)
+                                       double* __restrict__ rowsum)
 {
     const int cc = blockIdx.y;
+    const int col = cc < nr ? cc : RHS_CHUNK;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int K = i / RS_SR;
         double s = 0.0;
-        for (int c = 0; c < nch; ++c) s += part[(int64_t)c * pstride + i + (int64_t)cc * n];
-        R[i + (int64_t)cc * ldr] = B[i + (int64_t)cc * ldb] - s;
-        if (rowsum && cc == 0) {
-            double t = 0.0;
-            for (int c = 0; c < nch; ++c) t += rsum[(int64_t)c * n + i];
-            rowsum[i] = t;
-        }
+        for (int I = 0; I <= K; ++I)
+            s += part[rs_d_off(n, I) + (int64_t)col * (n - (int64_t)I * RS_SR) + (i - (int64_t)I * RS_SR)];
+        for (int Jx = K; Jx < nseg; ++Jx)
+            s += part[rs_t_off(n, nseg, Jx) + (int64_t)col * min((int64_t)n, (int64_t)(Jx + 1) * RS_SR) + i];
+        if (cc < nr) R[i + (int64_t)cc * ldr] = B[i + (int64_t)cc * ldb] - s;
+        else rowsum[i] = s;
     }
 }
 
@@ -632,47 +730,62 @@ __global__ void axpy_kernel(int n, const S* __restrict__ D, int64_t ldd, double*
 }
 
 // out[0] = max|D|, out[1] = max|X|, out[2] = max_i rowsum[i] (if rowsum),
-// out[3 + 3c + {0,1,2}] = max|R[:,c]|, max|X[:,c]|, max|B[:,c]|.
+// out[3 + 3c + {0,1,2}] = max|R[:,c]|, max|X[:,c]|, max|B[:,c]| (NaN entries
+// count as 0).  Workgroup (x, y) takes rows [x NR_ROWS, (x+1) NR_ROWS) of column
+// y (y = nrhs: the row sums) and folds its maxima into out with atomic maxima of
+// the bit patterns, which order like the values for non-negative doubles; out
+// must hold zeros first.  A maximum does not depend on the order of its terms.
+constexpr int NR_ROWS = 2048;
+
+__device__ __forceinline__ double abs_or_zero(double v) {
+    const double a = fabs(v);
+    return a == a ? a : 0.0;
+}
+__device__ __forceinline__ double block_max(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
+    atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
 __global__ __launch_bounds__(256)
 void norms_kernel(int n, int nrhs, const double* rowsum, const double* X, int64_t ldx, const double* D,
                   int64_t ldd, const double* R, int64_t ldr, const double* B, int64_t ldb, double* out)
 {
-    __shared__ double red[256];
-    const int tid = threadIdx.x;
-    auto reduce = [&](double v) -> double {
-        red[tid] = v;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-            __syncthreads();
-        }
-        const double res = red[0];
-        __syncthreads();
-        return res;
-    };
-    double md = 0.0, mx = 0.0, ma = 0.0;
-    for (int c = 0; c < nrhs; ++c)
-        for (int i = tid; i < n; i += 256) {
-            if (D) md = fmax(md, fabs(D[i + (int64_t)c * ldd]));
-            mx = fmax(mx, fabs(X[i + (int64_t)c * ldx]));
-        }
-    if (rowsum)
-        for (int i = tid; i < n; i += 256) ma = fmax(ma, rowsum[i]);
-    md = reduce(md);
-    mx = reduce(mx);
-    ma = reduce(ma);
-    if (tid == 0) { out[0] = md; out[1] = mx; out[2] = ma; }
-    for (int c = 0; c < nrhs; ++c) {
-        double vr = 0.0, vx = 0.0, vb = 0.0;
-        for (int i = tid; i < n; i += 256) {
-            if (R) vr = fmax(vr, fabs(R[i + (int64_t)c * ldr]));
-            vx = fmax(vx, fabs(X[i + (int64_t)c * ldx]));
-            if (B) vb = fmax(vb, fabs(B[i + (int64_t)c * ldb]));
-        }
-        vr = reduce(vr);
-        vx = reduce(vx);
-        vb = reduce(vb);
-        if (tid == 0) { out[3 + 3 * c] = vr; out[4 + 3 * c] = vx; out[5 + 3 * c] = vb; }
+    __shared__ double red[4];
+    const int c = blockIdx.y;
+    const int i0 = blockIdx.x * NR_ROWS, i1 = min(n, i0 + NR_ROWS);
+    if (c == nrhs) {
+        double ma = 0.0;
+        if (rowsum)
+            for (int i = i0 + threadIdx.x; i < i1; i += 256) ma = fmax(ma, abs_or_zero(rowsum[i]));
+        ma = block_max(ma, red);
+        if (threadIdx.x == 0) atomic_max_nonneg(out + 2, ma);
+        return;
+    }
+    double vd = 0.0, vr = 0.0, vx = 0.0, vb = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+        if (D) vd = fmax(vd, abs_or_zero(D[i + (int64_t)c * ldd]));
+        if (R) vr = fmax(vr, abs_or_zero(R[i + (int64_t)c * ldr]));
+        vx = fmax(vx, abs_or_zero(X[i + (int64_t)c * ldx]));
+        if (B) vb = fmax(vb, abs_or_zero(B[i + (int64_t)c * ldb]));
+    }
+    vd = block_max(vd, red);
+    vr = block_max(vr, red);
+    vx = block_max(vx, red);
+    vb = block_max(vb, red);
+    if (threadIdx.x == 0) {
+        atomic_max_nonneg(out + 0, vd);
+        atomic_max_nonneg(out + 1, vx);
+        atomic_max_nonneg(out + 3 + 3 * c, vr);
+        atomic_max_nonneg(out + 4 + 3 * c, vx);
+        atomic_max_nonneg(out + 5 + 3 * c, vb);
     }
 }
 
@@ -869,18 +982,16 @@ hipError_t launch_residual_f64(int n, int nrhs, const double* A, int64_t lda, co
                                const double* B, int64_t ldb, double* R, int64_t ldr, double* rowsum, double* part,
                                hipStream_t st) {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
-    const int nblk = (n + TB - 1) / TB;
-    const int nch = (nblk + RCB - 1) / RCB;
-    const int64_t pstride = (int64_t)n * RHS_CHUNK;
-    double* rsum = part + (int64_t)nch * pstride;
+    const int nseg = residual_segments(n);
+    const int nwg = nseg * (nseg + 1) / 2;
     for (int c0 = 0; c0 < nrhs; c0 += RHS_CHUNK) {
         const int nr = std::min(RHS_CHUNK, nrhs - c0);
-        double* rs = (c0 == 0 && rowsum) ? rsum : nullptr;
-        hipLaunchKernelGGL(residual_part_kernel, dim3(nblk, nch), dim3(256), 0, st, n, nr, A, lda,
-                           X + (int64_t)c0 * ldx, ldx, part, pstride, rs);
-        hipLaunchKernelGGL(residual_reduce_kernel, dim3(std::min(1024, (n + 255) / 256), nr), dim3(256), 0, st, n, nr,
-                           nch, part, pstride, B + (int64_t)c0 * ldb, ldb, R + (int64_t)c0 * ldr, ldr, rs,
-                           c0 == 0 ? rowsum : nullptr);
+        const bool rs = c0 == 0 && rowsum;
+        hipLaunchKernelGGL(residual_part_kernel, dim3(nwg), dim3(256), 0, st, n, nr, nseg, A, lda,
+                           X + (int64_t)c0 * ldx, ldx, part, rs ? 1 : 0);
+        hipLaunchKernelGGL(residual_reduce_kernel, dim3(std::min(1024, (n + 255) / 256), nr + (rs ? 1 : 0)), dim3(256),
+                           0, st, n, nr, nseg, part, B + (int64_t)c0 * ldb, ldb, R + (int64_t)c0 * ldr, ldr,
+                           rs ? rowsum : nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -897,7 +1008,11 @@ hipError_t launch_axpy_update(int n, int nrhs, const S* D, int64_t ldd, double* 
 hipError_t launch_norms(int n, int nrhs, const double* rowsum, const double* X, int64_t ldx, const double* D,
                         int64_t ldd, const double* R, int64_t ldr, const double* B, int64_t ldb, double* out,
                         hipStream_t st) {
-    hipLaunchKernelGGL(norms_kernel, dim3(1), dim3(256), 0, st, n, nrhs, rowsum, X, ldx, D, ldd, R, ldr, B, ldb, out);
+    const int nout = 3 + 3 * nrhs;
+    hipLaunchKernelGGL(fill_double_kernel, dim3((nout + 255) / 256), dim3(256), 0, st, nout, out, 0.0);
+    if (n <= 0 || nrhs <= 0) return hipGetLastError();
+    hipLaunchKernelGGL(norms_kernel, dim3((n + NR_ROWS - 1) / NR_ROWS, nrhs + 1), dim3(256), 0, st, n, nrhs, rowsum,
+                       X, ldx, D, ldd, R, ldr, B, ldb, out);
     return hipGetLastError();
 }
 
