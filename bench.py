@@ -60,8 +60,9 @@ def parse():
     p.add_argument("--no-extras", action="store_true")
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision table")
     p.add_argument("--mixed-only", action="store_true", help="only the mixed-precision table")
-    p.add_argument("--leg", choices=("lowprec", "trisolve", "qr"), default=None,
-                   help="only one leg, for profiling: the binary32 / bfloat16 factorisations, or the triangular solves")
+    p.add_argument("--leg", choices=("lowprec", "trisolve", "qr", "solve"), default=None,
+                   help="only one leg, for profiling: the binary32 / bfloat16 factorisations, the triangular "
+                        "solves, QR, or one mixed-precision cell (lambda = 1e-6, 1 and 16 right-hand sides)")
     p.add_argument("--serving-only", action="store_true", help="only the serving leg (many independent solves)")
     p.add_argument("--serving-requests", type=int, default=10000)
     p.add_argument("--copy-calibration", action="store_true",
@@ -107,6 +108,8 @@ def main():
             res = run_low_precision_factor(ff, torch, dev, n, A0)
         elif args.leg == "qr":
             res = run_qr(ff, torch, wl, dev, n=n)
+        elif args.leg == "solve":
+            res = run_solve_cell(ff, torch, wl, dev, n)
         else:
             res = run_trisolve(ff, torch, dev, n)
         log(f"[bench] {args.leg}: {res}")
@@ -711,6 +714,31 @@ def run_qr(ff, torch, wl, dev, n=16384, steps=(64, 96, 112, 128, 142), reps=3, p
         res[f"n{m}_s{s}"] = {"block": ff.qr_step(m, m, s), "ms": round(dt * 1e3, 3), "info": int(info.item()),
                              "tflops_4n3_3": round(4 * m ** 3 / 3 / dt / 1e12, 3)}
         del A, Q, R, ws
+    return res
+
+
+def run_solve_cell(ff, torch, wl, dev, n, lam=1e-6, reps=3):
+    """One cell of the mixed-precision table, for profiling the solve path: binary64
+    and binary32 + refinement (escalation allowed) at lambda = 1e-6 with 1 and 16
+    right-hand sides, median of reps solves after one untimed solve."""
+    A = wl.spd_scaled_device(n, seed=0, lam=lam, device=dev)          # symmetric
+    res = {}
+    for nrhs in (1, 16):
+        B = wl.rhs_device(n, nrhs, seed=1000, device=dev).t()
+        for dtype in ("f64", "f32"):
+            s = MIXED_STEP.get(n, MIXED_STEP[16384])[dtype]
+            W = ff.colmajor_empty(n, n, torch.float64 if dtype == "f64" else torch.float32, dev)
+            ws = torch.empty(ff.solve_workspace_size(n, s, nrhs, dtype, escalate=dtype != "f64"), dtype=torch.uint8,
+                             device=dev)
+            X = ff.colmajor_empty(n, nrhs, torch.float64, dev)
+
+            def solve():
+                return ff.chol_solve(A.t(), B, s, dtype=dtype, W=W, X=X, ws=ws, tol=1e-12,
+                                     max_iter=0 if dtype == "f64" else 50, escalate=dtype != "f64")[2]
+            dt, info = median_time(solve, reps, torch)
+            res[f"{dtype}_nrhs{nrhs}"] = {"ms": round(dt * 1e3, 3), "s": s, "iters": info["total_iters"],
+                                          "info": info["info"], "backward_err": info["backward_err"]}
+            del W, ws, X
     return res
 
 
