@@ -194,7 +194,11 @@ int lu_nopiv_factor(int64_t n, int64_t s, void *A, int64_t lda, int dtype, unsig
  *   stream hipStream_t; the call is asynchronous.
  * The Gram-Schmidt kernel keeps one workgroup per compute unit resident and
  * synchronises them through device memory; it must not share the device with
- * work that holds compute units indefinitely.
+ * work that holds compute units indefinitely.  While it runs, tiles of R whose
+ * columns of Q are final are formed (over chunks of rows, added in order) on a
+ * second, library-owned stream of default priority, on the compute units it
+ * leaves idle; events order that stream, and the call still returns with all of
+ * its work ordered before later work on `stream`.
  */
 size_t ff_qr_workspace_size(int64_t m, int64_t n, int64_t s, int dtype, unsigned flags);
 int ff_qr_step(int64_t m, int64_t n, int64_t s);
