@@ -533,12 +533,13 @@ hipError_t launch_sweep(int n, int nr, const S* L, int64_t ldl, const S* fac, S*
 //                    part[D, I] (rows of segment J);
 //   A(j, i)^T x_j   for row block i (j > i): summed over j (ascending) into
 //                    part[T, J] (rows of segment I).
-// The diagonal tile (i = i) is made symmetric in LDS and taken once, as a row
-// product.  With rsum the absolute row sums are formed the same way (column
+// A diagonal tile (j = i) is made symmetric in LDS and taken once, as a row
+// product.  The products run on v_mfma_f64_16x16x4f64, one 16-row slice of the
+// tile per wave over all 16 right-hand sides.  With rsum the absolute row sums are formed the same way (column
 // RHS_CHUNK of each part).  residual_reduce_kernel adds, for a row of segment
 // K, part[D, I] for I = 0..K and then part[T, J] for J = K..nseg-1: a fixed
 // order, so results do not depend on scheduling.
-// Layout: part[D, I] holds rows [I SR, n) (SR = RS_G 64 rows), part[T, J] rows
+// Layout: part[D, I] holds rows [I SR, n) (SR = 64 RS_G rows), part[T, J] rows
 // [0, min(n, (J+1) SR)), each as RS_COLS columns of that length; all D parts
 // first, then all T parts: 17 (nseg + 1) n doubles in all.
 constexpr int RS_G = RESIDUAL_SEG;
