@@ -176,12 +176,14 @@ hipError_t launch_convert_from_f64(int n, int nrhs, const double* B, int64_t ldb
 //         sweep expired; never cleared here, callers clear it once per call),
 //         [1, 1 + TRI_GROUPS) and [1 + TRI_GROUPS, 1 + 2 TRI_GROUPS) the two
 //         sweeps' workgroup tickets, one per group of right-hand sides.
-// Up to 4 right-hand sides are solved by one chain of workgroups; 5..16 by
-// ceil(nr / 4) independent chains of 4 in the same launch.
+// One right-hand side is solved by one chain of workgroups; 2..16 by
+// independent chains of 2 columns in the same launch (binary64 with more than
+// 8 right-hand sides: chains of 4, fewer chains re-reading L).
 constexpr int TRI_TB = 64;          // row block
 constexpr int TRI_RC = 16;          // right-hand sides per sweep
 constexpr int TRI_F = 2;            // newest solved blocks the solving workgroup folds itself
-constexpr int TRI_GC = 4;           // right-hand sides per chain when several chains run
+constexpr int TRI_GC = 2;           // right-hand sides per chain when several chains run (narrowest)
+constexpr int TRI_GC_WIDE = 4;      // the same for binary64 with more than 8 right-hand sides
 constexpr int TRI_GROUPS = TRI_RC / TRI_GC;
 constexpr int TRI_CTL = 1 + 2 * TRI_GROUPS;
 constexpr int RESIDUAL_SEG = 4;     // 64-row blocks per residual segment (side of a workgroup's tile square)

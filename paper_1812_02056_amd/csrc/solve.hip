@@ -513,13 +513,20 @@ hipError_t launch_sweep(int n, int nr, const S* L, int64_t ldl, const S* fac, S*
                         int* ticket, hipStream_t st) {
     const int nblk = (n + TB - 1) / TB;
     const int per_chain = 1 + std::max(0, nblk - TRI_F - 1);
+    // chain width measured at n = 16384 (ms per solve pair, binary32 / binary64):
+    // 2 columns 1.32 / 2.54 (4 rhs), 1.65 / 3.09 (8), 2.12 / 4.96 (16); 4 columns
+    // 1.67 / 2.86, 1.95 / 3.11, 2.35 / 3.69; 1 and 8 columns slower throughout
     if (nr == 1) {
         hipLaunchKernelGGL((trisolve_kernel<S, TRANS, 1>), dim3(per_chain), dim3(256), 0, st, n, nr, 1, L, ldl, fac,
                            X, ldx, pub, err, ticket);
-    } else {
+    } else if (sizeof(S) == 4 || nr <= 8) {
         const int groups = (nr + TRI_GC - 1) / TRI_GC;
         hipLaunchKernelGGL((trisolve_kernel<S, TRANS, TRI_GC>), dim3(per_chain * groups), dim3(256), 0, st, n, nr,
                            groups, L, ldl, fac, X, ldx, pub, err, ticket);
+    } else {
+        const int groups = (nr + TRI_GC_WIDE - 1) / TRI_GC_WIDE;
+        hipLaunchKernelGGL((trisolve_kernel<S, TRANS, TRI_GC_WIDE>), dim3(per_chain * groups), dim3(256), 0, st, n,
+                           nr, groups, L, ldl, fac, X, ldx, pub, err, ticket);
     }
     return hipGetLastError();
 }
