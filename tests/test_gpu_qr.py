@@ -203,3 +203,20 @@ def test_qr_r_slabs_against_oracle(m, n, s):
     print(f"m={m} n={n} (block {ws}): |dQ| = {dq:.2e}, |dR|/|R| = {dr:.2e}")
     assert dq <= 8 * n * kappa * U and dr <= 8 * n * kappa * U
     assert bool((torch.tril(R, -1) == 0).all())
+
+
+def test_qr_r_slabs_with_padded_leading_dimensions():
+    # the slab kernel addresses Q, A and R through their own leading dimensions
+    m, n, s = 8192, 700, 96
+    ws = ff.qr_step(m, n, s)
+    A = np.asfortranarray(np.random.default_rng(31).standard_normal((m, n)))
+    Ad = dev(A, ld=m + 8)
+    Qd = ff.colmajor_empty(m, n, torch.float64, DEV, ld=m + 24)
+    Rd = ff.colmajor_empty(n, n, torch.float64, DEV, ld=n + 40)
+    Q, R, info = ff.qr_factor(Ad, s, Q=Qd, R=Rd, sync=True)
+    assert info == 0
+    Qo, Ro, _, io = oracle.qr_alg3(A, ws)
+    assert io == 0
+    kappa = np.linalg.cond(A)
+    assert np.max(np.abs(host(Q) - Qo)) <= 8 * n * kappa * U
+    assert np.max(np.abs(host(R) - np.triu(Ro))) / np.max(np.abs(Ro)) <= 8 * n * kappa * U

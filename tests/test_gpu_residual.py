@@ -50,3 +50,17 @@ def test_refined_solve_across_residual_layout(n, nrhs):
           f"(library {info['backward_err']:.1e})")
     assert fwd <= 1e-12
     assert bwd <= 1e-14 and info["backward_err"] <= 1e-14
+
+
+@pytest.mark.parametrize("n,lda", [(257, 300), (700, 768), (1030, 1031)])
+def test_refined_solve_with_padded_leading_dimension(n, lda):
+    A = wl.spd_scaled(n, seed=n + 21, lam=1.0)
+    B = wl.rhs(n, 5, seed=n + 22)
+    Lo, _ = oracle.chol(A)
+    Xo = oracle.chol_solve(Lo, B)
+    X, _, info = ff.chol_solve(ff.to_device(A, DEV, ld=lda), ff.to_device(B, DEV, ld=n + 3), 64, dtype="f32",
+                               tol=1e-13, max_iter=30)
+    Xh = X.cpu().numpy()
+    assert info["info"] == 0 and info["converged"] == 1
+    assert float(np.max(np.abs(Xh - Xo)) / np.max(np.abs(Xo))) <= 1e-12
+    assert host_backward_error(A, Xh, B) <= 1e-14
