@@ -107,3 +107,21 @@ def test_gmres_ir_zero_rhs_column():
     Lo, _ = oracle.chol(A)
     assert oracle.fwd_x(Xh[:, :1], oracle.chol_solve(Lo, B[:, :1])) <= 1e-12
     assert info["info"] == 0
+
+
+@pytest.mark.parametrize("n,nrhs", [(65, 3), (257, 17), (1030, 16)])
+def test_gmres_ir_ragged_sizes(n, nrhs):
+    """Ragged sizes and right-hand-side counts past one 16-column pass: the
+    Krylov matrix products run through the residual's tile layout."""
+    A = wl.spd_scaled(n, seed=n + 75, lam=1e-3)
+    B = wl.rhs(n, nrhs, seed=n + 76)
+    Lo, info_o = oracle.chol(A)
+    assert info_o == 0
+    Xo = oracle.chol_solve(Lo, B)
+    X, _, info = ff.chol_solve(dev(A), dev(B), 64, dtype="f32", tol=1e-12, max_iter=20, gmres=True)
+    Xh = host(X)
+    assert info["info"] == 0 and info["converged"] == 1 and info["krylov_iters"] > 0
+    assert oracle.bwd_x(A, Xh, B) <= 1e-12
+    # kappa ~ 4e3: a backward error of 1e-12 bounds the forward error by about
+    # kappa * 1e-12 = 4e-9; binary64 itself lands near kappa * u ~ 1e-12
+    assert oracle.fwd_x(Xh, Xo) <= 1e-10
