@@ -15,12 +15,15 @@ Also reported on the same JSON line: the dominant trailing-update kernel of the
 timed steps against its roofline (binary64 MFMA peak; its launches are timed
 with HIP events on the stream they run on), the CPU oracle's rate on the same
 matrix, the fixed-step schedule, the one-level Strassen update, LU without
-pivoting (2n^3/3), the binary32 and bfloat16-operand factorisations with their
-update kernels, the triangular solves, the mixed-precision table (n in {16384,
-32768}, lambda in {1, 1e-3, 1e-6}, 1 and 16 right-hand sides, every result's
-error stated) and the serving workload.
+pivoting (2n^3/3) with one and two Strassen levels, the binary32 and
+bfloat16-operand factorisations with their update kernels, the triangular
+solves, QR (Sec. 2, Algorithm 3) over its step sweep and at the paper's sizes,
+the mixed-precision table (n in {16384, 32768}, lambda in {1, 1e-3, 1e-6}, 1 and
+16 right-hand sides, every result's error stated) and the serving workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+    python bench.py --leg lowprec|trisolve|qr|solve     # one leg alone, for profiling
+    python bench.py --copy-calibration                  # 1 GiB copies for HBM counter scaling
 """
 from __future__ import annotations
 
