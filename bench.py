@@ -66,6 +66,8 @@ def parse():
     p.add_argument("--leg", choices=("lowprec", "trisolve", "qr", "solve"), default=None,
                    help="only one leg, for profiling: the binary32 / bfloat16 factorisations, the triangular "
                         "solves, QR, or one mixed-precision cell (lambda = 1e-6, 1 and 16 right-hand sides)")
+    p.add_argument("--qr-steps", type=str, default="64,96,112,128,142",
+                   help="step sizes of the QR leg's sweep at n = 16384")
     p.add_argument("--serving-only", action="store_true", help="only the serving leg (many independent solves)")
     p.add_argument("--serving-requests", type=int, default=10000)
     p.add_argument("--copy-calibration", action="store_true",
@@ -110,7 +112,7 @@ def main():
             A0 = wl.spd_scaled_device(n, seed=0, lam=1.0, device=dev)
             res = run_low_precision_factor(ff, torch, dev, n, A0)
         elif args.leg == "qr":
-            res = run_qr(ff, torch, wl, dev, n=n)
+            res = run_qr(ff, torch, wl, dev, n=n, steps=tuple(int(v) for v in args.qr_steps.split(",")))
         elif args.leg == "solve":
             res = run_solve_cell(ff, torch, wl, dev, n)
         else:
@@ -685,6 +687,7 @@ def run_qr(ff, torch, wl, dev, n=16384, steps=(64, 96, 112, 128, 142), reps=3, p
             ff.qr_factor(A, s, Q=Q, R=R, ws=ws, info=info)
         dt, _ = median_time(call, reps, torch)
         sweep[s] = (dt, ff.qr_step(n, n, s), int(info.item()))
+        log(f"[bench] qr n={n} s={s}: {dt * 1e3:.2f} ms")
         del ws
     s_best = min(sweep, key=lambda k: sweep[k][0])
     dt, blk, inf = sweep[s_best]
@@ -716,6 +719,7 @@ def run_qr(ff, torch, wl, dev, n=16384, steps=(64, 96, 112, 128, 142), reps=3, p
         dt, _ = median_time(call, max(reps, 5), torch)
         res[f"n{m}_s{s}"] = {"block": ff.qr_step(m, m, s), "ms": round(dt * 1e3, 3), "info": int(info.item()),
                              "tflops_4n3_3": round(4 * m ** 3 / 3 / dt / 1e12, 3)}
+        log(f"[bench] qr n={m} s={s}: {dt * 1e3:.2f} ms")
         del A, Q, R, ws
     return res
 
